@@ -1,0 +1,235 @@
+"""One MCL update on a NeRF map in float64 (Alg. 1, Eq. 3, Eq. 6).
+
+``update_particles`` runs the per-particle loop of Alg. 1: prediction, the
+downscaled observation, rendering of B query pixels per particle at scale R,
+the uncertainty-weighted photometric score of Eq. 6 and the normalised weights
+of Eq. 3.  ``resample`` is the draw loop of Alg. 1 (systematic, with integer
+thresholds so that any exact implementation returns identical indices).
+
+Readings of points the paper leaves open (each is a named choice, listed with
+the design notes): Eq. 6's garbled exponent is the square; E_j is the squared
+L2 norm over RGB; one query-pixel set per update, shared by all particles and
+drawn with replacement; S_i is floored at 1e-12 before the logarithm; the
+log-likelihood is l_i = 4 (ln B - ln S_i), so w_i is proportional to
+(B / S_i)^4 exactly.
+"""
+import math
+import numpy as np
+
+from . import philox as px
+from . import render as rd
+from . import se3
+
+FINE_FLOOR = 1e-5      # pdf mass added per unit length before fine placement
+SCORE_FLOOR = 1e-12    # floor of S_i
+
+
+# ----------------------------------------------------------------------------
+# random draws (Philox4x32-10 keyed as documented in oracle.philox)
+
+def pixel_indices(seed, it, B, n_pix):
+    """p_j = floor(word0 * n_pix / 2^32), j = 0..B-1 (flat index v * W + u)."""
+    w = px.word_at(seed, it, px.S_PIX, np.arange(B), 0, 0)
+    return [(int(x) * int(n_pix)) >> 32 for x in w]
+
+
+def coarse_t(spec, seed, it, i, j):
+    """Stratified samples t_k = near + (k + xi_k) (far - near) / S_c."""
+    S = spec["n_coarse"]
+    k = np.arange(S)
+    if spec["jitter"]:
+        xi = px.unit24(px.word_at(seed, it, px.S_JIT_COARSE, i, j, k))
+    else:
+        xi = np.zeros(S)
+    return spec["near"] + (k + xi) * ((spec["far"] - spec["near"]) / S)
+
+
+def fine_u(spec, seed, it, i, j):
+    """u_m = (m + xi'_m) / S_f (xi' = 1/2 without jitter)."""
+    S = spec["n_fine"]
+    m = np.arange(S)
+    if spec["jitter"]:
+        xi = px.unit24(px.word_at(seed, it, px.S_JIT_FINE, i, j, m))
+    else:
+        xi = np.full(S, 0.5)
+    return (m + xi) / S
+
+
+def motion_twist(seed, it, i, sigma_t, sigma_r):
+    """Gaussian twist (rho, phi) ~ N(0, diag(sigma_t^2 I, sigma_r^2 I)) by
+    Box-Muller on pairs of (0,1) uniforms: g = sqrt(-2 ln u1) (cos, sin)(2 pi u2)."""
+    w = np.concatenate([px.draw_words(seed, it, px.S_MOTION, i, 0, g) for g in (0, 1)])
+    u = px.unit_open(w)
+    g = []
+    for a in range(3):
+        r = math.sqrt(-2.0 * math.log(u[2 * a]))
+        g.append(r * math.cos(2.0 * math.pi * u[2 * a + 1]))
+        g.append(r * math.sin(2.0 * math.pi * u[2 * a + 1]))
+    rho = sigma_t * np.array(g[0:3])
+    phi = sigma_r * np.array(g[3:6])
+    return rho, phi
+
+
+# ----------------------------------------------------------------------------
+# prediction (Sec. III-A: x_t = x_{t-1} * O_t * Exp(delta))
+
+def predict(pose, motion, sigma_t, sigma_r, seed, it, i):
+    pose = np.asarray(pose, dtype=np.float64).reshape(3, 4)
+    O = np.eye(4)[:3] if motion is None else np.asarray(motion, dtype=np.float64).reshape(3, 4)
+    rho, phi = motion_twist(seed, it, i, sigma_t, sigma_r)
+    return se3.compose(se3.compose(pose, O), se3.exp_se3(rho, phi))
+
+
+# ----------------------------------------------------------------------------
+# rendering of one particle's query rays
+
+def render_rays(spec, P, pose, pix, Wl, cam_l, seed, it, i):
+    """Render the query pixels of particle i: returns per-ray colour C (B, 3),
+    opacity A, z_trans, z_opaque and F."""
+    fx, fy, cx, cy = cam_l
+    B = len(pix)
+    rays = [rd.pixel_ray(pose, p % Wl, p // Wl, fx, fy, cx, cy) for p in pix]
+    tc = [coarse_t(spec, seed, it, i, j) for j in range(B)]
+    # coarse map queries for all rays of the particle in one batch
+    X = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tc)])
+    Dd = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tc)])
+    sig_c, rgb_c = rd.mlp(spec, P, X, Dd)
+    Sc = spec["n_coarse"]
+    far = spec["far"]
+    ts, sigs, rgbs = [], [], []
+    if spec["n_fine"] > 0:
+        tf = []
+        for j in range(B):
+            s = slice(j * Sc, (j + 1) * Sc)
+            w, _, _, _ = rd.composite(tc[j], sig_c[s], rgb_c[s], far)
+            mass = w + FINE_FLOOR * rd.deltas(tc[j], far)
+            tf.append(rd.sample_pdf(tc[j], mass, far, fine_u(spec, seed, it, i, j)))
+        Xf = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tf)])
+        Df = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tf)])
+        sig_f, rgb_f = rd.mlp(spec, P, Xf, Df)
+        Sf = spec["n_fine"]
+        for j in range(B):
+            sc, sf = slice(j * Sc, (j + 1) * Sc), slice(j * Sf, (j + 1) * Sf)
+            t_all = np.concatenate([tc[j], tf[j]])
+            order = np.argsort(t_all, kind="stable")   # ties: coarse first
+            ts.append(t_all[order])
+            sigs.append(np.concatenate([sig_c[sc], sig_f[sf]])[order])
+            rgbs.append(np.concatenate([rgb_c[sc], rgb_f[sf]])[order])
+    else:
+        for j in range(B):
+            s = slice(j * Sc, (j + 1) * Sc)
+            ts.append(tc[j])
+            sigs.append(sig_c[s])
+            rgbs.append(rgb_c[s])
+    C = np.zeros((B, 3))
+    A = np.zeros(B)
+    zt = np.zeros(B)
+    zo = np.zeros(B)
+    F = np.zeros(B)
+    for j in range(B):
+        _, logT, C[j], A[j] = rd.composite(ts[j], sigs[j], rgbs[j], far)
+        zt[j], zo[j] = rd.ray_quantiles(ts[j], sigs[j], logT, far, spec["alpha"])
+        F[j] = rd.uncertainty(zt[j], zo[j], spec["tau"])
+    return {"C": C, "A": A, "z_trans": zt, "z_opaque": zo, "F": F}
+
+
+def score(obs, C, F, B):
+    """Eq. 6: E_j = |I(p_j) - C_j|^2 summed over RGB, S = sum_j E_j F_j,
+    l = 4 (ln B - ln max(S, 1e-12)), i.e. w = (B / S)^4 in log form."""
+    E = ((np.asarray(obs) - C) ** 2).sum(-1)
+    S = float((E * F).sum())
+    return E, S, 4.0 * (math.log(B) - math.log(max(S, SCORE_FLOOR)))
+
+
+def normalise(loglik):
+    """w_i = exp(l_i - m) / sum_k exp(l_k - m), m = max_k l_k (Eq. 3: weights
+    normalised to [0, 1]).  Non-finite l_i get weight 0; if none is finite the
+    set is degenerate and all weights are 0."""
+    ll = np.asarray(loglik, dtype=np.float64)
+    ok = np.isfinite(ll)
+    w = np.zeros_like(ll)
+    if not ok.any():
+        return w
+    m = ll[ok].max()
+    e = np.where(ok, np.exp(np.where(ok, ll - m, 0.0)), 0.0)
+    return e / e.sum()
+
+
+def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
+                     sigma_t=0.0, sigma_r=0.0, seed=0, it=0, subset=None):
+    """One weighting pass of Alg. 1 over the particles ``subset`` (default all).
+
+    spec   : map/renderer settings (see oracle.render); params: flat float32 map
+    image  : H x W x 3 observation; cam = (W, H, fx, fy, cx, cy) at full size
+    inv_R  : level factor s, R_t = 1/s; intrinsics become R K (Sec. III-C)
+    poses  : (N, 3, 4) particle poses x_{t-1}
+    Returns per-particle predicted poses, log-likelihoods, normalised weights
+    (over the subset), mean uncertainty, and per-ray renders."""
+    P = rd.unpack(spec, params)
+    Wf, Hf, fx, fy, cx, cy = cam
+    s = int(inv_R)
+    img_l = rd.downscale(image, s)
+    Hl, Wl = img_l.shape[:2]
+    cam_l = (fx / s, fy / s, cx / s, cy / s)
+    pix = pixel_indices(seed, it, B, Wl * Hl)
+    obs = np.array([img_l[p // Wl, p % Wl] for p in pix])
+    poses = np.asarray(poses, dtype=np.float64).reshape(-1, 3, 4)
+    idx = range(poses.shape[0]) if subset is None else list(subset)
+    out = {"index": list(idx), "pose": [], "loglik": [], "score": [], "uncert": [],
+           "C": [], "A": [], "F": [], "E": [], "z_trans": [], "z_opaque": [],
+           "pix": pix, "obs": obs}
+    for i in idx:
+        x = predict(poses[i], motion, sigma_t, sigma_r, seed, it, i)
+        r = render_rays(spec, P, x, pix, Wl, cam_l, seed, it, i)
+        E, S, ll = score(obs, r["C"], r["F"], B)
+        out["pose"].append(x)
+        out["loglik"].append(ll)
+        out["score"].append(S)
+        out["uncert"].append(float(r["F"].mean()))
+        for key in ("C", "A", "F", "z_trans", "z_opaque"):
+            out[key].append(r[key])
+        out["E"].append(E)
+    for key in ("pose", "loglik", "score", "uncert", "C", "A", "F", "E", "z_trans", "z_opaque"):
+        out[key] = np.array(out[key])
+    out["weight"] = normalise(out["loglik"])
+    return out
+
+
+# ----------------------------------------------------------------------------
+# resampling (Alg. 1, draw loop): systematic, integer thresholds
+
+def resample(weight, n_out, seed, it):
+    """Draw n_out indices with probability proportional to weight.
+
+    q_i = floor(w_i / w_max * 2^40) (w_i <= 0 or non-finite counts as 0),
+    Q = sum q_i, r0 = word 0 of the resampling stream,
+    theta_k = floor((k 2^32 + r0) Q / (n_out 2^32)),
+    idx_k = the smallest i whose inclusive prefix sum of q exceeds theta_k.
+    All sums are exact integers; the only floating-point step is one correctly
+    rounded division per particle.  Returns None when Q = 0 (degenerate)."""
+    wt = [float(w) if (math.isfinite(float(w)) and float(w) > 0.0) else 0.0 for w in weight]
+    wmax = max(wt) if wt else 0.0
+    if wmax <= 0.0:
+        return None
+    q = [int(math.floor(w / wmax * 2.0 ** 40)) for w in wt]
+    Q = sum(q)
+    if Q == 0:
+        return None
+    r0 = int(px.draw_words(seed, it, px.S_RESAMPLE, 0, 0, 0)[0])
+    prefix = []
+    acc = 0
+    for x in q:
+        acc += x
+        prefix.append(acc)
+    out = []
+    for k in range(n_out):
+        theta = ((k << 32) + r0) * Q // (n_out << 32)
+        lo, hi = 0, len(prefix) - 1          # smallest i with prefix[i] > theta
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if prefix[mid] > theta:
+                hi = mid
+            else:
+                lo = mid + 1
+        out.append(lo)
+    return out
