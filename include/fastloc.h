@@ -1,0 +1,203 @@
+/*
+ * fastloc.h -- C ABI of the MI355X (gfx950) particle-update library for
+ * Monte Carlo localization on a NeRF map (Fast Loc-NeRF, arXiv 2406.12202).
+ *
+ * One MCL step (Alg. 1) is two calls:
+ *   loc_update_particles  -- the per-particle loop of Alg. 1: prediction
+ *                            x_t = x_{t-1} O_t Exp(delta) (Sec. III-A), the
+ *                            downscaled observation, rendering of B_t query
+ *                            pixels per particle with intrinsics R_t K (Eq. 1),
+ *                            the uncertainty F = max(z_opaque - z_trans, tau)
+ *                            (Eq. 5 and below Eq. 6) and the particle
+ *                            rejection weight of Eq. 6, normalised (Eq. 3);
+ *   loc_resample          -- the draw loop of Alg. 1: N_t indices drawn with
+ *                            probability proportional to the weights.
+ *
+ * Conventions for every entry point:
+ *  - C linkage; no exception crosses the ABI; every call returns a loc_status.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    rejected call enqueues nothing and returns LOC_E_ARG (detail text in
+ *    loc_last_error).
+ *  - Array arguments marked DEVICE are device pointers owned by the caller
+ *    (for example torch tensor storage) and must stay valid until the work
+ *    enqueued on the context's stream has completed.  HOST arguments are read
+ *    before the call returns.
+ *  - Work is enqueued on the HIP stream given to loc_init_map and the call
+ *    returns before it completes.  Failures of enqueued work surface as
+ *    LOC_E_HIP from a later call.  Conditions only known on the device
+ *    (degenerate weights) are reported by loc_sync through its flags.
+ *  - A context may be used by one host thread at a time.  It owns the packed
+ *    map weights and a workspace that grows on demand; calls on one context
+ *    are serialised by its stream.
+ *
+ * Random draws (query pixels, stratified jitter, fine jitter, motion noise,
+ * resampling offset) come from Philox4x32-10 (Salmon et al., SC'11) with
+ *   key     = (seed & 0xffffffff, seed >> 32)
+ *   counter = (c0, c1, iter & 0xffffffff, (stream << 24) | group)
+ * and streams
+ *   1 query pixel j             c0 = j, c1 = 0; p_j = (word0 * W'H') >> 32,
+ *                               flat index v * W' + u at the level resolution
+ *   2 coarse jitter of sample k of ray (i, j)   c0 = i, c1 = j, group k / 4,
+ *                               word k % 4; xi = (word >> 8) * 2^-24
+ *   3 fine jitter of sample m of ray (i, j)     as 2 with m
+ *   4 motion noise of particle i  c0 = i, c1 = 0, groups 0 and 1 (Box-Muller
+ *                               on u = (word + 1/2) 2^-32, pairs (w0,w1),
+ *                               (w2,w3), (w4,w5) -> rho = sigma_t (g0,g1,g2),
+ *                               phi = sigma_r (g3,g4,g5))
+ *   5 resampling offset         c0 = c1 = 0, group 0, word 0 = r0
+ * so results are reproducible from (seed, iter) on any device.
+ */
+#ifndef FASTLOC_H
+#define FASTLOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct loc_ctx loc_ctx;
+
+typedef enum {
+  LOC_OK = 0,
+  LOC_E_ARG = -1,          /* invalid argument (nothing enqueued)              */
+  LOC_E_HIP = -2,          /* a HIP runtime call or enqueued kernel failed     */
+  LOC_E_OOM = -3,          /* device allocation failed                         */
+  LOC_E_DEGENERATE = -4,   /* all weights zero / no finite log-likelihood      */
+  LOC_E_UNSUPPORTED = -5,  /* map shape or precision not compiled in           */
+  LOC_E_STATE = -6         /* call order violated (e.g. no update before read) */
+} loc_status;
+
+typedef enum { LOC_FP32 = 0, LOC_BF16 = 1, LOC_FP8_E4M3 = 2 } loc_precision;
+
+/*
+ * The NeRF map M (Sec. III-A: F_NeRF(x, d) -> (c, sigma)) and renderer settings.
+ *
+ * Map: positional encoding gamma(p) = (p, sin(2^0 pi p), cos(2^0 pi p), ...,
+ * sin(2^{L-1} pi p), cos(2^{L-1} pi p)) of widths in_x = 3 + 6 L_xyz and
+ * in_d = 3 + 6 L_dir, then n_layers ReLU layers of `width` units.
+ * `params` is a HOST float32 array of n_params values in this order
+ * (each W row-major out x in, then its bias):
+ *   for l in 0..n_layers-1: W_l, b_l with in_0 = in_x,
+ *        in_l = width + in_x if l == skip_layer (input [h_{l-1}, gamma(x)]),
+ *        in_l = width otherwise (skip_layer < 1 disables the skip input);
+ *   sigma head (1 x width), sigma = softplus(w h + b);
+ *   if dir_width > 0: feature (width x width, linear), dir
+ *        (dir_width x (width + in_d), ReLU, input [feature, gamma(d)]),
+ *        rgb (3 x dir_width, sigmoid);
+ *   else rgb (3 x (width + in_d), sigmoid, input [h_{n_layers-1}, gamma(d)]).
+ * The array is copied and repacked during loc_init_map.
+ * Compiled map shapes: (n_layers, width, skip_layer, L_xyz, L_dir, dir_width)
+ * = (4, 64, -1, 6, 2, 0) and (8, 256, 5, 10, 4, 128); others return
+ * LOC_E_UNSUPPORTED.
+ *
+ * Rendering (Eq. 1 as a Riemann sum): stratified samples
+ * t_k = near + (k + xi_k)(far - near)/n_coarse (xi = 0 when jitter == 0),
+ * interval lengths delta_k = t_{k+1} - t_k, delta_last = far - t_last,
+ * density and colour constant on each interval, black background.
+ * n_fine > 0 adds hierarchical samples: inverse-CDF placement on the coarse
+ * pdf with mass w_k + 1e-5 delta_k at u_m = (m + xi'_m)/n_fine (xi' = 1/2
+ * when jitter == 0), merged with the coarse samples (stable order).
+ * alpha: Eq. 5 threshold (the paper gives none; 0.05 by default);
+ * tau: lower bound of F (0.1 in the paper's experiments).
+ */
+typedef struct {
+  int n_layers, width, skip_layer;
+  int L_xyz, L_dir, dir_width;
+  const float* params;     /* HOST */
+  size_t n_params;
+  loc_precision precision; /* LOC_FP32 now; others return LOC_E_UNSUPPORTED */
+  float near_, far_;
+  int n_coarse, n_fine;    /* n_coarse in [1, 256], n_fine in [0, 256] */
+  float alpha, tau;        /* 0 < alpha < 0.5, tau > 0 */
+  int jitter;              /* 1 stratified jitter, 0 deterministic */
+} loc_map_desc;
+
+/* Full-resolution pinhole intrinsics K (OpenGL camera: x right, y up, looking
+ * along -z; pixel (u, v) has centre (u + 1/2, v + 1/2)).  At level factor
+ * s = 1/R the intrinsics are R K = (fx/s, fy/s, cx/s, cy/s). */
+typedef struct { int W, H; double fx, fy, cx, cy; } loc_camera;
+
+/* Create a context for map `map` bound to `hip_stream` (a hipStream_t, or
+ * NULL for the null stream) on the current HIP device.  *out receives the
+ * context; on failure *out is NULL. */
+loc_status loc_init_map(const loc_map_desc* map, void* hip_stream, loc_ctx** out);
+
+/*
+ * One MCL weighting pass over N particles (Alg. 1, per-particle loop;
+ * Sec. III-B/C).
+ *   image_rgb  DEVICE H x W x 3 float32 (row-major, RGB) full-resolution I_t
+ *   cam        HOST   full-resolution intrinsics; W and H divisible by inv_R
+ *   inv_R      level factor s in {1, 2, 4, 8}: R_t = 1/s; the observation is
+ *              box-averaged over s x s blocks (downscale(I_t, R_t))
+ *   B, N       query pixels per particle B_t (1..1024) and particles (>= 1)
+ *   pose_in    DEVICE N x 12 float64 camera-to-world [R | t], row-major
+ *   motion     HOST   12 float64 O_t, or NULL for the identity
+ *   sigma_t, sigma_r  prediction noise (scene units, radians), >= 0
+ *   seed, iter  Philox key / counter word (see the header comment)
+ *   pose_out   DEVICE N x 12 float64: predicted x_t (may equal pose_in)
+ *   loglik_out DEVICE N float64: l_i = 4 (ln B - ln max(S_i, 1e-12)) with
+ *              S_i = sum_j E_ij F_ij and E_ij = |I^R(p_j) - C_ij|^2 summed
+ *              over RGB (Eq. 6 in log form: w_i proportional to e^{l_i})
+ *   weight_out DEVICE N float64: w_i = e^{l_i - max l} / sum_k e^{l_k - max l}
+ *              (non-finite l_i -> 0; if none is finite all are 0 and loc_sync
+ *              reports LOC_FLAG_DEGENERATE_WEIGHTS)
+ *   uncert_out DEVICE N float32: mean_j F_ij, or NULL
+ */
+loc_status loc_update_particles(loc_ctx* ctx, const float* image_rgb, const loc_camera* cam,
+                                int inv_R, int B, int N, const double* pose_in,
+                                const double* motion, double sigma_t, double sigma_r,
+                                uint64_t seed, uint64_t iter, double* pose_out,
+                                double* loglik_out, double* weight_out, float* uncert_out);
+
+/*
+ * Alg. 1 draw loop: systematic resampling with integer thresholds.
+ *   weight   DEVICE n_in float64 (w <= 0 or non-finite counts as 0)
+ *   idx_out  DEVICE n_out int32, non-decreasing
+ * q_i = floor(w_i / w_max * 2^40), Q = sum q_i (exact), r0 = word 0 of stream
+ * 5, theta_k = floor((k 2^32 + r0) Q / (n_out 2^32)), idx_k = min{i : q_0 +
+ * ... + q_i > theta_k}.  Every step is exact or a correctly rounded division,
+ * so the indices are bit-identical to any exact implementation.  If Q = 0 all
+ * indices are -1 and loc_sync reports LOC_FLAG_DEGENERATE_RESAMPLE.
+ * 1 <= n_in, n_out <= 2^24.
+ */
+loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
+                        uint64_t seed, uint64_t iter, int32_t* idx_out);
+
+/* Per-ray results of the last loc_update_particles on this context, copied
+ * into DEVICE arrays of N*B entries (ray (i, j) at i*B + j); any pointer may be
+ * NULL.  rgb: 3 floats per ray (C), opacity: A = 1 - T(far), F: uncertainty,
+ * E: squared colour error.  Enqueued on the stream. */
+loc_status loc_ray_outputs(loc_ctx* ctx, float* rgb, float* opacity, float* F, float* E);
+
+enum { LOC_FLAG_DEGENERATE_WEIGHTS = 1, LOC_FLAG_DEGENERATE_RESAMPLE = 2 };
+
+/* Wait for the context's stream; *flags (may be NULL) receives the OR of
+ * LOC_FLAG_* raised since the previous loc_sync.  Returns LOC_E_HIP if
+ * enqueued work failed. */
+loc_status loc_sync(loc_ctx* ctx, int* flags);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch while enabled.  loc_kernel_stats waits for the stream and
+ * fills up to max entries (name, launches, summed milliseconds, summed
+ * algorithmic FLOP and HBM bytes of those launches); *n receives the number
+ * of kernels.  Enabling clears the counters. */
+typedef struct {
+  char name[48];
+  long long launches;
+  double ms;
+  double flop;
+  double bytes;
+} loc_kernel_stat;
+loc_status loc_set_profiling(loc_ctx* ctx, int enable);
+loc_status loc_kernel_stats(loc_ctx* ctx, loc_kernel_stat* out, int max, int* n);
+
+void loc_destroy(loc_ctx* ctx);
+const char* loc_status_str(loc_status s);     /* static text, never NULL */
+const char* loc_last_error(const loc_ctx* ctx);/* detail of the last failure; "" if none */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTLOC_H */

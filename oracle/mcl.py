@@ -138,6 +138,8 @@ def score(obs, C, F, B):
     l = 4 (ln B - ln max(S, 1e-12)), i.e. w = (B / S)^4 in log form."""
     E = ((np.asarray(obs) - C) ** 2).sum(-1)
     S = float((E * F).sum())
+    if math.isnan(S):
+        return E, S, math.nan
     return E, S, 4.0 * (math.log(B) - math.log(max(S, SCORE_FLOOR)))
 
 

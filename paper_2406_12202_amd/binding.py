@@ -1,0 +1,207 @@
+"""Python binding of the C ABI in include/fastloc.h (ctypes; argument
+marshalling only).
+
+Every step of the particle update runs in the HIP library; PyTorch supplies
+device memory and the stream.  ``load()`` raises if the built library is
+missing: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfastloc.so")
+
+LOC_OK, LOC_E_ARG, LOC_E_HIP, LOC_E_OOM, LOC_E_DEGENERATE, LOC_E_UNSUPPORTED, LOC_E_STATE = 0, -1, -2, -3, -4, -5, -6
+LOC_FP32, LOC_BF16, LOC_FP8_E4M3 = 0, 1, 2
+FLAG_DEGENERATE_WEIGHTS, FLAG_DEGENERATE_RESAMPLE = 1, 2
+PRECISIONS = {"fp32": LOC_FP32, "bf16": LOC_BF16, "fp8": LOC_FP8_E4M3}
+
+EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
+           "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error"]
+
+
+class MapDesc(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int), ("width", ctypes.c_int), ("skip_layer", ctypes.c_int),
+                ("L_xyz", ctypes.c_int), ("L_dir", ctypes.c_int), ("dir_width", ctypes.c_int),
+                ("params", ctypes.POINTER(ctypes.c_float)), ("n_params", ctypes.c_size_t),
+                ("precision", ctypes.c_int), ("near_", ctypes.c_float), ("far_", ctypes.c_float),
+                ("n_coarse", ctypes.c_int), ("n_fine", ctypes.c_int), ("alpha", ctypes.c_float),
+                ("tau", ctypes.c_float), ("jitter", ctypes.c_int)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int), ("H", ctypes.c_int), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("flop", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class LocError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+_LIB = None
+
+
+def load(path=LIB_PATH):
+    """Load libfastloc.so (built by paper_2406_12202_amd.build); raises if absent."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, c_int, c_u64, c_dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
+    lib.loc_init_map.argtypes = [ctypes.POINTER(MapDesc), vp, ctypes.POINTER(vp)]
+    lib.loc_update_particles.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, c_int, c_int, vp, vp,
+                                         c_dbl, c_dbl, c_u64, c_u64, vp, vp, vp, vp]
+    lib.loc_resample.argtypes = [vp, vp, c_int, c_int, c_u64, c_u64, vp]
+    lib.loc_ray_outputs.argtypes = [vp, vp, vp, vp, vp]
+    lib.loc_sync.argtypes = [vp, ctypes.POINTER(c_int)]
+    lib.loc_set_profiling.argtypes = [vp, c_int]
+    lib.loc_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat), c_int, ctypes.POINTER(c_int)]
+    lib.loc_destroy.argtypes = [vp]
+    lib.loc_destroy.restype = None
+    lib.loc_status_str.argtypes = [c_int]
+    lib.loc_status_str.restype = ctypes.c_char_p
+    lib.loc_last_error.argtypes = [vp]
+    lib.loc_last_error.restype = ctypes.c_char_p
+    for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
+              "loc_set_profiling", "loc_kernel_stats"):
+        getattr(lib, f).restype = c_int
+    _LIB = lib
+    return lib
+
+
+def _ptr(t, dtype, numel, name):
+    """Device pointer of a contiguous CUDA tensor of the expected dtype and size."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError("%s must be a contiguous %s tensor of %d elements" % (name, dtype, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def map_desc(spec, params, precision="fp32"):
+    """loc_map_desc from a spec dict (see synth.spec) and float32 params."""
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    d = MapDesc(n_layers=spec["n_layers"], width=spec["width"], skip_layer=spec["skip_layer"],
+                L_xyz=spec["L_xyz"], L_dir=spec["L_dir"], dir_width=spec["dir_width"],
+                params=p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_params=p.size,
+                precision=PRECISIONS[precision] if isinstance(precision, str) else precision,
+                near_=spec["near"], far_=spec["far"], n_coarse=spec["n_coarse"], n_fine=spec["n_fine"],
+                alpha=spec["alpha"], tau=spec["tau"], jitter=spec["jitter"])
+    return d, p
+
+
+class Context:
+    """A loc_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, spec, params, precision="fp32", stream=None):
+        import torch
+        self.lib = load()
+        self.spec = dict(spec)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        d, self._p = map_desc(spec, params, precision)
+        h = ctypes.c_void_p()
+        st = self.lib.loc_init_map(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != LOC_OK:
+            raise LocError(st, "loc_init_map: %s" % self.lib.loc_status_str(st).decode())
+        self.h = h
+
+    def _check(self, st, what):
+        if st != LOC_OK:
+            raise LocError(st, "%s: %s (%s)" % (what, self.lib.loc_status_str(st).decode(),
+                                                self.lib.loc_last_error(self.h).decode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.loc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def loc_update_particles(self, image, cam, inv_R, B, pose_in, motion=None, sigma_t=0.0, sigma_r=0.0,
+                             seed=0, iter=0, pose_out=None, loglik_out=None, weight_out=None,
+                             uncert_out=None):
+        """One weighting pass; returns (pose_out, loglik, weight, uncert) device tensors."""
+        import torch
+        N = pose_in.shape[0]
+        dev = pose_in.device
+        if pose_out is None:
+            pose_out = torch.empty((N, 3, 4), dtype=torch.float64, device=dev)
+        if loglik_out is None:
+            loglik_out = torch.empty(N, dtype=torch.float64, device=dev)
+        if weight_out is None:
+            weight_out = torch.empty(N, dtype=torch.float64, device=dev)
+        if uncert_out is None:
+            uncert_out = torch.empty(N, dtype=torch.float32, device=dev)
+        W, H, fx, fy, cx, cy = cam
+        c = Camera(W=int(W), H=int(H), fx=fx, fy=fy, cx=cx, cy=cy)
+        mo = None
+        if motion is not None:
+            import numpy as np
+            self._mo = np.ascontiguousarray(np.asarray(motion, dtype=np.float64).reshape(12))
+            mo = ctypes.c_void_p(self._mo.ctypes.data)
+        st = self.lib.loc_update_particles(
+            self.h, _ptr(image, torch.float32, int(H) * int(W) * 3, "image"), ctypes.byref(c), int(inv_R),
+            int(B), int(N), _ptr(pose_in, torch.float64, N * 12, "pose_in"), mo, float(sigma_t),
+            float(sigma_r), int(seed), int(iter), _ptr(pose_out, torch.float64, N * 12, "pose_out"),
+            _ptr(loglik_out, torch.float64, N, "loglik_out"), _ptr(weight_out, torch.float64, N, "weight_out"),
+            _ptr(uncert_out, torch.float32, N, "uncert_out"))
+        self._check(st, "loc_update_particles")
+        self.last = (N, B)
+        return pose_out, loglik_out, weight_out, uncert_out
+
+    def loc_resample(self, weight, n_out, seed=0, iter=0, idx_out=None):
+        import torch
+        n_in = weight.numel()
+        if idx_out is None:
+            idx_out = torch.empty(n_out, dtype=torch.int32, device=weight.device)
+        st = self.lib.loc_resample(self.h, _ptr(weight, torch.float64, n_in, "weight"), int(n_in), int(n_out),
+                                   int(seed), int(iter), _ptr(idx_out, torch.int32, n_out, "idx_out"))
+        self._check(st, "loc_resample")
+        return idx_out
+
+    def loc_ray_outputs(self):
+        """Per-ray (rgb (N,B,3), opacity (N,B), F (N,B), E (N,B)) of the last update."""
+        import torch
+        N, B = self.last
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rgb = torch.empty((N, B, 3), dtype=torch.float32, device=dev)
+        op = torch.empty((N, B), dtype=torch.float32, device=dev)
+        F = torch.empty((N, B), dtype=torch.float32, device=dev)
+        E = torch.empty((N, B), dtype=torch.float32, device=dev)
+        st = self.lib.loc_ray_outputs(self.h, _ptr(rgb, torch.float32, N * B * 3, "rgb"),
+                                      _ptr(op, torch.float32, N * B, "opacity"),
+                                      _ptr(F, torch.float32, N * B, "F"), _ptr(E, torch.float32, N * B, "E"))
+        self._check(st, "loc_ray_outputs")
+        return rgb, op, F, E
+
+    def loc_sync(self):
+        f = ctypes.c_int(0)
+        self._check(self.lib.loc_sync(self.h, ctypes.byref(f)), "loc_sync")
+        return f.value
+
+    def loc_set_profiling(self, enable):
+        self._check(self.lib.loc_set_profiling(self.h, int(bool(enable))), "loc_set_profiling")
+
+    def loc_kernel_stats(self):
+        arr = (KernelStat * 32)()
+        n = ctypes.c_int(0)
+        self._check(self.lib.loc_kernel_stats(self.h, arr, 32, ctypes.byref(n)), "loc_kernel_stats")
+        return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms, flop=arr[k].flop,
+                                           bytes=arr[k].bytes) for k in range(min(n.value, 32))}

@@ -1,0 +1,209 @@
+// Particle-filter kernels in float64: prediction (SE(3) motion with Gaussian
+// noise), weight normalisation and integer-exact systematic resampling.
+#include "common.h"
+#include "kernels.h"
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// x_t = x_{t-1} O_t Exp(delta), delta = (rho, phi) ~ N(0, diag(sigma_t^2 I,
+// sigma_r^2 I)) (Sec. III-A, prediction step); Exp by Rodrigues' formula and
+// the left Jacobian, Taylor coefficients for |phi| < 1e-4.
+__global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  double x[12];
+  for (int q = 0; q < 12; ++q) x[q] = a.pose_in[(long)i * 12 + q];
+  const u32x4 w0 = draw(a.seed, a.iter, kStreamMotion, (uint32_t)i, 0, 0);
+  const u32x4 w1 = draw(a.seed, a.iter, kStreamMotion, (uint32_t)i, 0, 1);
+  const uint32_t ws[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
+  double g[6];
+  for (int p = 0; p < 3; ++p) {
+    const double u1 = unit_open(ws[2 * p]), u2 = unit_open(ws[2 * p + 1]);
+    const double r = sqrt(-2.0 * log(u1));
+    g[2 * p] = r * cos(2.0 * M_PI * u2);
+    g[2 * p + 1] = r * sin(2.0 * M_PI * u2);
+  }
+  const double rho[3] = {a.sigma_t * g[0], a.sigma_t * g[1], a.sigma_t * g[2]};
+  const double ph[3] = {a.sigma_r * g[3], a.sigma_r * g[4], a.sigma_r * g[5]};
+  const double th2 = ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2];
+  const double th = sqrt(th2);
+  double A, Bc, C;
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    Bc = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    A = sin(th) / th;
+    Bc = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[3][3] = {{0.0, -ph[2], ph[1]}, {ph[2], 0.0, -ph[0]}, {-ph[1], ph[0], 0.0}};
+  double K2[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) K2[r][c] = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
+  double E[12];
+  for (int r = 0; r < 3; ++r) {
+    double tv = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double id = (r == c) ? 1.0 : 0.0;
+      E[4 * r + c] = id + A * K[r][c] + Bc * K2[r][c];
+      tv += (id + Bc * K[r][c] + C * K2[r][c]) * rho[c];
+    }
+    E[4 * r + 3] = tv;
+  }
+  // y = x * O, then y * E
+  const double* O = a.motion.m;
+  double y[12], z[12];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c)
+      y[4 * r + c] = x[4 * r + 0] * O[c] + x[4 * r + 1] * O[4 + c] + x[4 * r + 2] * O[8 + c];
+    y[4 * r + 3] = x[4 * r + 0] * O[3] + x[4 * r + 1] * O[7] + x[4 * r + 2] * O[11] + x[4 * r + 3];
+  }
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c)
+      z[4 * r + c] = y[4 * r + 0] * E[c] + y[4 * r + 1] * E[4 + c] + y[4 * r + 2] * E[8 + c];
+    z[4 * r + 3] = y[4 * r + 0] * E[3] + y[4 * r + 1] * E[7] + y[4 * r + 2] * E[11] + y[4 * r + 3];
+  }
+  for (int q = 0; q < 12; ++q) a.pose_out[(long)i * 12 + q] = z[q];
+}
+
+hipError_t launch_predict(const PredictArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_predict, dim3((a.N + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// w_i = exp(l_i - m) / sum_k exp(l_k - m), m = max over finite l (Eq. 3).
+// One workgroup; fixed strided assignment and a fixed tree, so the sums are
+// deterministic.
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kRedThreads) void k_normalize(const double* ll, double* w, int N, int* flags) {
+  __shared__ double s[kRedThreads];
+  const int tid = threadIdx.x;
+  double m = -INFINITY;
+  for (int i = tid; i < N; i += kRedThreads) {
+    const double v = ll[i];
+    if (isfinite(v)) m = fmax(m, v);
+  }
+  s[tid] = m;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
+    __syncthreads();
+  }
+  m = s[0];
+  __syncthreads();
+  const bool none = !(m > -INFINITY);
+  double acc = 0.0;
+  for (int i = tid; i < N; i += kRedThreads) {
+    const double v = ll[i];
+    if (!none && isfinite(v)) acc += exp(v - m);
+  }
+  s[tid] = acc;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) s[tid] += s[tid + o];
+    __syncthreads();
+  }
+  const double tot = s[0];
+  for (int i = tid; i < N; i += kRedThreads) {
+    const double v = ll[i];
+    w[i] = (!none && isfinite(v)) ? exp(v - m) / tot : 0.0;
+  }
+  if (none && tid == 0) atomicOr(flags, 1);
+}
+
+hipError_t launch_normalize(const double* loglik, double* weight, int N, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize, dim3(1), dim3(kRedThreads), 0, st, loglik, weight, N, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// systematic resampling with integer thresholds (Alg. 1, draw loop):
+// q_i = floor(w_i / w_max 2^40), inclusive prefix P (exact uint64),
+// theta_k = floor((k 2^32 + r0) Q / (n_out 2^32)), idx_k = min{i : P_i > theta_k}.
+typedef unsigned long long u64;
+
+__device__ inline double clean_weight(double w) { return (isfinite(w) && w > 0.0) ? w : 0.0; }
+
+// floor(a * Q / (n 2^32)) for a < 2^63, Q < 2^64, n < 2^31, as 32-bit limbs
+__device__ inline u64 threshold(u64 a, u64 Q, u64 n) {
+  const u64 lo = a * Q;
+  const u64 hi = __umul64hi(a, Q);
+  // x = (hi:lo) >> 32, a 96-bit number with limbs x2 x1 x0
+  const u64 x2 = hi >> 32, x1 = hi & 0xffffffffull, x0 = lo >> 32;
+  u64 r = 0, q = 0;
+  const u64 limbs[3] = {x2, x1, x0};
+  for (int i = 0; i < 3; ++i) {
+    const u64 cur = (r << 32) | limbs[i];
+    q = (q << 32) | (cur / n);
+    r = cur % n;
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_resample(const double* weight, int n_in, int n_out,
+                                                          uint64_t seed, uint64_t iter, u64* prefix,
+                                                          int32_t* idx, int* flags) {
+  __shared__ double s_max[kRedThreads];
+  __shared__ u64 s_sum[kRedThreads];
+  const int tid = threadIdx.x;
+  double m = 0.0;
+  for (int i = tid; i < n_in; i += kRedThreads) m = fmax(m, clean_weight(weight[i]));
+  s_max[tid] = m;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) s_max[tid] = fmax(s_max[tid], s_max[tid + o]);
+    __syncthreads();
+  }
+  const double wmax = s_max[0];
+  // contiguous chunk per thread: local sums, block exclusive scan, local prefixes
+  const int chunk = (n_in + kRedThreads - 1) / kRedThreads;
+  const int b0 = min(tid * chunk, n_in), b1 = min(b0 + chunk, n_in);
+  u64 local = 0;
+  if (wmax > 0.0)
+    for (int i = b0; i < b1; ++i) local += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
+  s_sum[tid] = local;
+  __syncthreads();
+  for (int o = 1; o < kRedThreads; o <<= 1) {     // Hillis-Steele inclusive scan
+    const u64 v = (tid >= o) ? s_sum[tid - o] : 0;
+    __syncthreads();
+    s_sum[tid] += v;
+    __syncthreads();
+  }
+  const u64 Q = s_sum[kRedThreads - 1];
+  u64 run = s_sum[tid] - local;
+  if (wmax > 0.0)
+    for (int i = b0; i < b1; ++i) {
+      run += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
+      prefix[i] = run;
+    }
+  __syncthreads();
+  __threadfence_block();
+  if (Q == 0) {
+    for (int k = tid; k < n_out; k += kRedThreads) idx[k] = -1;
+    if (tid == 0) atomicOr(flags, 2);
+    return;
+  }
+  const u64 r0 = draw(seed, iter, kStreamResample, 0, 0, 0).x;
+  for (int k = tid; k < n_out; k += kRedThreads) {
+    const u64 th = threshold(((u64)k << 32) + r0, Q, (u64)n_out);
+    int lo = 0, hi = n_in - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (prefix[mid] > th) hi = mid; else lo = mid + 1;
+    }
+    idx[k] = lo;
+  }
+}
+
+hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
+                           u64* prefix, int32_t* idx, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_resample, dim3(1), dim3(kRedThreads), 0, st, weight, n_in, n_out, seed, iter,
+                     prefix, idx, flags);
+  return hipGetLastError();
+}
+
+}  // namespace fl

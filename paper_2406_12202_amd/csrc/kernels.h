@@ -1,0 +1,87 @@
+// Kernel argument blocks and launchers of the particle-update library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fl {
+
+enum MapKind { kMapSmall = 0, kMapNerf = 1 };
+
+// map evaluation over n_samples = n_rays * spr samples laid out [ray][k]
+struct MlpArgs {
+  const float4* ray_o;   // per ray origin (xyz, pad)
+  const float4* ray_d;   // per ray unit direction (xyz, pad)
+  const float* t_in;     // per sample depth, or NULL: stratified coarse samples
+  float* t_out;          // coarse depths written when t_in == NULL
+  float4* out;           // per sample (sigma, r, g, b)
+  const float* weights;  // packed map (maplayout.h)
+  long n_samples;
+  int spr;               // samples per ray in this pass
+  int B;                 // rays per particle (ray = i * B + j)
+  float near_, dt;       // coarse grid: t_k = near + (k + xi) dt
+  int jitter;
+  uint64_t seed, iter;
+};
+hipError_t launch_mlp(int map_kind, const MlpArgs& a, hipStream_t st);
+
+struct Pose12 { double m[12]; };
+
+struct PredictArgs {
+  const double* pose_in;
+  double* pose_out;
+  Pose12 motion;         // O_t
+  double sigma_t, sigma_r;
+  int N;
+  uint64_t seed, iter;
+};
+hipError_t launch_predict(const PredictArgs& a, hipStream_t st);
+
+struct RaygenArgs {
+  const double* pose;    // N x 12 predicted poses
+  const float* image;    // full-resolution H x W x 3
+  int W_full, s;         // full width, level factor
+  int Wl, Hl;            // level resolution
+  double fx, fy, cx, cy; // level intrinsics R K
+  int N, B;
+  uint64_t seed, iter;
+  float4* ray_o;
+  float4* ray_d;
+  float4* obs;           // I^R(p_j) per ray (rgb, pad)
+};
+hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st);
+
+struct FineArgs {
+  const float* t_coarse;   // [ray][Sc]
+  const float4* out_coarse;
+  float* t_fine;           // [ray][Sf]
+  int n_rays, Sc, Sf, B;
+  float far_;
+  int jitter;
+  uint64_t seed, iter;
+};
+hipError_t launch_fine(const FineArgs& a, hipStream_t st);
+
+struct CompositeArgs {
+  const float* t_coarse;
+  const float4* out_coarse;
+  const float* t_fine;     // NULL when Sf == 0
+  const float4* out_fine;
+  const float4* obs;
+  int N, B, Sc, Sf;
+  float far_, log_trans, log_opq, tau;   // log(1 - alpha), log(alpha)
+  float4* ray_rgba;        // per ray (C, A)
+  float2* ray_fe;          // per ray (F, E)
+  double* loglik;          // per particle
+  float* uncert;           // per particle mean F, may be NULL
+};
+hipError_t launch_composite(const CompositeArgs& a, hipStream_t st);
+
+hipError_t launch_normalize(const double* loglik, double* weight, int N, int* flags, hipStream_t st);
+
+hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
+                           unsigned long long* prefix, int32_t* idx, int* flags, hipStream_t st);
+
+hipError_t launch_split_ray_outputs(const float4* rgba, const float2* fe, int n, float* rgb,
+                                    float* opacity, float* F, float* E, hipStream_t st);
+
+}  // namespace fl

@@ -1,0 +1,523 @@
+// Host runtime of the particle-update library: the C ABI of fastloc.h,
+// argument validation, weight packing for the MFMA kernels, workspace
+// management, launch sequencing and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fastloc.h"
+#include "kernels.h"
+#include "maplayout.h"
+
+using namespace fl;
+
+namespace {
+
+enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
+                K_RESAMPLE, K_SPLIT, K_COUNT };
+const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "mlp_fine",
+                                     "composite_score", "normalize", "resample", "ray_outputs"};
+
+struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct loc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  loc_map_desc desc{};
+  int kind = kMapSmall;
+  long macs = 0;
+  float* weights = nullptr;
+  // workspace
+  DevBuf<float4> ray_o, ray_d, obs, out_c, out_f, rgba;
+  DevBuf<float2> fe;
+  DevBuf<float> t_c, t_f;
+  DevBuf<unsigned long long> prefix;
+  int* flags = nullptr;
+  int last_N = 0, last_B = 0;
+  // profiling
+  bool prof = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  long long launches[K_COUNT] = {};
+  double ms[K_COUNT] = {}, flop[K_COUNT] = {}, bytes[K_COUNT] = {};
+  std::string err;
+};
+
+namespace {
+
+loc_status fail(loc_ctx* c, loc_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(c, expr)                                                                      \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail((c), LOC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+loc_status ensure(loc_ctx* c, DevBuf<T>& b, size_t n) {
+  if (b.n >= n) return LOC_OK;
+  if (b.p) {
+    hipStreamSynchronize(c->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+  }
+  if (hipMalloc(&b.p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, LOC_E_OOM, "workspace allocation of %zu bytes failed", sizeof(T) * n);
+  }
+  b.n = n;
+  return LOC_OK;
+}
+
+hipEvent_t get_event(loc_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// launch `fn` with optional event timing
+template <class F>
+loc_status timed(loc_ctx* c, int kid, double flop, double bytes, F fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->prof) {
+    a = get_event(c);
+    b = get_event(c);
+    if (a) hipEventRecord(a, c->stream);
+  }
+  hipError_t e = fn();
+  if (e != hipSuccess) return fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
+  if (c->prof && a && b) {
+    hipEventRecord(b, c->stream);
+    c->pending.push_back({kid, a, b, flop, bytes});
+  }
+  return LOC_OK;
+}
+
+// ------------------------------------------------------------- weight packing
+struct Canon {            // canonical (unpacked) layers, row-major W (out x in) and b
+  std::vector<const float*> W, b;
+  std::vector<int> nout, nin;
+};
+
+bool canon_split(const loc_map_desc& d, Canon& cn) {
+  const int in_x = 3 + 6 * d.L_xyz, in_d = 3 + 6 * d.L_dir, Wd = d.width;
+  std::vector<std::pair<int, int>> sh;
+  for (int l = 0; l < d.n_layers; ++l)
+    sh.push_back({Wd, l == 0 ? in_x : (l == d.skip_layer ? Wd + in_x : Wd)});
+  sh.push_back({1, Wd});
+  if (d.dir_width > 0) {
+    sh.push_back({Wd, Wd});
+    sh.push_back({d.dir_width, Wd + in_d});
+    sh.push_back({3, d.dir_width});
+  } else {
+    sh.push_back({3, Wd + in_d});
+  }
+  size_t pos = 0;
+  for (auto& s : sh) {
+    cn.W.push_back(d.params + pos);
+    pos += (size_t)s.first * s.second;
+    cn.b.push_back(d.params + pos);
+    pos += s.first;
+    cn.nout.push_back(s.first);
+    cn.nin.push_back(s.second);
+  }
+  return pos == d.n_params;
+}
+
+// one dense block: A fragments then permuted biases (maplayout.h)
+// in_feature(kb, h) -> canonical input column or -1
+template <class FeatFn>
+void pack_dense(float* dst, int mto, int kb_total, const float* W, int nin, const float* b, FeatFn in_feature) {
+  for (int mt = 0; mt < mto; ++mt)
+    for (int kb = 0; kb < kb_total; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int row = 16 * mt + lane % 16;
+        const int col = in_feature(kb, lane / 16);
+        const long idx = (((long)mt * (kb_total / 4) + kb / 4) * 64 + lane) * 4 + kb % 4;
+        dst[idx] = col >= 0 ? W[(long)row * nin + col] : 0.0f;
+      }
+  float* bias = dst + (long)mto * kb_total * 64;
+  for (int mt = 0; mt < mto; ++mt)
+    for (int g = 0; g < 4; ++g)
+      for (int r = 0; r < 4; ++r) bias[(mt * 4 + g) * 4 + r] = b[16 * mt + 4 * g + r];
+}
+
+template <class S>
+std::vector<float> pack_map(const loc_map_desc& d) {
+  Canon cn;
+  canon_split(d, cn);
+  std::vector<float> P(S::TOTAL, 0.0f);
+  auto chain = [](int kb, int h) { return chain_feature(kb, h); };
+  auto gx = [](int kb, int h) { return posenc_feature(S::LX, kb, h); };
+  for (int l = 0; l < S::D; ++l) {
+    float* dst = P.data() + S::layer_off(l);
+    if (l == 0) {
+      pack_dense(dst, S::MT, S::KBX, cn.W[0], cn.nin[0], cn.b[0], gx);
+    } else if (l == S::SKIP) {
+      pack_dense(dst, S::MT, S::KBH + S::KBX, cn.W[l], cn.nin[l], cn.b[l], [](int kb, int h) {
+        if (kb < S::KBH) return chain_feature(kb, h);
+        const int f = posenc_feature(S::LX, kb - S::KBH, h);
+        return f >= 0 ? S::W + f : -1;
+      });
+    } else {
+      pack_dense(dst, S::MT, S::KBH, cn.W[l], cn.nin[l], cn.b[l], chain);
+    }
+  }
+  const int li = S::D;   // sigma head
+  float* sig = P.data() + S::SIG_OFF;
+  for (int g = 0; g < 4; ++g)
+    for (int kb = 0; kb < S::KBH; ++kb) sig[g * S::KBH + kb] = cn.W[li][chain_feature(kb, g)];
+  sig[4 * S::KBH] = cn.b[li][0];
+  float* rgb = P.data() + S::RGB_OFF;
+  if constexpr (S::DW > 0) {
+    pack_dense(P.data() + S::FEAT_OFF, S::MT, S::KBH, cn.W[li + 1], cn.nin[li + 1], cn.b[li + 1], chain);
+    pack_dense(P.data() + S::DIR_OFF, S::MTD, S::KBH + S::KBD, cn.W[li + 2], cn.nin[li + 2], cn.b[li + 2],
+               [](int kb, int h) {
+                 if (kb < S::KBH) return chain_feature(kb, h);
+                 const int f = posenc_feature(S::LD, kb - S::KBH, h);
+                 return f >= 0 ? S::W + f : -1;
+               });
+    const float* Wc = cn.W[li + 3];
+    for (int c = 0; c < 3; ++c)
+      for (int g = 0; g < 4; ++g)
+        for (int kb = 0; kb < S::KBG; ++kb) rgb[(4 * c + g) * S::KBG + kb] = Wc[c * S::DW + chain_feature(kb, g)];
+    for (int c = 0; c < 3; ++c) rgb[12 * S::KBG + c] = cn.b[li + 3][c];
+  } else {
+    const float* Wc = cn.W[li + 1];
+    const int nin = cn.nin[li + 1];
+    for (int c = 0; c < 3; ++c)
+      for (int g = 0; g < 4; ++g)
+        for (int kb = 0; kb < S::KBG; ++kb) {
+          int col;
+          if (kb < S::KBH) col = chain_feature(kb, g);
+          else {
+            const int f = posenc_feature(S::LD, kb - S::KBH, g);
+            col = f >= 0 ? S::W + f : -1;
+          }
+          rgb[(4 * c + g) * S::KBG + kb] = col >= 0 ? Wc[c * nin + col] : 0.0f;
+        }
+    for (int c = 0; c < 3; ++c) rgb[12 * S::KBG + c] = cn.b[li + 1][c];
+  }
+  return P;
+}
+
+bool same_shape(const loc_map_desc& d, int W, int D, int skip, int lx, int ld, int dw) {
+  const int dskip = d.skip_layer >= 1 ? d.skip_layer : -1;
+  return d.width == W && d.n_layers == D && dskip == skip && d.L_xyz == lx && d.L_dir == ld &&
+         d.dir_width == dw;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* loc_status_str(loc_status s) {
+  switch (s) {
+    case LOC_OK: return "ok";
+    case LOC_E_ARG: return "invalid argument";
+    case LOC_E_HIP: return "HIP runtime error";
+    case LOC_E_OOM: return "out of device memory";
+    case LOC_E_DEGENERATE: return "degenerate weights";
+    case LOC_E_UNSUPPORTED: return "unsupported map shape or precision";
+    case LOC_E_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* loc_last_error(const loc_ctx* c) { return c ? c->err.c_str() : ""; }
+
+loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) {
+  if (!out) return LOC_E_ARG;
+  *out = nullptr;
+  if (!d || !d->params) return LOC_E_ARG;
+  if (!(d->near_ >= 0.0f && d->far_ > d->near_)) return LOC_E_ARG;
+  if (d->n_coarse < 1 || d->n_coarse > 256 || d->n_fine < 0 || d->n_fine > 256) return LOC_E_ARG;
+  if (!(d->alpha > 0.0f && d->alpha < 0.5f) || !(d->tau > 0.0f)) return LOC_E_ARG;
+  if (d->precision != LOC_FP32) return LOC_E_UNSUPPORTED;
+  int kind;
+  long macs, total;
+  if (same_shape(*d, 64, 4, -1, 6, 2, 0)) { kind = kMapSmall; macs = SmallMap::macs(); total = SmallMap::TOTAL; }
+  else if (same_shape(*d, 256, 8, 5, 10, 4, 128)) { kind = kMapNerf; macs = NerfMap::macs(); total = NerfMap::TOTAL; }
+  else return LOC_E_UNSUPPORTED;
+  Canon cn;
+  if (!canon_split(*d, cn)) return LOC_E_ARG;
+  loc_ctx* c = new (std::nothrow) loc_ctx();
+  if (!c) return LOC_E_OOM;
+  c->desc = *d;
+  c->desc.params = nullptr;
+  c->kind = kind;
+  c->macs = macs;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LOC_E_HIP; }
+  std::vector<float> P = kind == kMapSmall ? pack_map<SmallMap>(*d) : pack_map<NerfMap>(*d);
+  if (hipMalloc(&c->weights, sizeof(float) * total) != hipSuccess ||
+      hipMalloc(&c->flags, sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    loc_destroy(c);
+    return LOC_E_OOM;
+  }
+  if (hipMemcpyAsync(c->weights, P.data(), sizeof(float) * total, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    loc_destroy(c);
+    return LOC_E_HIP;
+  }
+  *out = c;
+  return LOC_OK;
+}
+
+void loc_destroy(loc_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  hipFree(c->weights);
+  hipFree(c->flags);
+  hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
+  hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
+  for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+  for (auto e : c->free_events) hipEventDestroy(e);
+  delete c;
+}
+
+loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera* cam, int inv_R, int B, int N,
+                                const double* pose_in, const double* motion, double sigma_t, double sigma_r,
+                                uint64_t seed, uint64_t iter, double* pose_out, double* loglik_out,
+                                double* weight_out, float* uncert_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!image || !cam || !pose_in || !pose_out || !loglik_out || !weight_out)
+    return fail(c, LOC_E_ARG, "null pointer argument");
+  if (inv_R != 1 && inv_R != 2 && inv_R != 4 && inv_R != 8) return fail(c, LOC_E_ARG, "inv_R must be 1, 2, 4 or 8");
+  if (cam->W <= 0 || cam->H <= 0 || cam->W % inv_R || cam->H % inv_R)
+    return fail(c, LOC_E_ARG, "image %dx%d not divisible by level factor %d", cam->W, cam->H, inv_R);
+  if (!(cam->fx > 0 && cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(c, LOC_E_ARG, "invalid intrinsics");
+  if (B < 1 || B > 1024) return fail(c, LOC_E_ARG, "B must be in [1, 1024]");
+  if (N < 1 || (long)N * B > (1L << 30) / 256) return fail(c, LOC_E_ARG, "N out of range");
+  if (!(sigma_t >= 0.0) || !(sigma_r >= 0.0)) return fail(c, LOC_E_ARG, "negative noise scale");
+  const loc_map_desc& d = c->desc;
+  const int Sc = d.n_coarse, Sf = d.n_fine;
+  const long nr = (long)N * B;
+  loc_status s;
+  if ((s = ensure(c, c->ray_o, nr)) || (s = ensure(c, c->ray_d, nr)) || (s = ensure(c, c->obs, nr)) ||
+      (s = ensure(c, c->rgba, nr)) || (s = ensure(c, c->fe, nr)) || (s = ensure(c, c->t_c, nr * Sc)) ||
+      (s = ensure(c, c->out_c, nr * Sc)))
+    return s;
+  if (Sf > 0 && ((s = ensure(c, c->t_f, nr * Sf)) || (s = ensure(c, c->out_f, nr * Sf)))) return s;
+  {
+    hipError_t pe = hipGetLastError();
+    if (pe != hipSuccess) return fail(c, LOC_E_HIP, "pending HIP error: %s", hipGetErrorString(pe));
+  }
+
+  PredictArgs pa{};
+  pa.pose_in = pose_in;
+  pa.pose_out = pose_out;
+  for (int q = 0; q < 12; ++q) pa.motion.m[q] = motion ? motion[q] : ((q % 5 == 0) ? 1.0 : 0.0);
+  pa.sigma_t = sigma_t;
+  pa.sigma_r = sigma_r;
+  pa.N = N;
+  pa.seed = seed;
+  pa.iter = iter;
+  if ((s = timed(c, K_PREDICT, 0, 192.0 * N, [&] { return launch_predict(pa, c->stream); }))) return s;
+
+  RaygenArgs ra{};
+  ra.pose = pose_out;
+  ra.image = image;
+  ra.W_full = cam->W;
+  ra.s = inv_R;
+  ra.Wl = cam->W / inv_R;
+  ra.Hl = cam->H / inv_R;
+  ra.fx = cam->fx / inv_R;
+  ra.fy = cam->fy / inv_R;
+  ra.cx = cam->cx / inv_R;
+  ra.cy = cam->cy / inv_R;
+  ra.N = N;
+  ra.B = B;
+  ra.seed = seed;
+  ra.iter = iter;
+  ra.ray_o = c->ray_o.p;
+  ra.ray_d = c->ray_d.p;
+  ra.obs = c->obs.p;
+  if ((s = timed(c, K_RAYGEN, 0, nr * (48.0 + 12.0 * inv_R * inv_R) + 96.0 * N,
+                 [&] { return launch_raygen(ra, c->stream); })))
+    return s;
+
+  MlpArgs ma{};
+  ma.ray_o = c->ray_o.p;
+  ma.ray_d = c->ray_d.p;
+  ma.t_in = nullptr;
+  ma.t_out = c->t_c.p;
+  ma.out = c->out_c.p;
+  ma.weights = c->weights;
+  ma.n_samples = nr * Sc;
+  ma.spr = Sc;
+  ma.B = B;
+  ma.near_ = d.near_;
+  ma.dt = (d.far_ - d.near_) / (float)Sc;
+  ma.jitter = d.jitter;
+  ma.seed = seed;
+  ma.iter = iter;
+  const double fl_sample = 2.0 * (double)c->macs;
+  if ((s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
+                 [&] { return launch_mlp(c->kind, ma, c->stream); })))
+    return s;
+
+  if (Sf > 0) {
+    FineArgs fa{};
+    fa.t_coarse = c->t_c.p;
+    fa.out_coarse = c->out_c.p;
+    fa.t_fine = c->t_f.p;
+    fa.n_rays = (int)nr;
+    fa.Sc = Sc;
+    fa.Sf = Sf;
+    fa.B = B;
+    fa.far_ = d.far_;
+    fa.jitter = d.jitter;
+    fa.seed = seed;
+    fa.iter = iter;
+    if ((s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); }))) return s;
+    MlpArgs mf = ma;
+    mf.t_in = c->t_f.p;
+    mf.t_out = nullptr;
+    mf.out = c->out_f.p;
+    mf.n_samples = nr * Sf;
+    mf.spr = Sf;
+    if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
+                   [&] { return launch_mlp(c->kind, mf, c->stream); })))
+      return s;
+  }
+
+  CompositeArgs ca{};
+  ca.t_coarse = c->t_c.p;
+  ca.out_coarse = c->out_c.p;
+  ca.t_fine = Sf > 0 ? c->t_f.p : nullptr;
+  ca.out_fine = Sf > 0 ? c->out_f.p : nullptr;
+  ca.obs = c->obs.p;
+  ca.N = N;
+  ca.B = B;
+  ca.Sc = Sc;
+  ca.Sf = Sf;
+  ca.far_ = d.far_;
+  ca.log_trans = (float)std::log1p(-(double)d.alpha);
+  ca.log_opq = (float)std::log((double)d.alpha);
+  ca.tau = d.tau;
+  ca.ray_rgba = c->rgba.p;
+  ca.ray_fe = c->fe.p;
+  ca.loglik = loglik_out;
+  ca.uncert = uncert_out;
+  if ((s = timed(c, K_COMPOSITE, 0, nr * (20.0 * (Sc + Sf) + 16.0 + 24.0) + 12.0 * N,
+                 [&] { return launch_composite(ca, c->stream); })))
+    return s;
+  if ((s = timed(c, K_NORMALIZE, 0, 16.0 * N,
+                 [&] { return launch_normalize(loglik_out, weight_out, N, c->flags, c->stream); })))
+    return s;
+  c->last_N = N;
+  c->last_B = B;
+  return LOC_OK;
+}
+
+loc_status loc_resample(loc_ctx* c, const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
+                        int32_t* idx_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!weight || !idx_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n_in < 1 || n_in > (1 << 24) || n_out < 1 || n_out > (1 << 24))
+    return fail(c, LOC_E_ARG, "n_in and n_out must be in [1, 2^24]");
+  loc_status s;
+  if ((s = ensure(c, c->prefix, (size_t)n_in))) return s;
+  return timed(c, K_RESAMPLE, 0, 8.0 * n_in * 2 + 4.0 * n_out, [&] {
+    return launch_resample(weight, n_in, n_out, seed, iter, c->prefix.p, idx_out, c->flags, c->stream);
+  });
+}
+
+loc_status loc_ray_outputs(loc_ctx* c, float* rgb, float* opacity, float* F, float* E) {
+  if (!c) return LOC_E_ARG;
+  if (c->last_N == 0) return fail(c, LOC_E_STATE, "no update has run on this context");
+  const int n = c->last_N * c->last_B;
+  return timed(c, K_SPLIT, 0, 24.0 * n, [&] {
+    return launch_split_ray_outputs(c->rgba.p, c->fe.p, n, rgb, opacity, F, E, c->stream);
+  });
+}
+
+loc_status loc_sync(loc_ctx* c, int* flags) {
+  if (!c) return LOC_E_ARG;
+  int h = 0;
+  HIP_TRY(c, hipMemcpyAsync(&h, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->flags, 0, sizeof(int), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (flags) *flags = h;
+  return LOC_OK;
+}
+
+loc_status loc_set_profiling(loc_ctx* c, int enable) {
+  if (!c) return LOC_E_ARG;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) { c->free_events.push_back(p.a); c->free_events.push_back(p.b); }
+  c->pending.clear();
+  for (int k = 0; k < K_COUNT; ++k) { c->launches[k] = 0; c->ms[k] = c->flop[k] = c->bytes[k] = 0.0; }
+  c->prof = enable != 0;
+  return LOC_OK;
+}
+
+loc_status loc_kernel_stats(loc_ctx* c, loc_kernel_stat* out, int max, int* n) {
+  if (!c || (max > 0 && !out)) return LOC_E_ARG;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, p.a, p.b));
+    c->launches[p.kid] += 1;
+    c->ms[p.kid] += ms;
+    c->flop[p.kid] += p.flop;
+    c->bytes[p.kid] += p.bytes;
+    c->free_events.push_back(p.a);
+    c->free_events.push_back(p.b);
+  }
+  c->pending.clear();
+  int k_out = 0;
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (c->launches[k] == 0) continue;
+    if (k_out < max) {
+      loc_kernel_stat& st = out[k_out];
+      std::memset(&st, 0, sizeof st);
+      std::strncpy(st.name, kKernelNames[k], sizeof st.name - 1);
+      st.launches = c->launches[k];
+      st.ms = c->ms[k];
+      st.flop = c->flop[k];
+      st.bytes = c->bytes[k];
+    }
+    ++k_out;
+  }
+  if (n) *n = k_out;
+  return LOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and the FP64 oracle on the same seeded inputs, and summarise differences."""
+import math
+
+import numpy as np
+
+from oracle import mcl
+from paper_2406_12202_amd import synth
+
+
+def inputs(workload, seed, N=None, **spec_over):
+    s = synth.spec(workload, **spec_over)
+    p = synth.map_params(s, seed)
+    cam = synth.camera(workload)
+    poses = synth.particles(workload, seed, N=N)
+    img = synth.observation(workload, seed)
+    return s, p, cam, poses, img
+
+
+def run_gpu(ctx, img, cam, inv_R, B, poses, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0, it=0):
+    import torch
+    dev = torch.device("cuda", 0)
+    img_d = torch.as_tensor(np.ascontiguousarray(img, dtype=np.float32), device=dev)
+    pose_d = torch.as_tensor(np.ascontiguousarray(poses, dtype=np.float64), device=dev)
+    po, ll, w, un = ctx.loc_update_particles(img_d, cam, inv_R, B, pose_d, motion, sigma_t, sigma_r,
+                                             seed, it)
+    rgb, op, F, E = ctx.loc_ray_outputs()
+    flags = ctx.loc_sync()
+    out = dict(pose=po.cpu().numpy(), loglik=ll.cpu().numpy(), weight=w.cpu().numpy(),
+               uncert=un.cpu().numpy(), C=rgb.cpu().numpy().astype(np.float64),
+               A=op.cpu().numpy().astype(np.float64), F=F.cpu().numpy().astype(np.float64),
+               E=E.cpu().numpy().astype(np.float64), flags=flags)
+    return out
+
+
+def run_oracle(spec, params, img, cam, inv_R, B, poses, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0, it=0,
+               subset=None):
+    return mcl.update_particles(spec, params, img, cam, inv_R, B, poses, motion, sigma_t, sigma_r, seed, it,
+                                subset=subset)
+
+
+def stats(name, a, b):
+    d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).ravel()
+    if d.size == 0:
+        return dict(name=name, n=0)
+    r = dict(name=name, n=int(d.size), p50=float(np.percentile(d, 50)), p99=float(np.percentile(d, 99)),
+             max=float(d.max()))
+    print("%-10s n=%-7d p50=%.3e p99=%.3e max=%.3e" % (name, r["n"], r["p50"], r["p99"], r["max"]), flush=True)
+    return r
+
+
+def frac_over(a, b, tol):
+    d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))
+    return float((d > tol).mean())

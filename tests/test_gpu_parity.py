@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Needs an MI355X and the built library.
+
+Tolerances (FP32 path; derivation in the design notes):
+  poses              1e-12 (float64 on both sides)
+  colour C, opacity A  TOL_C per map (float32 MLP + float32 compositing)
+  uncertainty F      99% of rays within TOL_F, all within TOL_F_MAX (F is
+                     continuous but its slope is 1/sigma at the threshold
+                     crossing, so thin-density crossings amplify rounding)
+  log-likelihood l   TOL_L absolute
+  weights            relative TOL_W
+  resampling         bit-exact
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mcl
+from paper_2406_12202_amd import synth
+from parity_util import frac_over, inputs, run_gpu, run_oracle, stats
+
+pytestmark = pytest.mark.gpu
+
+TOL = {
+    "small": dict(C=2e-5, F=1e-3, F_MAX=0.05, L=2e-3, W=1e-2),
+    "nerf": dict(C=2e-4, F=2e-3, F_MAX=0.1, L=1e-2, W=5e-2),
+}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _ctx(spec, params):
+    from paper_2406_12202_amd import binding
+    return binding.Context(spec, params)
+
+
+def _compare(g, o, tol, subset=None):
+    idx = list(range(g["loglik"].shape[0])) if subset is None else list(subset)
+    stats("pose", g["pose"][idx].reshape(-1), o["pose"].reshape(-1))
+    assert np.allclose(g["pose"][idx].reshape(len(idx), 12), o["pose"].reshape(len(idx), 12), atol=1e-12, rtol=0)
+    rC = stats("C", g["C"][idx], o["C"])
+    rA = stats("A", g["A"][idx], o["A"])
+    rF = stats("F", g["F"][idx], o["F"])
+    stats("E", g["E"][idx], o["E"])
+    rL = stats("loglik", g["loglik"][idx], o["loglik"])
+    stats("uncert", g["uncert"][idx], o["uncert"])
+    assert rC["max"] <= tol["C"] and rA["max"] <= tol["C"]
+    assert frac_over(g["F"][idx], o["F"], tol["F"]) <= 0.01
+    assert rF["max"] <= tol["F_MAX"]
+    assert rL["max"] <= tol["L"]
+
+
+def test_small_map_parity(torch_dev):
+    s, p, cam, poses, img = inputs("small", 1)
+    ctx = _ctx(s, p)
+    kw = dict(sigma_t=0.02, sigma_r=0.02, seed=5, it=3)
+    g = run_gpu(ctx, img, cam, 1, 16, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 16, poses, **kw)
+    _compare(g, o, TOL["small"])
+    rw = np.abs(g["weight"] - o["weight"]) / np.maximum(o["weight"], 1e-300)
+    big = o["weight"] > 1e-6
+    print("weight rel max (w > 1e-6): %.3e" % rw[big].max())
+    assert rw[big].max() <= TOL["small"]["W"]
+    assert abs(g["weight"].sum() - 1.0) < 1e-12
+    assert g["flags"] == 0
+
+
+def test_small_map_ragged_tiles_levels_and_motion(torch_dev):
+    # 37 coarse samples (ragged last tile), level factor 2, an explicit motion
+    # O_t, no jitter, 5 particles x 3 rays
+    s, p, cam, poses, img = inputs("small", 2, N=5, n_coarse=37, jitter=0)
+    ctx = _ctx(s, p)
+    from oracle import se3
+    O = se3.exp_se3([0.05, -0.02, 0.01], [0.01, 0.02, -0.03])
+    for inv_R in (2, 4):
+        kw = dict(motion=O, sigma_t=0.01, sigma_r=0.01, seed=9, it=inv_R)
+        g = run_gpu(ctx, img, cam, inv_R, 3, poses, **kw)
+        o = run_oracle(s, p, img, cam, inv_R, 3, poses, **kw)
+        _compare(g, o, TOL["small"])
+
+
+def test_single_particle_single_ray(torch_dev):
+    s, p, cam, poses, img = inputs("small", 3, N=1)
+    ctx = _ctx(s, p)
+    g = run_gpu(ctx, img, cam, 1, 1, poses, seed=1, it=0)
+    o = run_oracle(s, p, img, cam, 1, 1, poses, seed=1, it=0)
+    _compare(g, o, TOL["small"])
+    assert g["weight"][0] == 1.0
+
+
+def test_nerf_map_hierarchical_parity(torch_dev):
+    s, p, cam, poses, img = inputs("nerf", 4, N=6)
+    ctx = _ctx(s, p)
+    kw = dict(seed=11, it=2)
+    g = run_gpu(ctx, img, cam, 1, 8, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 8, poses, **kw)
+    _compare(g, o, TOL["nerf"])
+
+
+def test_nerf_map_full_size_sampled(torch_dev):
+    # the bench workload: 400 particles x 64 rays x (64 + 128) samples; the
+    # oracle checks three particles one by one
+    s, p, cam, poses, img = inputs("nerf", 5)
+    ctx = _ctx(s, p)
+    kw = dict(seed=3, it=7)
+    g = run_gpu(ctx, img, cam, 1, 64, poses, **kw)
+    sub = [0, 199, 399]
+    o = run_oracle(s, p, img, cam, 1, 64, poses, subset=sub, **kw)
+    _compare(g, o, TOL["nerf"], subset=sub)
+    assert abs(g["weight"].sum() - 1.0) < 1e-12
+    assert np.all(np.isfinite(g["loglik"]))
+
+
+def test_tau_dominant_reduces_to_eq4(torch_dev):
+    # tau >= far - near: F = tau on every ray, so the normalised weights equal
+    # normalised (B / sum_j E_j)^4 computed from the GPU's own E
+    s, p, cam, poses, img = inputs("small", 6, tau=10.0)
+    ctx = _ctx(s, p)
+    g = run_gpu(ctx, img, cam, 1, 8, poses, seed=2, it=1)
+    assert np.all(g["F"] == np.float32(10.0))
+    ll4 = np.array([4 * (math.log(8) - math.log(e.sum())) for e in g["E"]])
+    w4 = np.exp(ll4 - ll4.max())
+    w4 /= w4.sum()
+    assert np.allclose(g["weight"], w4, rtol=1e-4, atol=1e-12)
+
+
+def test_update_is_deterministic(torch_dev):
+    s, p, cam, poses, img = inputs("nerf", 7, N=16)
+    ctx = _ctx(s, p)
+    a = run_gpu(ctx, img, cam, 1, 16, poses, seed=4, it=4)
+    b = run_gpu(ctx, img, cam, 1, 16, poses, seed=4, it=4)
+    for k in ("pose", "loglik", "weight", "C", "A", "F", "E"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_degenerate_observation_flags_and_zero_weights(torch_dev):
+    s, p, cam, poses, img = inputs("small", 8, N=4)
+    ctx = _ctx(s, p)
+    bad = np.full_like(img, np.nan)
+    g = run_gpu(ctx, bad, cam, 1, 4, poses, seed=1, it=1)
+    assert g["flags"] & 1
+    assert np.all(g["weight"] == 0.0)
+    o = run_oracle(s, p, bad, cam, 1, 4, poses, seed=1, it=1)
+    assert np.all(o["weight"] == 0.0)
+
+
+# ----------------------------------------------------------------------------- resampling
+
+def _resample_gpu(ctx, w, n_out, seed, it):
+    import torch
+    wd = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64), device="cuda")
+    idx = ctx.loc_resample(wd, n_out, seed, it)
+    flags = ctx.loc_sync()
+    return idx.cpu().numpy().tolist(), flags
+
+
+@pytest.mark.parametrize("case", ["random", "uniform", "onehot", "ties", "tiny", "large", "upsample", "mixed"])
+def test_resample_bit_exact(torch_dev, case):
+    s, p, _, _, _ = inputs("small", 0, N=1)
+    ctx = _ctx(s, p)
+    rng = np.random.default_rng(sum(map(ord, case)))
+    n_out = None
+    if case == "random":
+        w = rng.random(1000) ** 8
+    elif case == "uniform":
+        w = np.full(777, 1 / 777)
+    elif case == "onehot":
+        w = np.zeros(300)
+        w[123] = 1.0
+    elif case == "ties":
+        w = np.repeat(rng.random(10), 50)
+    elif case == "tiny":
+        w = rng.random(5) * 1e-300
+    elif case == "large":
+        w = rng.exponential(1.0, 10000) ** 3
+    elif case == "upsample":
+        w = rng.random(100)
+        n_out = 3000
+    else:
+        w = rng.random(2000)
+        w[::7] = 0.0
+        w[3] = np.nan
+        w[5] = -1.0
+        w[9] = np.inf
+    n_out = n_out or w.size
+    for seed, it in [(1, 0), (77, 12345)]:
+        got, flags = _resample_gpu(ctx, w, n_out, seed, it)
+        want = mcl.resample(w, n_out, seed, it)
+        assert got == want
+        assert flags == 0
+
+
+def test_resample_degenerate(torch_dev):
+    s, p, _, _, _ = inputs("small", 0, N=1)
+    ctx = _ctx(s, p)
+    got, flags = _resample_gpu(ctx, np.zeros(50), 20, 1, 1)
+    assert flags & 2 and got == [-1] * 20
+    assert mcl.resample(np.zeros(50), 20, 1, 1) is None
