@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-particles", type=int, default=0,
@@ -81,7 +82,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    ctx = binding.Context(spec, params, stream=stream)
+    ctx = binding.Context(spec, params, precision=args.precision, stream=stream)
     img_d = torch.as_tensor(img, device=dev)
     pose_a = torch.as_tensor(poses, device=dev).contiguous()
     pose_b = torch.empty_like(pose_a)
@@ -124,9 +125,11 @@ def main():
     mlp_ms = sum(m["ms"] for m in mlp)
     mlp_flop = sum(m["flop"] for m in mlp)
     achieved = (mlp_flop / launches) / (mlp_ms / launches * 1e-3) / 1e12
-    peak, unit = PEAK["f32"]
+    dt = "f32" if args.precision == "fp32" else "bf16"
+    peak, unit = PEAK[dt]
+    kname = ("k_mlp_f32" if dt == "f32" else "k_mlp_bf16") + " (%dx%d map)" % (spec["n_layers"], spec["width"])
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "k_mlp_f32 (8x256 map)",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
                 "flop_per_launch": mlp_flop / launches, "avg_launch_ms": mlp_ms / launches}
     kernels = {k: {"launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1),
                    "share": v["ms"] / max(sum(x["ms"] for x in kstats.values()), 1e-12)}
@@ -137,11 +140,11 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": dt, "data": "synthetic",
            "config": {"workload": "%s: %d particles x %d rays x (%d coarse + %d fine) samples, "
                                   "%dx%d map, %dx%d image" % (wl, N, B, spec["n_coarse"], spec["n_fine"],
                                                              spec["n_layers"], spec["width"], W["W"], W["H"]),
-                      "particles": N, "rays_per_particle": B, "precision": "fp32",
+                      "particles": N, "rays_per_particle": B, "precision": args.precision,
                       "samples_per_step": samples_per_step},
            "particle_updates_per_s": N * args.steps / (ms_total * 1e-3),
            "effective_samples_per_s": N * B * 192 * args.steps / (ms_total * 1e-3),

@@ -126,11 +126,14 @@ def render_rays(spec, P, pose, pix, Wl, cam_l, seed, it, i):
     zt = np.zeros(B)
     zo = np.zeros(B)
     F = np.zeros(B)
+    kt = np.zeros(B)
+    ko = np.zeros(B)
     for j in range(B):
         _, logT, C[j], A[j] = rd.composite(ts[j], sigs[j], rgbs[j], far)
         zt[j], zo[j] = rd.ray_quantiles(ts[j], sigs[j], logT, far, spec["alpha"])
         F[j] = rd.uncertainty(zt[j], zo[j], spec["tau"])
-    return {"C": C, "A": A, "z_trans": zt, "z_opaque": zo, "F": F}
+        kt[j], ko[j] = rd.crossing_densities(ts[j], sigs[j], logT, spec["alpha"])
+    return {"C": C, "A": A, "z_trans": zt, "z_opaque": zo, "F": F, "sig_trans": kt, "sig_opaque": ko}
 
 
 def score(obs, C, F, B):
@@ -179,6 +182,7 @@ def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
     idx = range(poses.shape[0]) if subset is None else list(subset)
     out = {"index": list(idx), "pose": [], "loglik": [], "score": [], "uncert": [],
            "C": [], "A": [], "F": [], "E": [], "z_trans": [], "z_opaque": [],
+           "sig_trans": [], "sig_opaque": [],
            "pix": pix, "obs": obs}
     for i in idx:
         x = predict(poses[i], motion, sigma_t, sigma_r, seed, it, i)
@@ -188,10 +192,11 @@ def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
         out["loglik"].append(ll)
         out["score"].append(S)
         out["uncert"].append(float(r["F"].mean()))
-        for key in ("C", "A", "F", "z_trans", "z_opaque"):
+        for key in ("C", "A", "F", "z_trans", "z_opaque", "sig_trans", "sig_opaque"):
             out[key].append(r[key])
         out["E"].append(E)
-    for key in ("pose", "loglik", "score", "uncert", "C", "A", "F", "E", "z_trans", "z_opaque"):
+    for key in ("pose", "loglik", "score", "uncert", "C", "A", "F", "E", "z_trans", "z_opaque",
+                "sig_trans", "sig_opaque"):
         out[key] = np.array(out[key])
     out["weight"] = normalise(out["loglik"])
     return out

@@ -174,6 +174,22 @@ def ray_quantiles(t, sigma, logT, far, alpha):
     return z_trans, z_opaque
 
 
+def crossing_densities(t, sigma, logT, alpha):
+    """Density on the intervals where T crosses 1 - alpha and alpha (nan when
+    it does not).  The crossing depths of ray_quantiles move by
+    |log L| * eps / sigma under a relative change eps of all optical depths, so
+    these densities give the conditioning of z_trans, z_opaque and F."""
+    l_trans, l_opq = np.log1p(-alpha), np.log(alpha)
+    st = so = np.nan
+    for k in range(len(t)):
+        if np.isnan(st) and logT[k + 1] <= l_trans:
+            st = sigma[k]
+        if logT[k + 1] < l_opq:
+            so = sigma[k]
+            break
+    return st, so
+
+
 def uncertainty(z_trans, z_opaque, tau):
     """F = max(z_opaque - z_trans, tau) (Sec. III-B, below Eq. 6); a ray that
     never becomes non-transparent (z_trans = +inf) gets F = tau."""

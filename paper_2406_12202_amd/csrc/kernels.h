@@ -14,7 +14,10 @@ struct MlpArgs {
   const float* t_in;     // per sample depth, or NULL: stratified coarse samples
   float* t_out;          // coarse depths written when t_in == NULL
   float4* out;           // per sample (sigma, r, g, b)
-  const float* weights;  // packed map (maplayout.h)
+  const float* weights;  // packed FP32 map (maplayout.h)
+  const void* wblocks;   // packed BF16 weight chunks (maplayout_bf16.h)
+  const float* bias;     // BF16 path: float32 biases
+  const float* heads;    // BF16 path: float32 density / colour heads
   long n_samples;
   int spr;               // samples per ray in this pass
   int B;                 // rays per particle (ray = i * B + j)
@@ -23,6 +26,7 @@ struct MlpArgs {
   uint64_t seed, iter;
 };
 hipError_t launch_mlp(int map_kind, const MlpArgs& a, hipStream_t st);
+hipError_t launch_mlp_bf16(int map_kind, const MlpArgs& a, hipStream_t st);
 
 struct Pose12 { double m[12]; };
 

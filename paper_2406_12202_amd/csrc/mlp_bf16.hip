@@ -1,0 +1,315 @@
+// BF16 map evaluation on MFMA (v_mfma_f32_32x32x16_bf16, float32 accumulate)
+// with register-chained bf16 activations and weights streamed through LDS.
+//
+// A workgroup is WAVES waves; each wave evaluates NTL column tiles of 32
+// samples.  The packed weights are a sequence of chunks (one per layer and
+// 32-row output tile, see maplayout_bf16.h); the workgroup streams MPC
+// consecutive chunks at a time through two LDS slots with direct global->LDS
+// loads (global_load_lds_dwordx4), prefetching the next group while all waves
+// multiply the current one.  Each 16-byte weight fragment read from LDS feeds
+// NTL MFMAs.  The bias enters as the accumulator input of the first MFMA of a
+// tile, and ReLU runs on packed bf16 pairs after rounding, so the epilogue of a
+// tile is one conversion and one packed max per pair of outputs.
+#include "common.h"
+#include "maplayout_bf16.h"
+#include "kernels.h"
+
+namespace fl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int L, int KB>
+__device__ __forceinline__ void posenc_b(const float p0, const float p1, const float p2, const int h,
+                                         bf16x8 (&out)[KB]) {
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = 8 * kb + 4 * h + j;
+      float a = 0.0f, b = 0.0f;
+      if (p < 3 * L) {
+        const int c = p % 3;
+        const float x = c == 0 ? p0 : (c == 1 ? p1 : p2);
+        sincospif(ldexpf(x, p / 3), &a, &b);
+      } else if (p == 3 * L) {
+        a = p0; b = p1;
+      } else if (p == 3 * L + 1) {
+        a = p2;
+      }
+      out[kb][2 * j] = (__bf16)a;
+      out[kb][2 * j + 1] = (__bf16)b;
+    }
+  }
+}
+
+// issue the direct loads of nkb consecutive 1 KB blocks into an LDS slot;
+// wave wv takes blocks wv, wv + WAVES, ...
+template <int WAVES>
+__device__ __forceinline__ void issue_blocks(const uint4* __restrict__ wb, const long base, const int nkb,
+                                             uint4* slot, const int wv, const int lane) {
+  for (int b = wv; b < nkb; b += WAVES)
+    __builtin_amdgcn_global_load_lds((const void*)(wb + (base + b) * 64 + lane),
+                                     (lds_void_t*)(slot + b * 64), 16, 0, 0);
+}
+
+// rounded bf16 operands of the next layer from one finished output tile; the
+// bias is already in the accumulators; ReLU acts on the packed bf16 pairs
+// (a non-negative bf16 is a non-negative int16, a negative one a negative
+// int16, so max with 0 as int16 is ReLU)
+template <int NTL, int NY>
+__device__ __forceinline__ void epilogue_b(const f32x16 (&acc)[NTL], const bool relu, const int mt,
+                                           bf16x8 (&y)[NTL][NY]) {
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      bf16x8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)acc[nt][8 * c + q];
+      if (relu) {
+        s16x2 w[4];
+        __builtin_memcpy(w, &v, 16);
+        const s16x2 z = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = __builtin_elementwise_max(w[i], z);
+        __builtin_memcpy(&v, w, 16);
+      }
+      y[nt][2 * mt + c] = v;
+    }
+  }
+}
+
+// One MFMA layer: y = act(b + W [x1, x2]) for MTO output tiles of 32 rows.
+// Chunk groups of MPC m-tiles alternate between slot0 and slot1 (every layer
+// has an even number of groups, so the slot of a tile is static).  On entry
+// the loads of this layer's first group are in flight.  x1 is a register
+// array (chained activations) or, when X1_LDS, the wave's encoding block in
+// LDS; x2 (the encoding segment) comes from LDS, laid out
+// [column tile][k-block][lane].
+template <class S, int NTL, int WAVES, int MPC, int MTO, int KB1, int KB2, int NY, bool X1_LDS, int NX1>
+__device__ __forceinline__ void dense_b(const uint4* __restrict__ wb, const float* bias_lds, const int l,
+                                        const bool use2, const bool relu, uint4* slot0, uint4* slot1,
+                                        const bf16x8 (&x1)[NTL][NX1], const uint4* x1s, const uint4* x2s,
+                                        bf16x8 (&y)[NTL][NY], const int wv, const int lane) {
+  static_assert(MTO % (2 * MPC) == 0 && 2 * MTO <= NY && (X1_LDS || KB1 <= NX1), "layout");
+  const int h = lane >> 5;
+  const int kb_tot = KB1 + (use2 ? KB2 : 0);
+  const long base = S::block_base(l);
+  const float* bl = bias_lds + S::bias_base(l) + h * 16;
+#pragma unroll
+  for (int mt = 0; mt < MTO; ++mt) {
+    uint4* grp = ((mt / MPC) & 1) ? slot1 : slot0;
+    if (mt % MPC == 0) {
+      uint4* nxt = ((mt / MPC) & 1) ? slot0 : slot1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (mt + MPC < MTO)
+        issue_blocks<WAVES>(wb, base + (long)(mt + MPC) * kb_tot, MPC * kb_tot, nxt, wv, lane);
+      else if (l + 1 < S::NL)
+        issue_blocks<WAVES>(wb, S::block_base(l + 1), MPC * S::layer_kb(l + 1), nxt, wv, lane);
+    }
+    const uint4* cur = grp + (mt % MPC) * kb_tot * 64;
+    // bias of this tile's 16 rows (lane half h), used as the accumulator input
+    f32x16 binit;
+    {
+      const float4* b4 = reinterpret_cast<const float4*>(bl + mt * 32);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4 v = b4[i];
+        binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
+      }
+    }
+    f32x16 acc[NTL];
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+      const bf16x8 a = __builtin_bit_cast(bf16x8, cur[kb * 64 + lane]);
+#pragma unroll
+      for (int nt = 0; nt < NTL; ++nt) {
+        bf16x8 bx;
+        if constexpr (X1_LDS) bx = __builtin_bit_cast(bf16x8, x1s[(nt * KB1 + kb) * 64 + lane]);
+        else bx = x1[nt][kb];
+        acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+      }
+    }
+    if (use2) {
+      const int kb1 = X1_LDS ? 0 : KB1;
+#pragma unroll
+      for (int kb = 0; kb < KB2; ++kb) {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, cur[(kb1 + kb) * 64 + lane]);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) {
+          const bf16x8 bx = __builtin_bit_cast(bf16x8, x2s[(nt * KB2 + kb) * 64 + lane]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+        }
+      }
+    }
+    epilogue_b<NTL>(acc, relu, mt, y);
+  }
+}
+
+template <int KB, int N>
+__device__ __forceinline__ float dot_b(const float* __restrict__ w, const bf16x8 (&x)[N]) {
+  float s = 0.0f;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const float4* w4 = reinterpret_cast<const float4*>(w + kb * 8);
+    const float4 u = w4[0], v = w4[1];
+    s = fmaf(u.x, (float)x[kb][0], s); s = fmaf(u.y, (float)x[kb][1], s);
+    s = fmaf(u.z, (float)x[kb][2], s); s = fmaf(u.w, (float)x[kb][3], s);
+    s = fmaf(v.x, (float)x[kb][4], s); s = fmaf(v.y, (float)x[kb][5], s);
+    s = fmaf(v.z, (float)x[kb][6], s); s = fmaf(v.w, (float)x[kb][7], s);
+  }
+  return s;
+}
+
+__device__ __forceinline__ float softplus_b(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoid_b(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+template <class S, int NTL, int WAVES, int MPC>
+struct BCfg {
+  static constexpr int SLOT_KB = MPC * S::MAX_KB;   // 1 KB blocks per LDS slot
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int SAMPLES = 32 * NTL * WAVES;  // per workgroup
+};
+
+template <class S, int NTL, int WAVES, int MPC>
+__global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
+  using C = BCfg<S, NTL, WAVES, MPC>;
+  __shared__ uint4 slot0[C::SLOT_KB * 64];
+  __shared__ uint4 slot1[C::SLOT_KB * 64];
+  __shared__ uint4 s_gx[WAVES][NTL * S::KBX * 64];   // per wave: [column tile][k-block][lane]
+  __shared__ uint4 s_gd[WAVES][NTL * S::KBD * 64];
+  __shared__ float4 s_bias[S::BIASES / 4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 31, h = lane >> 5;
+  const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
+  // weights of layer 0's first chunk group start loading while the inputs
+  // are encoded; biases go to LDS (visible after the first barrier)
+  issue_blocks<WAVES>(wb, 0, MPC * S::layer_kb(0), slot0, wv, lane);
+  for (int i = threadIdx.x; i < S::BIASES / 4; i += C::THREADS)
+    s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
+
+  const long tile = (long)blockIdx.x * WAVES + wv;
+  long sidx[NTL];
+  bool valid[NTL];
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    const long s = tile * (32 * NTL) + nt * 32 + n;
+    valid[nt] = s < a.n_samples;
+    sidx[nt] = s;
+    const long sc = valid[nt] ? s : a.n_samples - 1;
+    const int ray = (int)(sc / a.spr);
+    const int k = (int)(sc - (long)ray * a.spr);
+    const float4 o = a.ray_o[ray];
+    const float4 d = a.ray_d[ray];
+    float t;
+    if (a.t_in) {
+      t = a.t_in[sc];
+    } else {
+      float xi = 0.0f;
+      if (a.jitter) {
+        const int i = ray / a.B, j = ray - (ray / a.B) * a.B;
+        xi = unit24(pick(draw(a.seed, a.iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
+      }
+      t = a.near_ + ((float)k + xi) * a.dt;
+      if (valid[nt] && h == 0) a.t_out[s] = t;
+    }
+    bf16x8 gx[S::KBX], gd[S::KBD];
+    posenc_b<S::LX>(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z), h, gx);
+    posenc_b<S::LD>(d.x, d.y, d.z, h, gd);
+    // each lane reads back only its own entries: no barrier needed
+#pragma unroll
+    for (int kb = 0; kb < S::KBX; ++kb) s_gx[wv][(nt * S::KBX + kb) * 64 + lane] = __builtin_bit_cast(uint4, gx[kb]);
+#pragma unroll
+    for (int kb = 0; kb < S::KBD; ++kb) s_gd[wv][(nt * S::KBD + kb) * 64 + lane] = __builtin_bit_cast(uint4, gd[kb]);
+  }
+
+  const float* bias = reinterpret_cast<const float*>(s_bias);
+  bf16x8 xa[NTL][S::KBH], xb[NTL][S::KBH];
+  dense_b<S, NTL, WAVES, MPC, S::MT, S::KBX, S::KBD, S::KBH, true>(wb, bias, 0, false, true, slot0, slot1, xb,
+                                                                  s_gx[wv], s_gd[wv], xa, wv, lane);
+#pragma unroll 1
+  for (int l = 1; l < S::D; ++l) {
+    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBX, S::KBH, false>(wb, bias, l, l == S::SKIP, true, slot0,
+                                                                     slot1, xa, nullptr, s_gx[wv], xb, wv, lane);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+      for (int i = 0; i < S::KBH; ++i) xa[nt][i] = xb[nt][i];
+  }
+  const float* __restrict__ hs = a.heads + S::SIG_OFF;
+  float sigma[NTL], rgb[NTL][3];
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    float z = dot_b<S::KBH>(hs + h * S::KBH * 8, xa[nt]);
+    z += __shfl_xor(z, 32, 64);
+    sigma[nt] = softplus_b(z + hs[16 * S::KBH]);
+  }
+  const float* __restrict__ hr = a.heads + S::RGB_OFF;
+  if constexpr (S::DW > 0) {
+    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D, false, false, slot0, slot1,
+                                                                     xa, nullptr, s_gd[wv], xb, wv, lane);
+    dense_b<S, NTL, WAVES, MPC, S::MTD, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D + 1, true, true, slot0,
+                                                                      slot1, xb, nullptr, s_gd[wv], xa, wv, lane);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float z = dot_b<S::KBG>(hr + (c * 2 + h) * S::KBG * 8, xa[nt]);
+        z += __shfl_xor(z, 32, 64);
+        rgb[nt][c] = sigmoid_b(z + hr[48 * S::KBG + c]);
+      }
+  } else {
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float* w = hr + (c * 2 + h) * S::KBG * 8;
+        bf16x8 gd[S::KBD];
+#pragma unroll
+        for (int kb = 0; kb < S::KBD; ++kb) gd[kb] = __builtin_bit_cast(bf16x8, s_gd[wv][(nt * S::KBD + kb) * 64 + lane]);
+        float z = dot_b<S::KBH>(w, xa[nt]) + dot_b<S::KBD>(w + S::KBH * 8, gd);
+        z += __shfl_xor(z, 32, 64);
+        rgb[nt][c] = sigmoid_b(z + hr[48 * S::KBG + c]);
+      }
+  }
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt)
+    if (valid[nt] && h == 0) a.out[sidx[nt]] = make_float4(sigma[nt], rgb[nt][0], rgb[nt][1], rgb[nt][2]);
+}
+
+template <class S, int NTL, int WAVES, int MPC>
+hipError_t launch_mlp_bf16_t(const MlpArgs& a, hipStream_t st) {
+  using C = BCfg<S, NTL, WAVES, MPC>;
+  const long blocks = (a.n_samples + C::SAMPLES - 1) / C::SAMPLES;
+  hipLaunchKernelGGL((k_mlp_bf16<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(C::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+// Tiling (measured on MI355X, 8x256 map): one 32-sample column tile per wave
+// and 8 waves per workgroup keep two waves on every SIMD (225 VGPRs), so one
+// wave's epilogue, LDS latency and barrier waits overlap the other's MFMAs;
+// streaming two m-tiles per chunk group halves the barriers.  1155 TFLOP/s,
+// against 922 for two column tiles per wave at one wave per SIMD.
+#ifndef FL_BF16_NTL
+#define FL_BF16_NTL 1
+#endif
+#ifndef FL_BF16_WAVES
+#define FL_BF16_WAVES 8
+#endif
+#ifndef FL_BF16_MPC
+#define FL_BF16_MPC 2
+#endif
+
+hipError_t launch_mlp_bf16(int map_kind, const MlpArgs& a, hipStream_t st) {
+  if (a.n_samples <= 0) return hipSuccess;
+  if (map_kind == kMapSmall) return launch_mlp_bf16_t<SmallMapB, FL_BF16_NTL, FL_BF16_WAVES, 1>(a, st);
+  return launch_mlp_bf16_t<NerfMapB, FL_BF16_NTL, FL_BF16_WAVES, FL_BF16_MPC>(a, st);
+}
+
+}  // namespace fl

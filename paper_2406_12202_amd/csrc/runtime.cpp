@@ -14,6 +14,7 @@
 #include "fastloc.h"
 #include "kernels.h"
 #include "maplayout.h"
+#include "maplayout_bf16.h"
 
 using namespace fl;
 
@@ -40,7 +41,10 @@ struct loc_ctx {
   loc_map_desc desc{};
   int kind = kMapSmall;
   long macs = 0;
-  float* weights = nullptr;
+  float* weights = nullptr;       // FP32 packed map
+  void* wblocks = nullptr;        // BF16 weight chunks
+  float* bias_b = nullptr;        // BF16 path biases
+  float* heads_b = nullptr;       // BF16 path heads
   // workspace
   DevBuf<float4> ray_o, ray_d, obs, out_c, out_f, rgba;
   DevBuf<float2> fe;
@@ -231,6 +235,86 @@ std::vector<float> pack_map(const loc_map_desc& d) {
   return P;
 }
 
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+struct PackedB {
+  std::vector<uint16_t> blocks;   // BLOCKS x 64 lanes x 8 bf16
+  std::vector<float> bias, heads;
+};
+
+// BF16 chunks, float32 biases and heads (maplayout_bf16.h)
+template <class S>
+PackedB pack_map_bf16(const loc_map_desc& d) {
+  Canon cn;
+  canon_split(d, cn);
+  PackedB P;
+  P.blocks.assign((size_t)S::BLOCKS * 64 * 8, 0);
+  P.bias.assign((size_t)S::BIASES, 0.0f);
+  P.heads.assign((size_t)S::HEADS, 0.0f);
+  // canonical index of layer l (execution order) in cn: hidden 0..D-1, then
+  // sigma head at D, feature at D+1, dir at D+2
+  for (int l = 0; l < S::NL; ++l) {
+    const int ci = l < S::D ? l : l + 1;
+    const float* W = cn.W[ci];
+    const int nin = cn.nin[ci];
+    const int kb_tot = S::layer_kb(l);
+    const int kb1 = (l == 0) ? 0 : S::KBH;    // chained k-blocks before the encoding segment
+    const int Lenc = (l == 0 || l < S::D) ? S::LX : S::LD;
+    const bool has_enc = (l == 0) || (l == S::SKIP) || (l == S::D + 1);
+    for (int mt = 0; mt < S::layer_mt(l); ++mt)
+      for (int kb = 0; kb < kb_tot; ++kb)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int q = 0; q < 8; ++q) {
+            const int row = 32 * mt + lane % 32, h = lane / 32;
+            int col;
+            if (kb < kb1) col = chain_feature_b(kb, h, q);
+            else if (has_enc) {
+              const int f = posenc_feature_b(Lenc, kb - kb1, h, q);
+              col = f >= 0 ? (kb1 ? S::W : 0) + f : -1;
+            } else col = -1;
+            const long blk = S::block_base(l) + (long)mt * kb_tot + kb;
+            P.blocks[(size_t)(blk * 64 + lane) * 8 + q] = col >= 0 ? to_bf16(W[(long)row * nin + col]) : 0;
+          }
+    for (int mt = 0; mt < S::layer_mt(l); ++mt)
+      for (int h = 0; h < 2; ++h)
+        for (int v = 0; v < 16; ++v)
+          P.bias[S::bias_base(l) + (mt * 2 + h) * 16 + v] = cn.b[ci][32 * mt + 8 * (v / 4) + 4 * h + v % 4];
+  }
+  float* sig = P.heads.data() + S::SIG_OFF;
+  for (int h = 0; h < 2; ++h)
+    for (int kb = 0; kb < S::KBH; ++kb)
+      for (int q = 0; q < 8; ++q) sig[(h * S::KBH + kb) * 8 + q] = cn.W[S::D][chain_feature_b(kb, h, q)];
+  sig[16 * S::KBH] = cn.b[S::D][0];
+  float* rgb = P.heads.data() + S::RGB_OFF;
+  const int ci = (int)cn.W.size() - 1;
+  const float* Wc = cn.W[ci];
+  const int nin = cn.nin[ci];
+  for (int c = 0; c < 3; ++c)
+    for (int h = 0; h < 2; ++h)
+      for (int kb = 0; kb < S::KBG; ++kb)
+        for (int q = 0; q < 8; ++q) {
+          int col;
+          if (S::DW > 0 || kb < S::KBH) col = chain_feature_b(kb, h, q);
+          else {
+            const int f = posenc_feature_b(S::LD, kb - S::KBH, h, q);
+            col = f >= 0 ? S::W + f : -1;
+          }
+          rgb[((c * 2 + h) * S::KBG + kb) * 8 + q] = col >= 0 ? Wc[c * nin + col] : 0.0f;
+        }
+  for (int c = 0; c < 3; ++c) rgb[48 * S::KBG + c] = cn.b[ci][c];
+  return P;
+}
+
+hipError_t mlp_launch(loc_ctx* c, const MlpArgs& a) {
+  return c->desc.precision == LOC_BF16 ? launch_mlp_bf16(c->kind, a, c->stream) : launch_mlp(c->kind, a, c->stream);
+}
+
 bool same_shape(const loc_map_desc& d, int W, int D, int skip, int lx, int ld, int dw) {
   const int dskip = d.skip_layer >= 1 ? d.skip_layer : -1;
   return d.width == W && d.n_layers == D && dskip == skip && d.L_xyz == lx && d.L_dir == ld &&
@@ -263,7 +347,7 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
   if (!(d->near_ >= 0.0f && d->far_ > d->near_)) return LOC_E_ARG;
   if (d->n_coarse < 1 || d->n_coarse > 256 || d->n_fine < 0 || d->n_fine > 256) return LOC_E_ARG;
   if (!(d->alpha > 0.0f && d->alpha < 0.5f) || !(d->tau > 0.0f)) return LOC_E_ARG;
-  if (d->precision != LOC_FP32) return LOC_E_UNSUPPORTED;
+  if (d->precision != LOC_FP32 && d->precision != LOC_BF16) return LOC_E_UNSUPPORTED;
   int kind;
   long macs, total;
   if (same_shape(*d, 64, 4, -1, 6, 2, 0)) { kind = kMapSmall; macs = SmallMap::macs(); total = SmallMap::TOTAL; }
@@ -279,16 +363,28 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
   c->macs = macs;
   c->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LOC_E_HIP; }
-  std::vector<float> P = kind == kMapSmall ? pack_map<SmallMap>(*d) : pack_map<NerfMap>(*d);
-  if (hipMalloc(&c->weights, sizeof(float) * total) != hipSuccess ||
-      hipMalloc(&c->flags, sizeof(int)) != hipSuccess) {
+  if (hipMalloc(&c->flags, sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     loc_destroy(c);
     return LOC_E_OOM;
   }
-  if (hipMemcpyAsync(c->weights, P.data(), sizeof(float) * total, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) != hipSuccess ||
+  bool ok = true;
+  if (d->precision == LOC_FP32) {
+    std::vector<float> P = kind == kMapSmall ? pack_map<SmallMap>(*d) : pack_map<NerfMap>(*d);
+    ok = hipMalloc(&c->weights, sizeof(float) * total) == hipSuccess &&
+         hipMemcpy(c->weights, P.data(), sizeof(float) * total, hipMemcpyHostToDevice) == hipSuccess;
+  } else {
+    PackedB P = kind == kMapSmall ? pack_map_bf16<SmallMapB>(*d) : pack_map_bf16<NerfMapB>(*d);
+    ok = hipMalloc(&c->wblocks, P.blocks.size() * 2) == hipSuccess &&
+         hipMalloc(&c->bias_b, P.bias.size() * 4) == hipSuccess &&
+         hipMalloc(&c->heads_b, P.heads.size() * 4) == hipSuccess &&
+         hipMemcpy(c->wblocks, P.blocks.data(), P.blocks.size() * 2, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->bias_b, P.bias.data(), P.bias.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->heads_b, P.heads.data(), P.heads.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok || hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
     loc_destroy(c);
     return LOC_E_HIP;
   }
@@ -300,6 +396,9 @@ void loc_destroy(loc_ctx* c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
   hipFree(c->weights);
+  hipFree(c->wblocks);
+  hipFree(c->bias_b);
+  hipFree(c->heads_b);
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
@@ -378,6 +477,9 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   ma.t_out = c->t_c.p;
   ma.out = c->out_c.p;
   ma.weights = c->weights;
+  ma.wblocks = c->wblocks;
+  ma.bias = c->bias_b;
+  ma.heads = c->heads_b;
   ma.n_samples = nr * Sc;
   ma.spr = Sc;
   ma.B = B;
@@ -388,7 +490,7 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   ma.iter = iter;
   const double fl_sample = 2.0 * (double)c->macs;
   if ((s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
-                 [&] { return launch_mlp(c->kind, ma, c->stream); })))
+                 [&] { return mlp_launch(c, ma); })))
     return s;
 
   if (Sf > 0) {
@@ -412,7 +514,7 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
     mf.n_samples = nr * Sf;
     mf.spr = Sf;
     if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
-                   [&] { return launch_mlp(c->kind, mf, c->stream); })))
+                   [&] { return mlp_launch(c, mf); })))
       return s;
   }
 

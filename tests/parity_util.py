@@ -39,6 +39,11 @@ def run_oracle(spec, params, img, cam, inv_R, B, poses, motion=None, sigma_t=0.0
                                 subset=subset)
 
 
+def ctx(spec, params, precision="fp32"):
+    from paper_2406_12202_amd import binding
+    return binding.Context(spec, params, precision=precision)
+
+
 def stats(name, a, b):
     d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).ravel()
     if d.size == 0:

@@ -305,6 +305,27 @@ def test_quantile_special_cases():
     assert abs(rd.uncertainty(zts, zos, tau) - (far - zts)) < 1e-15
 
 
+def test_crossing_densities_and_first_order_conditioning():
+    near, far, S, alpha = 2.0, 6.0, 32, 0.05
+    t = near + np.arange(S) * (far - near) / S
+    _, logT, _, _ = rd.composite(t, np.full(S, 2.0), np.zeros((S, 3)), far)
+    assert rd.crossing_densities(t, np.full(S, 2.0), logT, alpha) == (2.0, 2.0)
+    _, logT0, _, _ = rd.composite(t, np.zeros(S), np.zeros((S, 3)), far)
+    st, so = rd.crossing_densities(t, np.zeros(S), logT0, alpha)
+    assert np.isnan(st) and np.isnan(so)
+    # a relative change eps of every density moves each crossing by |log L| eps / sigma
+    rng = np.random.default_rng(8)
+    sig = rng.exponential(1.5, S)
+    eps = 1e-6
+    _, lA, _, _ = rd.composite(t, sig, np.zeros((S, 3)), far)
+    _, lB, _, _ = rd.composite(t, sig * (1 + eps), np.zeros((S, 3)), far)
+    ztA, zoA = rd.ray_quantiles(t, sig, lA, far, alpha)
+    ztB, zoB = rd.ray_quantiles(t, sig * (1 + eps), lB, far, alpha)
+    st, so = rd.crossing_densities(t, sig, lA, alpha)
+    assert abs(abs(ztB - ztA) - abs(math.log1p(-alpha)) * eps / st) < 1e-3 * abs(ztB - ztA)
+    assert abs(abs(zoB - zoA) - abs(math.log(alpha)) * eps / so) < 1e-3 * abs(zoB - zoA)
+
+
 # ----------------------------------------------------------------------------- fine sampling
 
 def test_sample_pdf_uniform_and_one_bin():
