@@ -17,6 +17,7 @@ import math
 import numpy as np
 
 from . import philox as px
+from . import proposal as pr
 from . import render as rd
 from . import se3
 
@@ -83,14 +84,15 @@ def predict(pose, motion, sigma_t, sigma_r, seed, it, i):
 # ----------------------------------------------------------------------------
 # rendering of one particle's query rays
 
-def render_rays(spec, P, pose, pix, Wl, cam_l, seed, it, i):
-    """Render the query pixels of particle i: returns per-ray colour C (B, 3),
-    opacity A, z_trans, z_opaque and F."""
-    fx, fy, cx, cy = cam_l
-    B = len(pix)
-    rays = [rd.pixel_ray(pose, p % Wl, p // Wl, fx, fy, cx, cy) for p in pix]
-    tc = [coarse_t(spec, seed, it, i, j) for j in range(B)]
-    # coarse map queries for all rays of the particle in one batch
+def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False):
+    """Render rays [(o, d)] whose random streams are keyed by (i, j) = keys[r].
+    Fine samples (n_fine > 0) come from hierarchical sampling on the coarse
+    weights, or, when ``proposal`` (flat proposal parameters) is given, from
+    the proposal network's histogram.  Returns per-ray colour C, opacity A,
+    z_trans, z_opaque, F and the densities at the two crossings."""
+    B = len(rays)
+    tc = [coarse_t(spec, seed, it, i, j) for (i, j) in keys]
+    # coarse map queries for all rays in one batch
     X = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tc)])
     Dd = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tc)])
     sig_c, rgb_c = rd.mlp(spec, P, X, Dd)
@@ -98,42 +100,65 @@ def render_rays(spec, P, pose, pix, Wl, cam_l, seed, it, i):
     far = spec["far"]
     ts, sigs, rgbs = [], [], []
     if spec["n_fine"] > 0:
-        tf = []
-        for j in range(B):
-            s = slice(j * Sc, (j + 1) * Sc)
-            w, _, _, _ = rd.composite(tc[j], sig_c[s], rgb_c[s], far)
-            mass = w + FINE_FLOOR * rd.deltas(tc[j], far)
-            tf.append(rd.sample_pdf(tc[j], mass, far, fine_u(spec, seed, it, i, j)))
+        if proposal is not None:
+            Q = pr.unpack(proposal)
+            O = np.array([o for o, _ in rays])
+            Dr = np.array([d for _, d in rays])
+            hist, _ = pr.forward(Q, pr.features(O, Dr))
+            tf = [pr.place(hist[r], spec["near"], far, fine_u(spec, seed, it, i, j))
+                  for r, (i, j) in enumerate(keys)]
+        else:
+            tf = []
+            for r, (i, j) in enumerate(keys):
+                s = slice(r * Sc, (r + 1) * Sc)
+                w, _, _, _ = rd.composite(tc[r], sig_c[s], rgb_c[s], far)
+                mass = w + FINE_FLOOR * rd.deltas(tc[r], far)
+                tf.append(rd.sample_pdf(tc[r], mass, far, fine_u(spec, seed, it, i, j)))
         Xf = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tf)])
         Df = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tf)])
         sig_f, rgb_f = rd.mlp(spec, P, Xf, Df)
         Sf = spec["n_fine"]
-        for j in range(B):
-            sc, sf = slice(j * Sc, (j + 1) * Sc), slice(j * Sf, (j + 1) * Sf)
-            t_all = np.concatenate([tc[j], tf[j]])
+        for r in range(B):
+            sc, sf = slice(r * Sc, (r + 1) * Sc), slice(r * Sf, (r + 1) * Sf)
+            t_all = np.concatenate([tc[r], tf[r]])
             order = np.argsort(t_all, kind="stable")   # ties: coarse first
             ts.append(t_all[order])
             sigs.append(np.concatenate([sig_c[sc], sig_f[sf]])[order])
             rgbs.append(np.concatenate([rgb_c[sc], rgb_f[sf]])[order])
     else:
-        for j in range(B):
-            s = slice(j * Sc, (j + 1) * Sc)
-            ts.append(tc[j])
+        for r in range(B):
+            s = slice(r * Sc, (r + 1) * Sc)
+            ts.append(tc[r])
             sigs.append(sig_c[s])
             rgbs.append(rgb_c[s])
-    C = np.zeros((B, 3))
-    A = np.zeros(B)
-    zt = np.zeros(B)
-    zo = np.zeros(B)
-    F = np.zeros(B)
-    kt = np.zeros(B)
-    ko = np.zeros(B)
-    for j in range(B):
-        _, logT, C[j], A[j] = rd.composite(ts[j], sigs[j], rgbs[j], far)
-        zt[j], zo[j] = rd.ray_quantiles(ts[j], sigs[j], logT, far, spec["alpha"])
-        F[j] = rd.uncertainty(zt[j], zo[j], spec["tau"])
-        kt[j], ko[j] = rd.crossing_densities(ts[j], sigs[j], logT, spec["alpha"])
-    return {"C": C, "A": A, "z_trans": zt, "z_opaque": zo, "F": F, "sig_trans": kt, "sig_opaque": ko}
+    out = {k: np.zeros(B) for k in ("A", "z_trans", "z_opaque", "F", "sig_trans", "sig_opaque")}
+    out["C"] = np.zeros((B, 3))
+    if keep_samples:
+        out["t"], out["w"] = [], []
+    for r in range(B):
+        w, logT, out["C"][r], out["A"][r] = rd.composite(ts[r], sigs[r], rgbs[r], far)
+        out["z_trans"][r], out["z_opaque"][r] = rd.ray_quantiles(ts[r], sigs[r], logT, far, spec["alpha"])
+        out["F"][r] = rd.uncertainty(out["z_trans"][r], out["z_opaque"][r], spec["tau"])
+        out["sig_trans"][r], out["sig_opaque"][r] = rd.crossing_densities(ts[r], sigs[r], logT, spec["alpha"])
+        if keep_samples:
+            out["t"].append(ts[r])
+            out["w"].append(w)
+    return out
+
+
+def particle_rays(pose, pix, Wl, cam_l):
+    fx, fy, cx, cy = cam_l
+    return [rd.pixel_ray(pose, p % Wl, p // Wl, fx, fy, cx, cy) for p in pix]
+
+
+def teacher_histograms(spec, params, O, D, seed, it):
+    """Proposal training targets for rays (O[r], D[r]) from a full render of
+    the map (streams keyed by (r, 0))."""
+    P = rd.unpack(spec, params)
+    rays = [(np.asarray(o, dtype=np.float64), np.asarray(d, dtype=np.float64)) for o, d in zip(O, D)]
+    r = render_rays(spec, P, rays, [(k, 0) for k in range(len(rays))], seed, it, keep_samples=True)
+    return np.array([pr.teacher_histogram(t, w, spec["near"], spec["far"], A)
+                     for t, w, A in zip(r["t"], r["w"], r["A"])])
 
 
 def score(obs, C, F, B):
@@ -161,13 +186,15 @@ def normalise(loglik):
 
 
 def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
-                     sigma_t=0.0, sigma_r=0.0, seed=0, it=0, subset=None):
+                     sigma_t=0.0, sigma_r=0.0, seed=0, it=0, subset=None, proposal=None):
     """One weighting pass of Alg. 1 over the particles ``subset`` (default all).
 
     spec   : map/renderer settings (see oracle.render); params: flat float32 map
     image  : H x W x 3 observation; cam = (W, H, fx, fy, cx, cy) at full size
     inv_R  : level factor s, R_t = 1/s; intrinsics become R K (Sec. III-C)
     poses  : (N, 3, 4) particle poses x_{t-1}
+    proposal: flat proposal-network parameters: fine samples from its
+           histogram instead of hierarchical sampling
     Returns per-particle predicted poses, log-likelihoods, normalised weights
     (over the subset), mean uncertainty, and per-ray renders."""
     P = rd.unpack(spec, params)
@@ -186,7 +213,8 @@ def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
            "pix": pix, "obs": obs}
     for i in idx:
         x = predict(poses[i], motion, sigma_t, sigma_r, seed, it, i)
-        r = render_rays(spec, P, x, pix, Wl, cam_l, seed, it, i)
+        r = render_rays(spec, P, particle_rays(x, pix, Wl, cam_l), [(i, j) for j in range(B)], seed, it,
+                        proposal=proposal)
         E, S, ll = score(obs, r["C"], r["F"], B)
         out["pose"].append(x)
         out["loglik"].append(ll)
