@@ -107,7 +107,7 @@ typedef struct {
   int L_xyz, L_dir, dir_width;
   const float* params;     /* HOST */
   size_t n_params;
-  loc_precision precision; /* LOC_FP32 now; others return LOC_E_UNSUPPORTED */
+  loc_precision precision; /* LOC_FP32 or LOC_BF16 (bf16 map, float32 accumulate) */
   float near_, far_;
   int n_coarse, n_fine;    /* n_coarse in [1, 256], n_fine in [0, 256] */
   float alpha, tau;        /* 0 < alpha < 0.5, tau > 0 */
@@ -192,6 +192,63 @@ typedef struct {
 } loc_kernel_stat;
 loc_status loc_set_profiling(loc_ctx* ctx, int enable);
 loc_status loc_kernel_stats(loc_ctx* ctx, loc_kernel_stat* out, int max, int* n);
+
+/*
+ * Learned proposal network (an extension of the paper's sampling: it places a
+ * ray's fine samples from a predicted 32-bin histogram of the compositing
+ * weights instead of from a coarse render).
+ *   x = [gamma_6(o), gamma_6(d)] (78), h1 = relu(W1 x + b1) (64),
+ *   h2 = relu(W2 h1 + b2) (64), z = W3 h2 + b3 (32), p = softmax(z);
+ *   parameters: 11296 float32 in the order W1 (64 x 78), b1, W2 (64 x 64), b2,
+ *   W3 (32 x 64), b3, row-major.
+ * Placement: pdf 0.99 p_b + 0.01/32 on 32 equal bins of [near, far), inverse
+ * CDF at u_m = (m + xi'_m) / n_fine (stream 3), merged with the coarse samples.
+ * Training targets: normalised 32-bin histograms of the map's compositing
+ * weights (sample depth t in bin b) from a full hierarchical render; uniform
+ * when the ray's opacity is below 1e-3.  Loss: mean over rays of
+ * sum_b (p_b - h_b)^2; optimiser Adam.
+ */
+#define LOC_PROPOSAL_PARAMS 11296
+
+/* Camera rays of N particles x B query pixels exactly as loc_update_particles
+ * casts them (no prediction step): DEVICE pose N x 12 float64; outputs DEVICE
+ * ray_o, ray_d of N*B*3 float32 (ray i*B + j). */
+loc_status loc_cast_rays(loc_ctx* ctx, const loc_camera* cam, int inv_R, int B, int N, const double* pose,
+                         uint64_t seed, uint64_t iter, float* ray_o, float* ray_d);
+
+/* Training targets for n rays (DEVICE ray_o, ray_d: n*3 float32) from a full
+ * render of the context's map with its n_coarse stratified samples and n_fine
+ * hierarchical samples (0..256); random streams keyed (ray, 0) with
+ * (seed, iter).  hist: DEVICE n*32 float32.  Uses the context's precision. */
+loc_status loc_teacher_histograms(loc_ctx* ctx, const float* ray_o, const float* ray_d, int n, int n_fine,
+                                  uint64_t seed, uint64_t iter, float* hist);
+
+/* Load (HOST, n == LOC_PROPOSAL_PARAMS) proposal parameters; clears the Adam
+ * moments and step.  loc_get_proposal copies them back to HOST memory. */
+loc_status loc_set_proposal(loc_ctx* ctx, const float* params, size_t n);
+loc_status loc_get_proposal(loc_ctx* ctx, float* params, size_t n);
+
+/* Fine-sample placement used by loc_update_particles: 0 = hierarchical on the
+ * coarse weights (default), 1 = learned proposal (needs loc_set_proposal). */
+loc_status loc_set_fine_mode(loc_ctx* ctx, int mode);
+
+/* Proposal histograms p (DEVICE n*32) for n rays (DEVICE n*3 each). */
+loc_status loc_proposal_forward(loc_ctx* ctx, const float* ray_o, const float* ray_d, int n, float* hist);
+
+/* Mean loss (DEVICE 1 float, may be NULL) and its gradient with respect to
+ * the parameters (DEVICE LOC_PROPOSAL_PARAMS floats) over n <= 2^20 rays with
+ * targets (DEVICE n*32).  Deterministic: per-wave partial sums reduced in a
+ * fixed order. */
+loc_status loc_proposal_grad(loc_ctx* ctx, const float* ray_o, const float* ray_d, const float* target, int n,
+                             float* loss_out, float* grad_out);
+
+/* Adam training on the GPU: step k uses the `batch` rays starting at
+ * (k * batch) mod n (cyclic); the Adam step counter continues across calls
+ * until loc_set_proposal.  loss_out: DEVICE `steps` floats (mean batch loss
+ * before each step), or NULL. */
+typedef struct { int batch, steps; float lr, beta1, beta2, eps; } loc_train_cfg;
+loc_status loc_train_proposal(loc_ctx* ctx, const float* ray_o, const float* ray_d, const float* target, int n,
+                              const loc_train_cfg* cfg, float* loss_out);
 
 void loc_destroy(loc_ctx* ctx);
 const char* loc_status_str(loc_status s);     /* static text, never NULL */

@@ -17,7 +17,10 @@ FLAG_DEGENERATE_WEIGHTS, FLAG_DEGENERATE_RESAMPLE = 1, 2
 PRECISIONS = {"fp32": LOC_FP32, "bf16": LOC_BF16, "fp8": LOC_FP8_E4M3}
 
 EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
-           "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error"]
+           "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error",
+           "loc_cast_rays", "loc_teacher_histograms", "loc_set_proposal", "loc_get_proposal",
+           "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal"]
+PROPOSAL_PARAMS = 11296
 
 
 class MapDesc(ctypes.Structure):
@@ -37,6 +40,11 @@ class Camera(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
                 ("flop", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("steps", ctypes.c_int), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class LocError(RuntimeError):
@@ -71,8 +79,18 @@ def load(path=LIB_PATH):
     lib.loc_status_str.restype = ctypes.c_char_p
     lib.loc_last_error.argtypes = [vp]
     lib.loc_last_error.restype = ctypes.c_char_p
+    lib.loc_cast_rays.argtypes = [vp, ctypes.POINTER(Camera), c_int, c_int, c_int, vp, c_u64, c_u64, vp, vp]
+    lib.loc_teacher_histograms.argtypes = [vp, vp, vp, c_int, c_int, c_u64, c_u64, vp]
+    lib.loc_set_proposal.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.loc_get_proposal.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.loc_set_fine_mode.argtypes = [vp, c_int]
+    lib.loc_proposal_forward.argtypes = [vp, vp, vp, c_int, vp]
+    lib.loc_proposal_grad.argtypes = [vp, vp, vp, vp, c_int, vp, vp]
+    lib.loc_train_proposal.argtypes = [vp, vp, vp, vp, c_int, ctypes.POINTER(TrainCfg), vp]
     for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
-              "loc_set_profiling", "loc_kernel_stats"):
+              "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
+              "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
+              "loc_proposal_grad", "loc_train_proposal"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -205,3 +223,77 @@ class Context:
         self._check(self.lib.loc_kernel_stats(self.h, arr, 32, ctypes.byref(n)), "loc_kernel_stats")
         return {arr[k].name.decode(): dict(launches=arr[k].launches, ms=arr[k].ms, flop=arr[k].flop,
                                            bytes=arr[k].bytes) for k in range(min(n.value, 32))}
+
+    # ------------------------------------------------------------------ proposal
+
+    def loc_cast_rays(self, cam, inv_R, B, pose, seed=0, iter=0):
+        """Rays (o, d) as (N*B, 3) float32 device tensors, cast as in loc_update_particles."""
+        import torch
+        N = pose.shape[0]
+        o = torch.empty((N * B, 3), dtype=torch.float32, device=pose.device)
+        d = torch.empty((N * B, 3), dtype=torch.float32, device=pose.device)
+        W, H, fx, fy, cx, cy = cam
+        c = Camera(W=int(W), H=int(H), fx=fx, fy=fy, cx=cx, cy=cy)
+        self._check(self.lib.loc_cast_rays(self.h, ctypes.byref(c), int(inv_R), int(B), int(N),
+                                           _ptr(pose, torch.float64, N * 12, "pose"), int(seed), int(iter),
+                                           _ptr(o, torch.float32, N * B * 3, "ray_o"),
+                                           _ptr(d, torch.float32, N * B * 3, "ray_d")), "loc_cast_rays")
+        return o, d
+
+    def loc_teacher_histograms(self, ray_o, ray_d, n_fine, seed=0, iter=0):
+        import torch
+        n = ray_o.shape[0]
+        hist = torch.empty((n, 32), dtype=torch.float32, device=ray_o.device)
+        self._check(self.lib.loc_teacher_histograms(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                                    _ptr(ray_d, torch.float32, n * 3, "ray_d"), int(n), int(n_fine),
+                                                    int(seed), int(iter), _ptr(hist, torch.float32, n * 32, "hist")),
+                    "loc_teacher_histograms")
+        return hist
+
+    def loc_set_proposal(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.loc_set_proposal(self.h, ctypes.c_void_p(p.ctypes.data), p.size), "loc_set_proposal")
+
+    def loc_get_proposal(self):
+        import numpy as np
+        p = np.empty(PROPOSAL_PARAMS, dtype=np.float32)
+        self._check(self.lib.loc_get_proposal(self.h, ctypes.c_void_p(p.ctypes.data), p.size), "loc_get_proposal")
+        return p
+
+    def loc_set_fine_mode(self, mode):
+        self._check(self.lib.loc_set_fine_mode(self.h, int(mode)), "loc_set_fine_mode")
+
+    def loc_proposal_forward(self, ray_o, ray_d):
+        import torch
+        n = ray_o.shape[0]
+        hist = torch.empty((n, 32), dtype=torch.float32, device=ray_o.device)
+        self._check(self.lib.loc_proposal_forward(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                                  _ptr(ray_d, torch.float32, n * 3, "ray_d"), int(n),
+                                                  _ptr(hist, torch.float32, n * 32, "hist")), "loc_proposal_forward")
+        return hist
+
+    def loc_proposal_grad(self, ray_o, ray_d, target):
+        import torch
+        n = ray_o.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=ray_o.device)
+        grad = torch.empty(PROPOSAL_PARAMS, dtype=torch.float32, device=ray_o.device)
+        self._check(self.lib.loc_proposal_grad(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                               _ptr(ray_d, torch.float32, n * 3, "ray_d"),
+                                               _ptr(target, torch.float32, n * 32, "target"), int(n),
+                                               _ptr(loss, torch.float32, 1, "loss"),
+                                               _ptr(grad, torch.float32, PROPOSAL_PARAMS, "grad")),
+                    "loc_proposal_grad")
+        return loss, grad
+
+    def loc_train_proposal(self, ray_o, ray_d, target, batch, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        n = ray_o.shape[0]
+        losses = torch.empty(max(steps, 1), dtype=torch.float32, device=ray_o.device)
+        cfg = TrainCfg(batch=int(batch), steps=int(steps), lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        self._check(self.lib.loc_train_proposal(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                                _ptr(ray_d, torch.float32, n * 3, "ray_d"),
+                                                _ptr(target, torch.float32, n * 32, "target"), int(n),
+                                                ctypes.byref(cfg), _ptr(losses, torch.float32, losses.numel(), "loss")),
+                    "loc_train_proposal")
+        return losses[:steps]

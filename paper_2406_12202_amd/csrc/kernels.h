@@ -75,10 +75,49 @@ struct CompositeArgs {
   float far_, log_trans, log_opq, tau;   // log(1 - alpha), log(alpha)
   float4* ray_rgba;        // per ray (C, A)
   float2* ray_fe;          // per ray (F, E)
-  double* loglik;          // per particle
+  double* loglik;          // per particle, or NULL (teacher mode)
   float* uncert;           // per particle mean F, may be NULL
+  float* hist;             // per ray 32-bin weight histogram (teacher targets), or NULL
+  int n_rays;              // rays present (N * B, or fewer in teacher mode)
+  float near_;
 };
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t st);
+
+constexpr int kProposalParams = 64 * 78 + 64 + 64 * 64 + 64 + 32 * 64 + 32;   // 11296
+
+struct ProposalArgs {
+  const float4* ray_o;
+  const float4* ray_d;
+  const float* params;     // flat proposal parameters (device)
+  float* hist;             // per ray 32 probabilities, or NULL
+  float* t_fine;           // per ray Sf fine depths (when Sf > 0)
+  int n_rays, Sf, B;
+  float near_, far_;
+  int jitter;
+  uint64_t seed, iter;
+};
+hipError_t launch_proposal_fine(const ProposalArgs& a, hipStream_t st);
+
+struct TrainArgs {
+  const float4* ray_o;
+  const float4* ray_d;
+  const float* target;     // per ray 32
+  const float* params;     // read by the gradient kernel
+  float* params_rw;        // Adam update target (same buffer), or NULL
+  float* m;
+  float* v;
+  float* partial;          // n_waves x kProposalParams
+  float* loss_partial;     // n_waves
+  float* loss_out;         // mean loss per call at loss_index, or NULL
+  float* grad_out;         // summed gradient, or NULL
+  int loss_index;
+  int n_rays, first, batch, rays_per_wave, n_waves;
+  int adam, step;
+  float lr, beta1, beta2, eps;
+};
+hipError_t launch_prop_grad(const TrainArgs& a, hipStream_t st);
+hipError_t launch_rays_to_f4(const float* o3, const float* d3, int n, float4* o4, float4* d4, hipStream_t st);
+hipError_t launch_rays_from_f4(const float4* o4, const float4* d4, int n, float* o3, float* d3, hipStream_t st);
 
 hipError_t launch_normalize(const double* loglik, double* weight, int N, int* flags, hipStream_t st);
 

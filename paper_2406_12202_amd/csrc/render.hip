@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void k_raygen(const RaygenArgs a) {
   d0 *= inv; d1 *= inv; d2 *= inv;
   a.ray_o[r] = make_float4((float)P[3], (float)P[7], (float)P[11], 0.0f);
   a.ray_d[r] = make_float4((float)d0, (float)d1, (float)d2, 0.0f);
+  if (!a.image) return;
   // downscale(I_t, R_t): mean of the s x s block behind level pixel (u, v)
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   for (int yy = 0; yy < a.s; ++yy) {
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
   // every wave runs the same number of rounds so that block barriers match
   for (int jb = 0; jb < a.B; jb += kCompWaves) {
     const int j = jb + wv;
-    const bool act = j < a.B;
+    const bool act = j < a.B && (long)i * a.B + j < a.n_rays;
     const long ray = (long)i * a.B + (act ? j : 0);
     // gather and merge
     if (act) {
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
       }
     }
     const float incl = wave_incl_scan(lsum, lane);
+    const float log_t_end = -__shfl(incl, 63, 64);
     float run = -(incl - lsum);
     float cr = 0.0f, cg = 0.0f, cb = 0.0f, acc = 0.0f;
     int ktr = 1 << 30, kop = 1 << 30;
@@ -219,6 +221,25 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
     ktr = wave_min_int(ktr);
     kop = wave_min_int(kop);
     __syncthreads();
+    if (a.hist && act && lane < 32) {
+      // teacher histogram: bin b collects the weights of samples with depth in
+      // [e_b, e_{b+1}); they are consecutive in the sorted list, and their sum
+      // telescopes to T(first in bin) - T(first in next bin)
+      const float width = (a.far_ - a.near_) / 32.0f;
+      int kb[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float edge = a.near_ + (float)(lane + e) * width;
+        int lo = 0, hi = S;                // first merged index with t >= edge
+        if (lane + e == 32) lo = S;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tm[wv][mid] < edge) lo = mid + 1; else hi = mid; }
+        kb[e] = lo;
+      }
+      const float t0 = kb[0] < S ? expf(s_lt[wv][kb[0]]) : expf(log_t_end);
+      const float t1 = kb[1] < S ? expf(s_lt[wv][kb[1]]) : expf(log_t_end);
+      const float den = -expm1f(log_t_end);
+      a.hist[ray * 32 + lane] = acc < 1e-3f ? 1.0f / 32.0f : (t0 - t1) / den;
+    }
     if (act && lane == 0) {
       float F = a.tau;
       if (ktr < S) {
@@ -226,9 +247,12 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
         const float zo = (kop < S) ? s_tm[wv][kop] + (s_lt[wv][kop] - a.log_opq) / s_sg[wv][kop] : a.far_;
         F = fmaxf(zo - zt, a.tau);
       }
-      const float4 ob = a.obs[ray];
-      const float er = ob.x - cr, eg = ob.y - cg, eb = ob.z - cb;
-      const float E = er * er + eg * eg + eb * eb;
+      float E = 0.0f;
+      if (a.obs) {
+        const float4 ob = a.obs[ray];
+        const float er = ob.x - cr, eg = ob.y - cg, eb = ob.z - cb;
+        E = er * er + eg * eg + eb * eb;
+      }
       a.ray_rgba[ray] = make_float4(cr, cg, cb, acc);
       a.ray_fe[ray] = make_float2(F, E);
       s_ef[j] = E * F;
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && a.loglik) {
     double S_i = 0.0, Fs = 0.0;
     for (int j = 0; j < a.B; ++j) { S_i += (double)s_ef[j]; Fs += (double)s_f[j]; }
     const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN

@@ -20,10 +20,11 @@ using namespace fl;
 
 namespace {
 
-enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
-                K_RESAMPLE, K_SPLIT, K_COUNT };
-const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "mlp_fine",
-                                     "composite_score", "normalize", "resample", "ray_outputs"};
+enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
+                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_COUNT };
+const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
+                                     "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
+                                     "ray_format", "teacher_histogram", "proposal_train"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -50,6 +51,14 @@ struct loc_ctx {
   DevBuf<float2> fe;
   DevBuf<float> t_c, t_f;
   DevBuf<unsigned long long> prefix;
+  // learned proposal
+  float* prop = nullptr;          // parameters
+  float* prop_m = nullptr;        // Adam moments
+  float* prop_v = nullptr;
+  int prop_step = 0;
+  int fine_mode = 0;              // 0 hierarchical, 1 proposal
+  DevBuf<float> prop_partial, prop_loss;
+  DevBuf<float4> tr_o, tr_d;      // rays of teacher / training calls
   int* flags = nullptr;
   int last_N = 0, last_B = 0;
   // profiling
@@ -402,6 +411,8 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
+  hipFree(c->prop); hipFree(c->prop_m); hipFree(c->prop_v); hipFree(c->prop_partial.p); hipFree(c->prop_loss.p);
+  hipFree(c->tr_o.p); hipFree(c->tr_d.p);
   for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
   for (auto e : c->free_events) hipEventDestroy(e);
   delete c;
@@ -416,6 +427,7 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   if (!image || !cam || !pose_in || !pose_out || !loglik_out || !weight_out)
     return fail(c, LOC_E_ARG, "null pointer argument");
   if (inv_R != 1 && inv_R != 2 && inv_R != 4 && inv_R != 8) return fail(c, LOC_E_ARG, "inv_R must be 1, 2, 4 or 8");
+  if (c->fine_mode == 1 && !c->prop) return fail(c, LOC_E_STATE, "proposal mode without proposal parameters");
   if (cam->W <= 0 || cam->H <= 0 || cam->W % inv_R || cam->H % inv_R)
     return fail(c, LOC_E_ARG, "image %dx%d not divisible by level factor %d", cam->W, cam->H, inv_R);
   if (!(cam->fx > 0 && cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
@@ -493,6 +505,25 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
                  [&] { return mlp_launch(c, ma); })))
     return s;
 
+  if (Sf > 0 && c->fine_mode == 1) {
+    ProposalArgs pa2{};
+    pa2.ray_o = c->ray_o.p;
+    pa2.ray_d = c->ray_d.p;
+    pa2.params = c->prop;
+    pa2.hist = nullptr;
+    pa2.t_fine = c->t_f.p;
+    pa2.n_rays = (int)nr;
+    pa2.Sf = Sf;
+    pa2.B = B;
+    pa2.near_ = d.near_;
+    pa2.far_ = d.far_;
+    pa2.jitter = d.jitter;
+    pa2.seed = seed;
+    pa2.iter = iter;
+    if ((s = timed(c, K_PROPOSAL, 2.0 * 11136.0 * nr, 40.0 * nr + 4.0 * nr * Sf,
+                   [&] { return launch_proposal_fine(pa2, c->stream); })))
+      return s;
+  }
   if (Sf > 0) {
     FineArgs fa{};
     fa.t_coarse = c->t_c.p;
@@ -506,7 +537,9 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
     fa.jitter = d.jitter;
     fa.seed = seed;
     fa.iter = iter;
-    if ((s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); }))) return s;
+    if (c->fine_mode == 0 &&
+        (s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); })))
+      return s;
     MlpArgs mf = ma;
     mf.t_in = c->t_f.p;
     mf.t_out = nullptr;
@@ -536,6 +569,9 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   ca.ray_fe = c->fe.p;
   ca.loglik = loglik_out;
   ca.uncert = uncert_out;
+  ca.hist = nullptr;
+  ca.n_rays = (int)nr;
+  ca.near_ = d.near_;
   if ((s = timed(c, K_COMPOSITE, 0, nr * (20.0 * (Sc + Sf) + 16.0 + 24.0) + 12.0 * N,
                  [&] { return launch_composite(ca, c->stream); })))
     return s;
@@ -619,6 +655,270 @@ loc_status loc_kernel_stats(loc_ctx* c, loc_kernel_stat* out, int max, int* n) {
     ++k_out;
   }
   if (n) *n = k_out;
+  return LOC_OK;
+}
+
+
+loc_status loc_cast_rays(loc_ctx* c, const loc_camera* cam, int inv_R, int B, int N, const double* pose,
+                         uint64_t seed, uint64_t iter, float* ray_o, float* ray_d) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!cam || !pose || !ray_o || !ray_d) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (inv_R != 1 && inv_R != 2 && inv_R != 4 && inv_R != 8) return fail(c, LOC_E_ARG, "inv_R must be 1, 2, 4 or 8");
+  if (cam->W <= 0 || cam->H <= 0 || cam->W % inv_R || cam->H % inv_R || !(cam->fx > 0 && cam->fy > 0))
+    return fail(c, LOC_E_ARG, "invalid camera for level factor %d", inv_R);
+  if (B < 1 || B > 1024 || N < 1 || (long)N * B > (1L << 30) / 256) return fail(c, LOC_E_ARG, "N or B out of range");
+  const long nr = (long)N * B;
+  loc_status s;
+  if ((s = ensure(c, c->tr_o, nr)) || (s = ensure(c, c->tr_d, nr))) return s;
+  RaygenArgs ra{};
+  ra.pose = pose;
+  ra.image = nullptr;
+  ra.W_full = cam->W;
+  ra.s = inv_R;
+  ra.Wl = cam->W / inv_R;
+  ra.Hl = cam->H / inv_R;
+  ra.fx = cam->fx / inv_R;
+  ra.fy = cam->fy / inv_R;
+  ra.cx = cam->cx / inv_R;
+  ra.cy = cam->cy / inv_R;
+  ra.N = N;
+  ra.B = B;
+  ra.seed = seed;
+  ra.iter = iter;
+  ra.ray_o = c->tr_o.p;
+  ra.ray_d = c->tr_d.p;
+  ra.obs = nullptr;
+  if ((s = timed(c, K_RAYGEN, 0, 32.0 * nr + 96.0 * N, [&] { return launch_raygen(ra, c->stream); }))) return s;
+  return timed(c, K_RAYS, 0, 56.0 * nr,
+               [&] { return launch_rays_from_f4(c->tr_o.p, c->tr_d.p, (int)nr, ray_o, ray_d, c->stream); });
+}
+
+loc_status loc_teacher_histograms(loc_ctx* c, const float* ray_o, const float* ray_d, int n, int n_fine,
+                                  uint64_t seed, uint64_t iter, float* hist) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !hist) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 24)) return fail(c, LOC_E_ARG, "n out of range");
+  if (n_fine < 0 || n_fine > 256) return fail(c, LOC_E_ARG, "n_fine must be in [0, 256]");
+  const loc_map_desc& d = c->desc;
+  const int Sc = d.n_coarse, Sf = n_fine;
+  loc_status s;
+  if ((s = ensure(c, c->ray_o, n)) || (s = ensure(c, c->ray_d, n)) || (s = ensure(c, c->t_c, (size_t)n * Sc)) ||
+      (s = ensure(c, c->out_c, (size_t)n * Sc)) || (s = ensure(c, c->rgba, n)) || (s = ensure(c, c->fe, n)))
+    return s;
+  if (Sf > 0 && ((s = ensure(c, c->t_f, (size_t)n * Sf)) || (s = ensure(c, c->out_f, (size_t)n * Sf)))) return s;
+  if ((s = timed(c, K_RAYS, 0, 56.0 * n,
+                 [&] { return launch_rays_to_f4(ray_o, ray_d, n, c->ray_o.p, c->ray_d.p, c->stream); })))
+    return s;
+  MlpArgs ma{};
+  ma.ray_o = c->ray_o.p;
+  ma.ray_d = c->ray_d.p;
+  ma.t_out = c->t_c.p;
+  ma.out = c->out_c.p;
+  ma.weights = c->weights;
+  ma.wblocks = c->wblocks;
+  ma.bias = c->bias_b;
+  ma.heads = c->heads_b;
+  ma.n_samples = (long)n * Sc;
+  ma.spr = Sc;
+  ma.B = 1;                      // streams keyed (ray, 0)
+  ma.near_ = d.near_;
+  ma.dt = (d.far_ - d.near_) / (float)Sc;
+  ma.jitter = d.jitter;
+  ma.seed = seed;
+  ma.iter = iter;
+  const double fl_sample = 2.0 * (double)c->macs;
+  if ((s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples, [&] { return mlp_launch(c, ma); })))
+    return s;
+  if (Sf > 0) {
+    FineArgs fa{};
+    fa.t_coarse = c->t_c.p;
+    fa.out_coarse = c->out_c.p;
+    fa.t_fine = c->t_f.p;
+    fa.n_rays = n;
+    fa.Sc = Sc;
+    fa.Sf = Sf;
+    fa.B = 1;
+    fa.far_ = d.far_;
+    fa.jitter = d.jitter;
+    fa.seed = seed;
+    fa.iter = iter;
+    if ((s = timed(c, K_FINE, 0, (double)n * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); })))
+      return s;
+    MlpArgs mf = ma;
+    mf.t_in = c->t_f.p;
+    mf.t_out = nullptr;
+    mf.out = c->out_f.p;
+    mf.n_samples = (long)n * Sf;
+    mf.spr = Sf;
+    if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples, [&] { return mlp_launch(c, mf); })))
+      return s;
+  }
+  CompositeArgs ca{};
+  ca.t_coarse = c->t_c.p;
+  ca.out_coarse = c->out_c.p;
+  ca.t_fine = Sf > 0 ? c->t_f.p : nullptr;
+  ca.out_fine = Sf > 0 ? c->out_f.p : nullptr;
+  ca.obs = nullptr;
+  ca.N = (n + 3) / 4;
+  ca.B = 4;
+  ca.Sc = Sc;
+  ca.Sf = Sf;
+  ca.far_ = d.far_;
+  ca.log_trans = (float)std::log1p(-(double)d.alpha);
+  ca.log_opq = (float)std::log((double)d.alpha);
+  ca.tau = d.tau;
+  ca.ray_rgba = c->rgba.p;
+  ca.ray_fe = c->fe.p;
+  ca.loglik = nullptr;
+  ca.uncert = nullptr;
+  ca.hist = hist;
+  ca.n_rays = n;
+  ca.near_ = d.near_;
+  return timed(c, K_TEACHER, 0, (double)n * (20.0 * (Sc + Sf) + 128.0),
+               [&] { return launch_composite(ca, c->stream); });
+}
+
+loc_status loc_set_proposal(loc_ctx* c, const float* params, size_t n) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!params || n != (size_t)kProposalParams)
+    return fail(c, LOC_E_ARG, "proposal parameters: expected %d floats", kProposalParams);
+  if (!c->prop) {
+    if (hipMalloc(&c->prop, 4 * kProposalParams) != hipSuccess || hipMalloc(&c->prop_m, 4 * kProposalParams) != hipSuccess ||
+        hipMalloc(&c->prop_v, 4 * kProposalParams) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, LOC_E_OOM, "proposal allocation failed");
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->prop, params, 4 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->prop_m, 0, 4 * n, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->prop_v, 0, 4 * n, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->prop_step = 0;
+  return LOC_OK;
+}
+
+loc_status loc_get_proposal(loc_ctx* c, float* params, size_t n) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!params || n != (size_t)kProposalParams)
+    return fail(c, LOC_E_ARG, "proposal parameters: expected %d floats", kProposalParams);
+  if (!c->prop) return fail(c, LOC_E_STATE, "no proposal parameters set");
+  HIP_TRY(c, hipMemcpyAsync(params, c->prop, 4 * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LOC_OK;
+}
+
+loc_status loc_set_fine_mode(loc_ctx* c, int mode) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (mode != 0 && mode != 1) return fail(c, LOC_E_ARG, "fine mode must be 0 (hierarchical) or 1 (proposal)");
+  if (mode == 1 && !c->prop) return fail(c, LOC_E_STATE, "no proposal parameters set");
+  c->fine_mode = mode;
+  return LOC_OK;
+}
+
+loc_status loc_proposal_forward(loc_ctx* c, const float* ray_o, const float* ray_d, int n, float* hist) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !hist) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 24)) return fail(c, LOC_E_ARG, "n out of range");
+  if (!c->prop) return fail(c, LOC_E_STATE, "no proposal parameters set");
+  loc_status s;
+  if ((s = ensure(c, c->tr_o, n)) || (s = ensure(c, c->tr_d, n))) return s;
+  if ((s = timed(c, K_RAYS, 0, 56.0 * n,
+                 [&] { return launch_rays_to_f4(ray_o, ray_d, n, c->tr_o.p, c->tr_d.p, c->stream); })))
+    return s;
+  ProposalArgs pa{};
+  pa.ray_o = c->tr_o.p;
+  pa.ray_d = c->tr_d.p;
+  pa.params = c->prop;
+  pa.hist = hist;
+  pa.n_rays = n;
+  pa.Sf = 0;
+  pa.B = 1;
+  return timed(c, K_PROPOSAL, 2.0 * 11136.0 * n, 160.0 * n, [&] { return launch_proposal_fine(pa, c->stream); });
+}
+
+namespace {
+constexpr int kRaysPerWave = 32;
+
+loc_status prop_prepare(loc_ctx* c, const float* ray_o, const float* ray_d, int n, int batch, TrainArgs& ta) {
+  loc_status s;
+  const int n_waves = (batch + kRaysPerWave - 1) / kRaysPerWave;
+  if ((s = ensure(c, c->tr_o, n)) || (s = ensure(c, c->tr_d, n)) ||
+      (s = ensure(c, c->prop_partial, (size_t)n_waves * kProposalParams)) || (s = ensure(c, c->prop_loss, n_waves)))
+    return s;
+  if ((s = timed(c, K_RAYS, 0, 56.0 * n,
+                 [&] { return launch_rays_to_f4(ray_o, ray_d, n, c->tr_o.p, c->tr_d.p, c->stream); })))
+    return s;
+  ta = TrainArgs{};
+  ta.ray_o = c->tr_o.p;
+  ta.ray_d = c->tr_d.p;
+  ta.params = c->prop;
+  ta.partial = c->prop_partial.p;
+  ta.loss_partial = c->prop_loss.p;
+  ta.n_rays = n;
+  ta.batch = batch;
+  ta.rays_per_wave = kRaysPerWave;
+  ta.n_waves = n_waves;
+  return LOC_OK;
+}
+}  // namespace
+
+loc_status loc_proposal_grad(loc_ctx* c, const float* ray_o, const float* ray_d, const float* target, int n,
+                             float* loss_out, float* grad_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !target || !grad_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 20)) return fail(c, LOC_E_ARG, "n must be in [1, 2^20]");
+  if (!c->prop) return fail(c, LOC_E_STATE, "no proposal parameters set");
+  TrainArgs ta;
+  loc_status s;
+  if ((s = prop_prepare(c, ray_o, ray_d, n, n, ta))) return s;
+  ta.target = target;
+  ta.first = 0;
+  ta.loss_out = loss_out;
+  ta.loss_index = 0;
+  ta.grad_out = grad_out;
+  ta.adam = 0;
+  return timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * n, 0.0, [&] { return launch_prop_grad(ta, c->stream); });
+}
+
+loc_status loc_train_proposal(loc_ctx* c, const float* ray_o, const float* ray_d, const float* target, int n,
+                              const loc_train_cfg* cfg, float* loss_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !target || !cfg) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 24)) return fail(c, LOC_E_ARG, "n out of range");
+  if (cfg->batch < 1 || cfg->batch > (1 << 20) || cfg->steps < 0) return fail(c, LOC_E_ARG, "batch or steps out of range");
+  if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f))
+    return fail(c, LOC_E_ARG, "invalid Adam hyperparameters");
+  if (!c->prop) return fail(c, LOC_E_STATE, "no proposal parameters set");
+  TrainArgs ta;
+  loc_status s;
+  if ((s = prop_prepare(c, ray_o, ray_d, n, cfg->batch, ta))) return s;
+  ta.target = target;
+  ta.params_rw = c->prop;
+  ta.m = c->prop_m;
+  ta.v = c->prop_v;
+  ta.loss_out = loss_out;
+  ta.grad_out = nullptr;
+  ta.adam = 1;
+  ta.lr = cfg->lr;
+  ta.beta1 = cfg->beta1;
+  ta.beta2 = cfg->beta2;
+  ta.eps = cfg->eps;
+  for (int k = 0; k < cfg->steps; ++k) {
+    ta.first = (int)(((long)k * cfg->batch) % n);
+    ta.loss_index = k;
+    ta.step = ++c->prop_step;
+    if ((s = timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * cfg->batch, 0.0, [&] { return launch_prop_grad(ta, c->stream); })))
+      return s;
+  }
   return LOC_OK;
 }
 

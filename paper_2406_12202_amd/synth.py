@@ -79,14 +79,25 @@ def _shapes(s):
 DENSITY_INIT = {64: (10.0, 5.0), 256: (16.0, 12.0)}
 
 
-def map_params(s, seed, sigma_bias=None, band_decay=0.5, sigma_gain=None):
+# embedded solid: the density pre-activation gains gain * relu(radius - |x|_1)
+SOLID = dict(gain=20.0, radius=1.5)
+
+
+def map_params(s, seed, sigma_bias=None, band_decay=0.5, sigma_gain=None, solid=True):
     """Seeded random-init map parameters (float32, flat).
 
     Hidden weights are He-scaled N(0, 2/fan_in) with zero biases; the columns
     of the first layer (and of the skip input) that read the frequency-l
     encoding terms are scaled by band_decay**l so that the density field has
     both empty and opaque stretches instead of uniform fog; the density output
-    weights are multiplied by sigma_gain and get bias sigma_bias."""
+    weights are multiplied by sigma_gain and get bias sigma_bias.
+
+    With ``solid`` (the default) the map also holds an opaque octahedron
+    |x|_1 < 1.5 inside the random field: hidden units 0..5 of the first layer
+    compute relu(+-x_c), unit 6 of the second layer computes
+    relu(1.5 - sum of them) and passes through every later layer unchanged,
+    and the density head adds 20 times it, so rays that reach the solid see a
+    surface whose depth varies smoothly with the ray."""
     g0, b0 = DENSITY_INIT.get(s["width"], (1.0, 0.0))
     sigma_gain = g0 if sigma_gain is None else sigma_gain
     sigma_bias = b0 if sigma_bias is None else sigma_bias
@@ -108,6 +119,20 @@ def map_params(s, seed, sigma_bias=None, band_decay=0.5, sigma_gain=None):
         if n == s["n_layers"]:          # sigma head
             W = W * sigma_gain
             b[:] = sigma_bias
+        if solid:
+            if n == 0:                  # units 0..5: relu(+x_c), relu(-x_c)
+                W[:6, :] = 0.0
+                for u in range(6):
+                    W[u, u // 2] = 1.0 if u % 2 == 0 else -1.0
+            elif n == 1:                # unit 6: relu(radius - |x|_1)
+                W[6, :] = 0.0
+                W[6, :6] = -1.0
+                b[6] = SOLID["radius"]
+            elif n < s["n_layers"]:     # unit 6 passes through
+                W[6, :] = 0.0
+                W[6, 6] = 1.0
+            elif n == s["n_layers"]:    # density head
+                W[0, 6] = SOLID["gain"]
         parts += [W.ravel(), b]
     return np.concatenate(parts).astype(np.float32)
 
@@ -215,3 +240,26 @@ def observation(workload, seed, noise=0.01):
 def add_noise(img, seed, noise=0.01):
     rng = np.random.default_rng([seed, 4])
     return (np.asarray(img, dtype=np.float64) + noise * rng.standard_normal(np.shape(img))).astype(np.float32)
+
+
+def proposal_params(seed):
+    """Seeded He-scaled initial parameters of the 78 -> 64 -> 64 -> 32 proposal
+    network (flat float32: W1, b1, W2, b2, W3, b3), zero biases."""
+    rng = np.random.default_rng([seed, 5])
+    parts = []
+    for o, i in ((64, 78), (64, 64), (32, 64)):
+        parts += [rng.standard_normal((o, i)).ravel() * math.sqrt(2.0 / i), np.zeros(o)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def training_poses(workload, seed, n):
+    """Poses for proposal training rays: the workload's particle distribution
+    under a separate seed."""
+    return particles(workload, seed + 7919, N=n)
+
+
+def random_histograms(seed, n, bins=32):
+    """Seeded random target histograms (rows sum to 1)."""
+    rng = np.random.default_rng([seed, 6])
+    h = rng.random((n, bins)) ** 4
+    return (h / h.sum(1, keepdims=True)).astype(np.float32)

@@ -34,9 +34,9 @@ def run_gpu(ctx, img, cam, inv_R, B, poses, motion=None, sigma_t=0.0, sigma_r=0.
 
 
 def run_oracle(spec, params, img, cam, inv_R, B, poses, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0, it=0,
-               subset=None):
+               subset=None, proposal=None):
     return mcl.update_particles(spec, params, img, cam, inv_R, B, poses, motion, sigma_t, sigma_r, seed, it,
-                                subset=subset)
+                                subset=subset, proposal=proposal)
 
 
 def ctx(spec, params, precision="fp32"):
