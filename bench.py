@@ -2,18 +2,26 @@
 """Throughput of the Fast Loc-NeRF particle update on one MI355X.
 
 A step is one pass of the whole hot path over one batch: loc_update_particles
-(prediction, rays, stratified + hierarchical samples, posenc + MLP,
-compositing with the uncertainty F, Eq. 6 score, normalisation) followed by
-loc_resample (systematic, integer-exact).  Inputs are resident in HBM before
-the timed region.  Default workload: the NeRF-sized plain FP32 configuration
-(8x256 map, 400 particles x 64 rays x (64 + 128) samples).
+(prediction, rays, stratified + fine samples, posenc + MLP, compositing with
+the uncertainty F, Eq. 6 score, normalisation) followed by loc_resample
+(systematic, integer-exact).  Inputs are resident in HBM before the timed
+region.
 
-Prints one JSON line.  Per-kernel durations come from HIP events that the
-library records on its own stream around every launch during the timed steps.
+Default: the headline comparison on the NeRF-sized workload (8x256 map,
+400 particles x 64 rays, identical seeded particles, pixels and jitter):
+  * plain FP32 path, 64 coarse + 128 hierarchical samples per ray;
+  * BF16 map + learned proposal, 64 coarse + 32 proposal-placed samples (the
+    proposal is trained beforehand, untimed, on 2M rays whose targets the
+    map renders itself).
+`value` is the BF16+proposal path's MLP samples/s; the FP32 path's numbers
+and the speedups (particle updates/s, i.e. effective samples/s at 192
+samples per ray) sit beside it.
+
+Per-kernel durations come from HIP events that the library records on its own
+stream around every launch during the timed steps.  Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -24,8 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLP samples/s & particle updates/s, BF16+proposal vs plain FP32, 1 GPU"
-PEAK = {"f32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s"), "fp8": (5000.0, "TFLOP/s")}
-HBM_PEAK = 8000.0   # GB/s
+PEAK = {"fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}
+DTYPE = {"fp32": "f32", "bf16": "bf16"}
 
 
 def parse():
@@ -33,16 +41,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="headline", choices=["headline", "single"],
+                    help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision)")
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--train-poses", type=int, default=31250, help="proposal training poses (x 64 rays)")
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-particles", type=int, default=0,
-                    help="particles of the oracle sample (default: sized to ~15 s)")
+    ap.add_argument("--cpu-particles", type=int, default=0)
     return ap.parse_args()
 
 
-def cpu_baseline(workload, spec, params, img, cam, B, poses, seed, n_particles):
+def cpu_baseline(spec, params, img, cam, B, poses, seed, n_particles):
     """The FP64 oracle, as it stands, timed on a bounded sample of the same
     workload; scaled to MLP samples/s."""
     from oracle import mcl
@@ -51,14 +62,78 @@ def cpu_baseline(workload, spec, params, img, cam, B, poses, seed, n_particles):
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:
         threads = 1
-    sub = list(range(n_particles))
     t0 = time.perf_counter()
-    mcl.update_particles(spec, params, img, cam, 1, B, poses, seed=seed, it=0, subset=sub)
+    mcl.update_particles(spec, params, img, cam, 1, B, poses, seed=seed, it=0, subset=list(range(n_particles)))
     dt = time.perf_counter() - t0
     samples = n_particles * B * (spec["n_coarse"] + spec["n_fine"])
     return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "%d of %d particles x %d rays x (%d + %d) samples, float64 numpy, %.1f s"
                       % (n_particles, poses.shape[0], B, spec["n_coarse"], spec["n_fine"], dt)}
+
+
+def time_path(ctx, img_d, cam, B, pose_a, steps, warmup, seed, torch):
+    """Warm up, then time `steps` update + resample steps with per-kernel events."""
+    N = pose_a.shape[0]
+    dev = pose_a.device
+    pose_b = torch.empty_like(pose_a)
+    ll = torch.empty(N, dtype=torch.float64, device=dev)
+    w = torch.empty(N, dtype=torch.float64, device=dev)
+    un = torch.empty(N, dtype=torch.float32, device=dev)
+    idx = torch.empty(N, dtype=torch.int32, device=dev)
+
+    def step(k):
+        ctx.loc_update_particles(img_d, cam, 1, B, pose_a, None, 0.0, 0.0, seed, k,
+                                 pose_out=pose_b, loglik_out=ll, weight_out=w, uncert_out=un)
+        ctx.loc_resample(w, N, seed, k, idx_out=idx)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ctx.loc_set_profiling(True)
+    stream = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        step(warmup + k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    kstats = ctx.loc_kernel_stats()
+    ctx.loc_set_profiling(False)
+    flags = ctx.loc_sync()
+    return ms_total, kstats, flags
+
+
+def summarize(spec, precision, N, B, steps, ms_total, kstats):
+    S = spec["n_coarse"] + spec["n_fine"]
+    mlp = [kstats[k] for k in ("mlp_coarse", "mlp_fine") if k in kstats]
+    launches = sum(m["launches"] for m in mlp)
+    mlp_ms = sum(m["ms"] for m in mlp)
+    mlp_flop = sum(m["flop"] for m in mlp)
+    achieved = (mlp_flop / launches) / (mlp_ms / launches * 1e-3) / 1e12
+    peak, unit = PEAK[precision]
+    kname = ("k_mlp_f32" if precision == "fp32" else "k_mlp_bf16") + " (%dx%d map)" % (spec["n_layers"], spec["width"])
+    total_k = sum(x["ms"] for x in kstats.values())
+    kernels = {k: {"launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1), "share": v["ms"] / total_k}
+               for k, v in kstats.items()}
+    for k, v in kstats.items():
+        if v["bytes"] > 0 and v["ms"] > 0:
+            kernels[k]["hbm_GBps"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        if v["flop"] > 0 and v["ms"] > 0:
+            kernels[k]["TFLOPs"] = v["flop"] / (v["ms"] * 1e-3) / 1e12
+    return {
+        "samples_per_s": N * B * S * steps / (ms_total * 1e-3),
+        "effective_samples_per_s": N * B * 192 * steps / (ms_total * 1e-3),
+        "particle_updates_per_s": N * steps / (ms_total * 1e-3),
+        "ms_per_step": ms_total / steps,
+        "samples_per_ray": S,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
+                     "flop_per_launch": mlp_flop / launches, "avg_launch_ms": mlp_ms / launches},
+        "kernels": kernels,
+    }
 
 
 def main():
@@ -70,90 +145,81 @@ def main():
     import torch
     from paper_2406_12202_amd import binding, synth
 
-    wl = args.workload
-    spec = synth.spec(wl)
-    params = synth.map_params(spec, args.seed)
-    cam = synth.camera(wl)
+    wl = args.workload if args.mode == "single" else "nerf"
     W = synth.WORKLOADS[wl]
     N, B = W["N"], W["B"]
+    cam = synth.camera(wl)
+    spec = synth.spec(wl)
+    params = synth.map_params(spec, args.seed)
     poses = synth.particles(wl, args.seed)
     img = synth.observation(wl, args.seed)
-
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    ctx = binding.Context(spec, params, precision=args.precision, stream=stream)
     img_d = torch.as_tensor(img, device=dev)
     pose_a = torch.as_tensor(poses, device=dev).contiguous()
-    pose_b = torch.empty_like(pose_a)
-    ll = torch.empty(N, dtype=torch.float64, device=dev)
-    w = torch.empty(N, dtype=torch.float64, device=dev)
-    un = torch.empty(N, dtype=torch.float32, device=dev)
-    idx = torch.empty(N, dtype=torch.int32, device=dev)
 
-    def step(k):
-        ctx.loc_update_particles(img_d, cam, 1, B, pose_a, None, 0.0, 0.0, args.seed, k,
-                                 pose_out=pose_b, loglik_out=ll, weight_out=w, uncert_out=un)
-        ctx.loc_resample(w, N, args.seed, k, idx_out=idx)
-
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    ctx.loc_set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for k in range(args.steps):
-        step(args.warmup + k)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    kstats = ctx.loc_kernel_stats()
-    ctx.loc_set_profiling(False)
-    flags = ctx.loc_sync()
-
-    samples_per_step = N * B * (spec["n_coarse"] + spec["n_fine"])
-    ms_step = ms_total / args.steps
-    value = samples_per_step * args.steps / (ms_total * 1e-3)
-
-    # dominant kernel: the map MLP (coarse and fine launches of one kernel)
-    mlp = [kstats[k] for k in ("mlp_coarse", "mlp_fine") if k in kstats]
-    launches = sum(m["launches"] for m in mlp)
-    mlp_ms = sum(m["ms"] for m in mlp)
-    mlp_flop = sum(m["flop"] for m in mlp)
-    achieved = (mlp_flop / launches) / (mlp_ms / launches * 1e-3) / 1e12
-    dt = "f32" if args.precision == "fp32" else "bf16"
-    peak, unit = PEAK[dt]
-    kname = ("k_mlp_f32" if dt == "f32" else "k_mlp_bf16") + " (%dx%d map)" % (spec["n_layers"], spec["width"])
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
-                "flop_per_launch": mlp_flop / launches, "avg_launch_ms": mlp_ms / launches}
-    kernels = {k: {"launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1),
-                   "share": v["ms"] / max(sum(x["ms"] for x in kstats.values()), 1e-12)}
-               for k, v in kstats.items()}
-    for k, v in kstats.items():
-        if v["bytes"] > 0 and v["ms"] > 0:
-            kernels[k]["hbm_GBps"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
-
-    out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": dt, "data": "synthetic",
-           "config": {"workload": "%s: %d particles x %d rays x (%d coarse + %d fine) samples, "
-                                  "%dx%d map, %dx%d image" % (wl, N, B, spec["n_coarse"], spec["n_fine"],
-                                                             spec["n_layers"], spec["width"], W["W"], W["H"]),
-                      "particles": N, "rays_per_particle": B, "precision": args.precision,
-                      "samples_per_step": samples_per_step},
-           "particle_updates_per_s": N * args.steps / (ms_total * 1e-3),
-           "effective_samples_per_s": N * B * 192 * args.steps / (ms_total * 1e-3),
-           "roofline": roofline, "kernels": kernels, "flags": flags, "wall_s": wall}
+    if args.mode == "single":
+        ctx = binding.Context(spec, params, precision=args.precision, stream=stream)
+        ms, ks, flags = time_path(ctx, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
+        r = summarize(spec, args.precision, N, B, args.steps, ms, ks)
+        out = {"metric": METRIC, "value": r["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
+               "data": "synthetic",
+               "config": {"workload": "%s: %d particles x %d rays x (%d + %d) samples, %dx%d map, %s"
+                                      % (wl, N, B, spec["n_coarse"], spec["n_fine"], spec["n_layers"],
+                                         spec["width"], args.precision),
+                          "particles": N, "rays_per_particle": B},
+               "particle_updates_per_s": r["particle_updates_per_s"], "roofline": r["roofline"],
+               "kernels": r["kernels"], "flags": flags}
+        ctx.close()
+    else:
+        # plain FP32, 64 + 128 hierarchical
+        ctx32 = binding.Context(spec, params, precision="fp32", stream=stream)
+        ms32, ks32, fl32 = time_path(ctx32, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
+        r32 = summarize(spec, "fp32", N, B, args.steps, ms32, ks32)
+        ctx32.close()
+        # BF16 + learned proposal, 64 + 32
+        spec_p = synth.spec("proposal")
+        ctxp = binding.Context(spec_p, params, precision="bf16", stream=stream)
+        t0 = time.perf_counter()
+        tp = torch.as_tensor(synth.training_poses("proposal", args.seed, args.train_poses), device=dev)
+        O, D = ctxp.loc_cast_rays(cam, 1, 64, tp, seed=args.seed + 1, iter=0)
+        T = ctxp.loc_teacher_histograms(O, D, 128, seed=args.seed + 1, iter=1)
+        ctxp.loc_set_proposal(synth.proposal_params(args.seed))
+        losses = ctxp.loc_train_proposal(O, D, T, 8192, args.train_steps, lr=2e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        losses = losses.cpu().numpy()
+        del O, D, T, tp
+        ctxp.loc_set_fine_mode(1)
+        msp, ksp, flp = time_path(ctxp, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
+        rp = summarize(spec_p, "bf16", N, B, args.steps, msp, ksp)
+        ctxp.close()
+        out = {"metric": METRIC, "value": rp["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": rp["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+               "data": "synthetic",
+               "config": {"workload": "proposal: %d particles x %d rays, 8x256 map in bf16 + learned proposal, "
+                                      "64 coarse + 32 proposal-placed samples; against plain fp32 with 64 + 128 "
+                                      "hierarchical samples on identical particles, pixels and jitter" % (N, B),
+                          "particles": N, "rays_per_particle": B, "image": "%dx%d" % (W["W"], W["H"])},
+               "particle_updates_per_s": rp["particle_updates_per_s"],
+               "effective_samples_per_s": rp["effective_samples_per_s"],
+               "speedup_particle_updates_vs_fp32": rp["particle_updates_per_s"] / r32["particle_updates_per_s"],
+               "speedup_mlp_samples_vs_fp32": rp["samples_per_s"] / r32["samples_per_s"],
+               "roofline": rp["roofline"], "kernels": rp["kernels"], "flags": flp,
+               "proposal_training": {"rays": args.train_poses * 64, "steps": args.train_steps, "batch": 8192,
+                                     "seconds": train_s, "loss_first": float(losses[:20].mean()),
+                                     "loss_last": float(losses[-20:].mean())},
+               "fp32_plain": {"samples_per_s": r32["samples_per_s"], "ms_per_step": r32["ms_per_step"],
+                              "particle_updates_per_s": r32["particle_updates_per_s"],
+                              "roofline": r32["roofline"], "kernels": r32["kernels"], "flags": fl32}}
     if not args.no_cpu_baseline:
         n_cpu = args.cpu_particles or (48 if wl == "nerf" else 32)
-        out["cpu_baseline"] = cpu_baseline(wl, spec, params, img, cam, B, poses, args.seed, n_cpu)
+        out["cpu_baseline"] = cpu_baseline(spec, params, img, cam, B, poses, args.seed, n_cpu)
     print(json.dumps(out), flush=True)
-    ctx.close()
     return 0
 
 
