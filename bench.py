@@ -3,8 +3,9 @@
 
 A step is one pass of the whole hot path over one batch: loc_update_particles
 (prediction, rays, stratified + fine samples, posenc + MLP, compositing with
-the uncertainty F, Eq. 6 score, normalisation) followed by loc_resample
-(systematic, integer-exact).  Inputs are resident in HBM before the timed
+the uncertainty F, Eq. 6 score, normalisation), the pose read-out
+(loc_pose_estimate), loc_resample (systematic, integer-exact) and the gather
+of the resampled poses (loc_gather_poses).  Inputs are resident in HBM before the timed
 region.
 
 Default: the headline comparison on the NeRF-sized workload (8x256 map,
@@ -33,6 +34,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLP samples/s & particle updates/s, BF16+proposal vs plain FP32, 1 GPU"
 PEAK = {"fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}
+
+# HBM bytes per map-kernel launch (mean of the coarse and fine launches of one
+# step at 400 particles x 64 rays) from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs, scaled by what the counters read for a plain 1 GiB copy (x1.99995 and
+# x1.0), together with a digest of the kernel sources they were taken on: the
+# figure is reported only while the sources are unchanged.
+TRAFFIC = {
+    "bf16": {"sources": ("mlp_bf16.hip", "maplayout_bf16.h", "common.h"), "digest": "2c2d5588b35f41ed",
+             "bytes": {"headline": ((11.746e6 + 32.768e6) + (14.204e6 + 13.107e6)) / 2}},
+    "fp32": {"sources": ("mlp_f32.hip", "maplayout.h", "common.h"), "digest": "a40493ded30e7163",
+             "bytes": {"headline": ((26.498e6 + 32.768e6) + (39.600e6 + 52.429e6)) / 2}},
+}
+
+
+def traffic(precision, workload):
+    import hashlib
+    t = TRAFFIC[precision]
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2406_12202_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != t["digest"]:
+        return None
+    return t["bytes"].get(workload)
 DTYPE = {"fp32": "f32", "bf16": "bf16"}
 
 
@@ -41,8 +66,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="headline", choices=["headline", "single"],
-                    help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision)")
+    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy"],
+                    help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision); "
+                         "copy: a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--train-poses", type=int, default=31250, help="proposal training poses (x 64 rays)")
@@ -80,11 +106,15 @@ def time_path(ctx, img_d, cam, B, pose_a, steps, warmup, seed, torch):
     w = torch.empty(N, dtype=torch.float64, device=dev)
     un = torch.empty(N, dtype=torch.float32, device=dev)
     idx = torch.empty(N, dtype=torch.int32, device=dev)
+    pose_c = torch.empty_like(pose_a)
+    est = torch.empty((3, 4), dtype=torch.float64, device=dev)
 
     def step(k):
         ctx.loc_update_particles(img_d, cam, 1, B, pose_a, None, 0.0, 0.0, seed, k,
                                  pose_out=pose_b, loglik_out=ll, weight_out=w, uncert_out=un)
+        ctx.loc_pose_estimate(pose_b, w, est=est)
         ctx.loc_resample(w, N, seed, k, idx_out=idx)
+        ctx.loc_gather_poses(pose_b, idx, pose_out=pose_c)
 
     for k in range(warmup):
         step(k)
@@ -106,7 +136,7 @@ def time_path(ctx, img_d, cam, B, pose_a, steps, warmup, seed, torch):
     return ms_total, kstats, flags
 
 
-def summarize(spec, precision, N, B, steps, ms_total, kstats):
+def summarize(spec, precision, N, B, steps, ms_total, kstats, counted=None):
     S = spec["n_coarse"] + spec["n_fine"]
     mlp = [kstats[k] for k in ("mlp_coarse", "mlp_fine") if k in kstats]
     launches = sum(m["launches"] for m in mlp)
@@ -130,10 +160,32 @@ def summarize(spec, precision, N, B, steps, ms_total, kstats):
         "ms_per_step": ms_total / steps,
         "samples_per_ray": S,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": kname,
+                     "frac": round(achieved / peak, 4), "traffic": traffic(precision, counted) if counted else None, "kernel": kname,
                      "flop_per_launch": mlp_flop / launches, "avg_launch_ms": mlp_ms / launches},
         "kernels": kernels,
     }
+
+
+def copy_reference(args, torch):
+    """A plain device-to-device copy of 2^30 bytes per launch: what the HBM
+    byte counters read for it calibrates them (2^20 KiB read, 2^20 KiB written)."""
+    dev = torch.device("cuda", 0)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(json.dumps({"mode": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30, "ms_per_copy": ms,
+                      "GBps": 2 * (1 << 30) / (ms * 1e-3) / 1e9}), flush=True)
+    return 0
 
 
 def main():
@@ -143,6 +195,8 @@ def main():
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         return 2
     import torch
+    if args.mode == "copy":
+        return copy_reference(args, torch)
     from paper_2406_12202_amd import binding, synth
 
     wl = args.workload if args.mode == "single" else "nerf"
@@ -178,7 +232,7 @@ def main():
         # plain FP32, 64 + 128 hierarchical
         ctx32 = binding.Context(spec, params, precision="fp32", stream=stream)
         ms32, ks32, fl32 = time_path(ctx32, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
-        r32 = summarize(spec, "fp32", N, B, args.steps, ms32, ks32)
+        r32 = summarize(spec, "fp32", N, B, args.steps, ms32, ks32, counted="headline")
         ctx32.close()
         # BF16 + learned proposal, 64 + 32
         spec_p = synth.spec("proposal")
@@ -195,7 +249,7 @@ def main():
         del O, D, T, tp
         ctxp.loc_set_fine_mode(1)
         msp, ksp, flp = time_path(ctxp, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
-        rp = summarize(spec_p, "bf16", N, B, args.steps, msp, ksp)
+        rp = summarize(spec_p, "bf16", N, B, args.steps, msp, ksp, counted="headline")
         ctxp.close()
         out = {"metric": METRIC, "value": rp["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": rp["ms_per_step"],

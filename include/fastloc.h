@@ -165,13 +165,27 @@ loc_status loc_update_particles(loc_ctx* ctx, const float* image_rgb, const loc_
 loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
                         uint64_t seed, uint64_t iter, int32_t* idx_out);
 
+/* Poses of the resampled set (Alg. 1, "add x_t^[i] to X_t"): pose_out[k] =
+ * pose_in[idx[k]], DEVICE N x 12 float64 arrays and DEVICE int32 indices (an
+ * index outside [0, n_in) leaves pose_out[k] unchanged). */
+loc_status loc_gather_poses(loc_ctx* ctx, const double* pose_in, int n_in, const int32_t* idx, int n_out,
+                            double* pose_out);
+
+/* Pose read-out from a weighted particle set (the paper does not say how):
+ * est (DEVICE 12 float64) = [R | t] with t = sum w_i t_i / sum w_i and R the
+ * chordal L2 mean U diag(1, 1, det(U V^T)) V^T of sum_i w_i R_i = U S V^T
+ * (w <= 0 or non-finite counts as 0).  All weights zero: est is NaN and
+ * loc_sync reports LOC_FLAG_DEGENERATE_WEIGHTS; a singular sum: NaN and
+ * LOC_FLAG_SINGULAR_ROTATION. */
+loc_status loc_pose_estimate(loc_ctx* ctx, const double* pose, const double* weight, int N, double* est);
+
 /* Per-ray results of the last loc_update_particles on this context, copied
  * into DEVICE arrays of N*B entries (ray (i, j) at i*B + j); any pointer may be
  * NULL.  rgb: 3 floats per ray (C), opacity: A = 1 - T(far), F: uncertainty,
  * E: squared colour error.  Enqueued on the stream. */
 loc_status loc_ray_outputs(loc_ctx* ctx, float* rgb, float* opacity, float* F, float* E);
 
-enum { LOC_FLAG_DEGENERATE_WEIGHTS = 1, LOC_FLAG_DEGENERATE_RESAMPLE = 2 };
+enum { LOC_FLAG_DEGENERATE_WEIGHTS = 1, LOC_FLAG_DEGENERATE_RESAMPLE = 2, LOC_FLAG_SINGULAR_ROTATION = 4 };
 
 /* Wait for the context's stream; *flags (may be NULL) receives the OR of
  * LOC_FLAG_* raised since the previous loc_sync.  Returns LOC_E_HIP if

@@ -19,7 +19,8 @@ PRECISIONS = {"fp32": LOC_FP32, "bf16": LOC_BF16, "fp8": LOC_FP8_E4M3}
 EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
            "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error",
            "loc_cast_rays", "loc_teacher_histograms", "loc_set_proposal", "loc_get_proposal",
-           "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal"]
+           "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal",
+           "loc_gather_poses", "loc_pose_estimate"]
 PROPOSAL_PARAMS = 11296
 
 
@@ -87,10 +88,12 @@ def load(path=LIB_PATH):
     lib.loc_proposal_forward.argtypes = [vp, vp, vp, c_int, vp]
     lib.loc_proposal_grad.argtypes = [vp, vp, vp, vp, c_int, vp, vp]
     lib.loc_train_proposal.argtypes = [vp, vp, vp, vp, c_int, ctypes.POINTER(TrainCfg), vp]
+    lib.loc_gather_poses.argtypes = [vp, vp, c_int, vp, c_int, vp]
+    lib.loc_pose_estimate.argtypes = [vp, vp, vp, c_int, vp]
     for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
               "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
               "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
-              "loc_proposal_grad", "loc_train_proposal"):
+              "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -297,3 +300,26 @@ class Context:
                                                 ctypes.byref(cfg), _ptr(losses, torch.float32, losses.numel(), "loss")),
                     "loc_train_proposal")
         return losses[:steps]
+
+    # ------------------------------------------------------------------ poses
+
+    def loc_gather_poses(self, pose_in, idx, pose_out=None):
+        import torch
+        n_in, n_out = pose_in.shape[0], idx.numel()
+        if pose_out is None:
+            pose_out = torch.empty((n_out, 3, 4), dtype=torch.float64, device=pose_in.device)
+        self._check(self.lib.loc_gather_poses(self.h, _ptr(pose_in, torch.float64, n_in * 12, "pose_in"), int(n_in),
+                                              _ptr(idx, torch.int32, n_out, "idx"), int(n_out),
+                                              _ptr(pose_out, torch.float64, n_out * 12, "pose_out")),
+                    "loc_gather_poses")
+        return pose_out
+
+    def loc_pose_estimate(self, pose, weight, est=None):
+        import torch
+        N = pose.shape[0]
+        if est is None:
+            est = torch.empty((3, 4), dtype=torch.float64, device=pose.device)
+        self._check(self.lib.loc_pose_estimate(self.h, _ptr(pose, torch.float64, N * 12, "pose"),
+                                               _ptr(weight, torch.float64, N, "weight"), int(N),
+                                               _ptr(est, torch.float64, 12, "est")), "loc_pose_estimate")
+        return est

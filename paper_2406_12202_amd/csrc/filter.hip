@@ -207,3 +207,157 @@ hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t s
 }
 
 }  // namespace fl
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// pose gather after resampling: out[k] = in[idx[k]] (idx < 0 copies nothing)
+__global__ void k_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_out * 12) return;
+  const int k = t / 12, q = t - k * 12;
+  const int i = idx[k];
+  if (i >= 0 && i < n_in) out[t] = in[(long)i * 12 + q];
+}
+
+hipError_t launch_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out,
+                               hipStream_t st) {
+  const int n = n_out * 12;
+  hipLaunchKernelGGL(k_gather_poses, dim3((n + 255) / 256), dim3(256), 0, st, in, idx, n_in, n_out, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// pose read-out: weighted mean position and chordal L2 mean rotation
+// R = U diag(1, 1, det(U V^T)) V^T for sum_i w_i R_i = U S V^T.
+__device__ void mat3_mul(const double* A, const double* B, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+__device__ double mat3_det(const double* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// smallest-eigenvalue eigenvector of a symmetric 3x3 matrix by cyclic Jacobi rotations
+__device__ void sym3_min_eigvec(const double* Ain, double* v) {
+  double A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int i = 0; i < 9; ++i) A[i] = Ain[i];
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        const double apq = A[3 * p + q];
+        if (fabs(apq) < 1e-300) continue;
+        const double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; ++k) {     // A <- J^T A J
+          const double akp = A[3 * k + p], akq = A[3 * k + q];
+          A[3 * k + p] = c * akp - s * akq;
+          A[3 * k + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double apk = A[3 * p + k], aqk = A[3 * q + k];
+          A[3 * p + k] = c * apk - s * aqk;
+          A[3 * q + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {     // V <- V J
+          const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+          V[3 * k + p] = c * vkp - s * vkq;
+          V[3 * k + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int m = 0;
+  if (A[4] < A[3 * m + m]) m = 1;
+  if (A[8] < A[3 * m + m]) m = 2;
+  for (int k = 0; k < 3; ++k) v[k] = V[3 * k + m];
+}
+
+constexpr int kEstThreads = 256;
+
+__global__ __launch_bounds__(kEstThreads) void k_pose_estimate(const double* pose, const double* w, int N,
+                                                               double* est, int* flags) {
+  __shared__ double s[kEstThreads][13];
+  const int tid = threadIdx.x;
+  double acc[13];
+  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+  for (int i = tid; i < N; i += kEstThreads) {
+    const double wi = (isfinite(w[i]) && w[i] > 0.0) ? w[i] : 0.0;
+    const double* P = pose + (long)i * 12;
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) acc[3 * r + c] += wi * P[4 * r + c];
+      acc[9 + r] += wi * P[4 * r + 3];
+    }
+    acc[12] += wi;
+  }
+  for (int q = 0; q < 13; ++q) s[tid][q] = acc[q];
+  __syncthreads();
+  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int q = 0; q < 13; ++q) s[tid][q] += s[tid + o][q];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const double W = s[0][12];
+  if (!(W > 0.0)) {
+    atomicOr(flags, 1);
+    for (int q = 0; q < 12; ++q) est[q] = NAN;
+    return;
+  }
+  double M[9];
+  for (int q = 0; q < 9; ++q) M[q] = s[0][q] / W;
+  // orthogonal polar factor Q of M by scaled Newton iteration
+  // Q <- (g Q + Q^{-T} / g) / 2 with g = (|det Q|)^(-1/3)
+  double Q[9];
+  for (int q = 0; q < 9; ++q) Q[q] = M[q];
+  double d = mat3_det(Q);
+  if (!(fabs(d) > 1e-300)) {
+    atomicOr(flags, 4);
+    for (int q = 0; q < 12; ++q) est[q] = NAN;
+    return;
+  }
+  for (int it = 0; it < 60; ++it) {
+    d = mat3_det(Q);
+    const double g = pow(fabs(d), -1.0 / 3.0);
+    // inverse transpose = cofactor matrix / det
+    double C[9];
+    C[0] = Q[4] * Q[8] - Q[5] * Q[7]; C[1] = Q[5] * Q[6] - Q[3] * Q[8]; C[2] = Q[3] * Q[7] - Q[4] * Q[6];
+    C[3] = Q[2] * Q[7] - Q[1] * Q[8]; C[4] = Q[0] * Q[8] - Q[2] * Q[6]; C[5] = Q[1] * Q[6] - Q[0] * Q[7];
+    C[6] = Q[1] * Q[5] - Q[2] * Q[4]; C[7] = Q[2] * Q[3] - Q[0] * Q[5]; C[8] = Q[0] * Q[4] - Q[1] * Q[3];
+    double diff = 0.0;
+    for (int q = 0; q < 9; ++q) {
+      const double nq = 0.5 * (g * Q[q] + C[q] / (d * g));
+      diff = fmax(diff, fabs(nq - Q[q]));
+      Q[q] = nq;
+    }
+    if (diff < 1e-15) break;
+  }
+  double R[9];
+  for (int q = 0; q < 9; ++q) R[q] = Q[q];
+  if (mat3_det(Q) < 0.0) {
+    // reflection: flip the direction of the smallest singular value,
+    // R = Q - 2 (Q v) v^T with v the smallest eigenvector of H = Q^T M
+    double QT[9], H[9], v[3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) QT[3 * r + c] = Q[3 * c + r];
+    mat3_mul(QT, M, H);
+    for (int r = 0; r < 3; ++r)
+      for (int c = r + 1; c < 3; ++c) H[3 * r + c] = H[3 * c + r] = 0.5 * (H[3 * r + c] + H[3 * c + r]);
+    sym3_min_eigvec(H, v);
+    double u[3];
+    for (int r = 0; r < 3; ++r) u[r] = Q[3 * r] * v[0] + Q[3 * r + 1] * v[1] + Q[3 * r + 2] * v[2];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) R[3 * r + c] = Q[3 * r + c] - 2.0 * u[r] * v[c];
+  }
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) est[4 * r + c] = R[3 * r + c];
+    est[4 * r + 3] = s[0][9 + r] / W;
+  }
+}
+
+hipError_t launch_pose_estimate(const double* pose, const double* w, int N, double* est, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_estimate, dim3(1), dim3(kEstThreads), 0, st, pose, w, N, est, flags);
+  return hipGetLastError();
+}
+
+}  // namespace fl

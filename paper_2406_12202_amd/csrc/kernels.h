@@ -124,6 +124,10 @@ hipError_t launch_normalize(const double* loglik, double* weight, int N, int* fl
 hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
                            unsigned long long* prefix, int32_t* idx, int* flags, hipStream_t st);
 
+hipError_t launch_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out,
+                               hipStream_t st);
+hipError_t launch_pose_estimate(const double* pose, const double* w, int N, double* est, int* flags, hipStream_t st);
+
 hipError_t launch_split_ray_outputs(const float4* rgba, const float2* fe, int n, float* rgb,
                                     float* opacity, float* F, float* E, hipStream_t st);
 

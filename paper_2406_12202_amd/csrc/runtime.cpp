@@ -21,10 +21,11 @@ using namespace fl;
 namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
-                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_COUNT };
+                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
-                                     "ray_format", "teacher_histogram", "proposal_train"};
+                                     "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
+                                     "pose_estimate"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -920,6 +921,27 @@ loc_status loc_train_proposal(loc_ctx* c, const float* ray_o, const float* ray_d
       return s;
   }
   return LOC_OK;
+}
+
+
+loc_status loc_gather_poses(loc_ctx* c, const double* pose_in, int n_in, const int32_t* idx, int n_out,
+                            double* pose_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!pose_in || !idx || !pose_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n_in < 1 || n_in > (1 << 24) || n_out < 1 || n_out > (1 << 24))
+    return fail(c, LOC_E_ARG, "n_in and n_out must be in [1, 2^24]");
+  return timed(c, K_GATHER, 0, 96.0 * 2 * n_out + 4.0 * n_out, [&] {
+    return launch_gather_poses(pose_in, idx, n_in, n_out, pose_out, c->stream);
+  });
+}
+
+loc_status loc_pose_estimate(loc_ctx* c, const double* pose, const double* weight, int N, double* est) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!pose || !weight || !est) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (N < 1 || N > (1 << 24)) return fail(c, LOC_E_ARG, "N must be in [1, 2^24]");
+  return timed(c, K_ESTIMATE, 0, 104.0 * N, [&] { return launch_pose_estimate(pose, weight, N, est, c->flags, c->stream); });
 }
 
 }  // extern "C"
