@@ -107,7 +107,11 @@ typedef struct {
   int L_xyz, L_dir, dir_width;
   const float* params;     /* HOST */
   size_t n_params;
-  loc_precision precision; /* LOC_FP32 or LOC_BF16 (bf16 map, float32 accumulate) */
+  loc_precision precision; /* LOC_FP32, LOC_BF16 (bf16 map, float32 accumulate), or
+                              LOC_FP8_E4M3 (8x256 map only: hidden-to-hidden products
+                              in OCP E4M3 with per-layer power-of-two scales, products
+                              with the encodings in bf16, heads in float32; needs
+                              loc_calibrate_fp8 before use) */
   float near_, far_;
   int n_coarse, n_fine;    /* n_coarse in [1, 256], n_fine in [0, 256] */
   float alpha, tau;        /* 0 < alpha < 0.5, tau > 0 */
@@ -164,6 +168,24 @@ loc_status loc_update_particles(loc_ctx* ctx, const float* image_rgb, const loc_
  */
 loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
                         uint64_t seed, uint64_t iter, int32_t* idx_out);
+
+/* FP8 calibration of an LOC_FP8_E4M3 context (per-layer amax scaling): the
+ * float32 map is evaluated at the midpoints of the n_coarse strata of each of
+ * n_rays rays (o, d: DEVICE n_rays x 3 float32, e.g. loc_cast_rays output),
+ * the largest |output| of every layer sets the power-of-two scale 2^ea of the
+ * next layer's E4M3 input (largest with amax 2^ea <= 448), the largest |weight|
+ * of every hidden-to-hidden block sets 2^ew likewise, and the weights are
+ * packed.  Values beyond the calibrated range saturate at +-448.  Synchronous.
+ * n_rays in [1, 2^20].  LOC_E_STATE for a context of another precision.
+ * Update and teacher calls on an FP8 context return LOC_E_STATE until this has
+ * run. */
+loc_status loc_calibrate_fp8(loc_ctx* ctx, const float* o, const float* d, int n_rays);
+
+/* The calibrated exponents (HOST arrays of n >= 10 entries, any may be NULL):
+ * ew[l], ea[l] of layer l in execution order (0..7 trunk, 8 feature, 9
+ * direction; ew[0] = ea[0] = 0, the input layer being bf16) and amax[l], the
+ * calibrated largest |output| of layer l (l <= 8). */
+loc_status loc_fp8_scales(loc_ctx* ctx, int* ew, int* ea, float* amax, int n);
 
 /* Poses of the resampled set (Alg. 1, "add x_t^[i] to X_t"): pose_out[k] =
  * pose_in[idx[k]], DEVICE N x 12 float64 arrays and DEVICE int32 indices (an

@@ -20,7 +20,7 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outp
            "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error",
            "loc_cast_rays", "loc_teacher_histograms", "loc_set_proposal", "loc_get_proposal",
            "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal",
-           "loc_gather_poses", "loc_pose_estimate"]
+           "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales"]
 PROPOSAL_PARAMS = 11296
 
 
@@ -90,10 +90,12 @@ def load(path=LIB_PATH):
     lib.loc_train_proposal.argtypes = [vp, vp, vp, vp, c_int, ctypes.POINTER(TrainCfg), vp]
     lib.loc_gather_poses.argtypes = [vp, vp, c_int, vp, c_int, vp]
     lib.loc_pose_estimate.argtypes = [vp, vp, vp, c_int, vp]
+    lib.loc_calibrate_fp8.argtypes = [vp, vp, vp, c_int]
+    lib.loc_fp8_scales.argtypes = [vp, vp, vp, vp, c_int]
     for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
               "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
               "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
-              "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate"):
+              "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -323,3 +325,18 @@ class Context:
                                                _ptr(weight, torch.float64, N, "weight"), int(N),
                                                _ptr(est, torch.float64, 12, "est")), "loc_pose_estimate")
         return est
+
+    # -------------------------------------------------------------------- FP8
+
+    def loc_calibrate_fp8(self, o, d):
+        import torch
+        n = o.shape[0]
+        self._check(self.lib.loc_calibrate_fp8(self.h, _ptr(o, torch.float32, n * 3, "o"),
+                                               _ptr(d, torch.float32, n * 3, "d"), int(n)), "loc_calibrate_fp8")
+
+    def loc_fp8_scales(self):
+        ew = (ctypes.c_int * 12)()
+        ea = (ctypes.c_int * 12)()
+        am = (ctypes.c_float * 12)()
+        self._check(self.lib.loc_fp8_scales(self.h, ew, ea, am, 12), "loc_fp8_scales")
+        return list(ew[:10]), list(ea[:10]), list(am[:9])

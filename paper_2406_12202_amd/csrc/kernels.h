@@ -24,9 +24,28 @@ struct MlpArgs {
   float near_, dt;       // coarse grid: t_k = near + (k + xi) dt
   int jitter;
   uint64_t seed, iter;
+  // FP8 path, per layer l in execution order: E8M0 scale bytes of the weight
+  // (2^-ew_l) and activation (2^-ea_l) operands, and the factor 2^ea_{l+1}
+  // applied to layer l's output before it is rounded to E4M3
+  int f8_sw[12], f8_sx[12];
+  float f8_qout[12];
 };
 hipError_t launch_mlp(int map_kind, const MlpArgs& a, hipStream_t st);
 hipError_t launch_mlp_bf16(int map_kind, const MlpArgs& a, hipStream_t st);
+hipError_t launch_mlp_fp8(int map_kind, const MlpArgs& a, hipStream_t st);
+
+// FP8 calibration: float32 evaluation of the 8x256 map at the midpoints of
+// spr strata on each ray, recording per layer l (execution order 0..D) the
+// largest |output| (after ReLU where the layer has one) into amax[l]
+struct CalibArgs {
+  const float* o;        // n_rays x 3
+  const float* d;        // n_rays x 3
+  int n_rays, spr;
+  float near_, dt;
+  const float* wt;       // per layer, transposed weights (in x out) then bias (out)
+  unsigned* amax;        // float bits of non-negative maxima, D + 1 entries
+};
+hipError_t launch_calibrate_fp8(const CalibArgs& a, hipStream_t st);
 
 struct Pose12 { double m[12]; };
 

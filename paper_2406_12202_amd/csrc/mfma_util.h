@@ -1,0 +1,92 @@
+// Pieces shared by the MFMA map kernels with LDS-streamed weights (BF16 and
+// FP8 paths): operand vector types, the bf16 positional-encoding operands,
+// direct global->LDS weight streaming, and the per-tile sample set-up.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace fl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// bf16 operands of the encoding gamma(p) (pseudo-pair layout of maplayout_bf16.h)
+template <int L, int KB>
+__device__ __forceinline__ void posenc_b(const float p0, const float p1, const float p2, const int h,
+                                         bf16x8 (&out)[KB]) {
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = 8 * kb + 4 * h + j;
+      float a = 0.0f, b = 0.0f;
+      if (p < 3 * L) {
+        const int c = p % 3;
+        const float x = c == 0 ? p0 : (c == 1 ? p1 : p2);
+        sincospif(ldexpf(x, p / 3), &a, &b);
+      } else if (p == 3 * L) {
+        a = p0; b = p1;
+      } else if (p == 3 * L + 1) {
+        a = p2;
+      }
+      out[kb][2 * j] = (__bf16)a;
+      out[kb][2 * j + 1] = (__bf16)b;
+    }
+  }
+}
+
+// issue the direct loads of nkb consecutive 1 KB units into an LDS slot;
+// wave wv takes units wv, wv + WAVES, ...
+template <int WAVES>
+__device__ __forceinline__ void issue_blocks(const uint4* __restrict__ wb, const long base, const int nkb,
+                                             uint4* slot, const int wv, const int lane) {
+  for (int b = wv; b < nkb; b += WAVES)
+    __builtin_amdgcn_global_load_lds((const void*)(wb + (base + b) * 64 + lane),
+                                     (lds_void_t*)(slot + b * 64), 16, 0, 0);
+}
+
+// Sample set-up of one wave's NTL column tiles of 32 samples: depth (given, or
+// stratified with jitter and written out), then gamma(x) and gamma(d) as bf16
+// operands into the wave's LDS blocks laid out [column tile][k-block][lane].
+// Each lane later reads back only its own entries, so no barrier is needed.
+template <int LX, int LD, int KBX, int KBD, int NTL>
+__device__ __forceinline__ void stage_samples(const MlpArgs& a, const long tile, const int lane, uint4* gx_lds,
+                                              uint4* gd_lds, long (&sidx)[NTL], bool (&valid)[NTL]) {
+  const int n = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    const long s = tile * (32 * NTL) + nt * 32 + n;
+    valid[nt] = s < a.n_samples;
+    sidx[nt] = s;
+    const long sc = valid[nt] ? s : a.n_samples - 1;
+    const int ray = (int)(sc / a.spr);
+    const int k = (int)(sc - (long)ray * a.spr);
+    const float4 o = a.ray_o[ray];
+    const float4 d = a.ray_d[ray];
+    float t;
+    if (a.t_in) {
+      t = a.t_in[sc];
+    } else {
+      float xi = 0.0f;
+      if (a.jitter) {
+        const int i = ray / a.B, j = ray - (ray / a.B) * a.B;
+        xi = unit24(pick(draw(a.seed, a.iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
+      }
+      t = a.near_ + ((float)k + xi) * a.dt;
+      if (valid[nt] && h == 0) a.t_out[s] = t;
+    }
+    bf16x8 gx[KBX], gd[KBD];
+    posenc_b<LX>(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z), h, gx);
+    posenc_b<LD>(d.x, d.y, d.z, h, gd);
+#pragma unroll
+    for (int kb = 0; kb < KBX; ++kb) gx_lds[(nt * KBX + kb) * 64 + lane] = __builtin_bit_cast(uint4, gx[kb]);
+#pragma unroll
+    for (int kb = 0; kb < KBD; ++kb) gd_lds[(nt * KBD + kb) * 64 + lane] = __builtin_bit_cast(uint4, gd[kb]);
+  }
+}
+
+}  // namespace fl

@@ -10,50 +10,10 @@
 // NTL MFMAs.  The bias enters as the accumulator input of the first MFMA of a
 // tile, and ReLU runs on packed bf16 pairs after rounding, so the epilogue of a
 // tile is one conversion and one packed max per pair of outputs.
-#include "common.h"
+#include "mfma_util.h"
 #include "maplayout_bf16.h"
-#include "kernels.h"
 
 namespace fl {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-template <int L, int KB>
-__device__ __forceinline__ void posenc_b(const float p0, const float p1, const float p2, const int h,
-                                         bf16x8 (&out)[KB]) {
-#pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = 8 * kb + 4 * h + j;
-      float a = 0.0f, b = 0.0f;
-      if (p < 3 * L) {
-        const int c = p % 3;
-        const float x = c == 0 ? p0 : (c == 1 ? p1 : p2);
-        sincospif(ldexpf(x, p / 3), &a, &b);
-      } else if (p == 3 * L) {
-        a = p0; b = p1;
-      } else if (p == 3 * L + 1) {
-        a = p2;
-      }
-      out[kb][2 * j] = (__bf16)a;
-      out[kb][2 * j + 1] = (__bf16)b;
-    }
-  }
-}
-
-// issue the direct loads of nkb consecutive 1 KB blocks into an LDS slot;
-// wave wv takes blocks wv, wv + WAVES, ...
-template <int WAVES>
-__device__ __forceinline__ void issue_blocks(const uint4* __restrict__ wb, const long base, const int nkb,
-                                             uint4* slot, const int wv, const int lane) {
-  for (int b = wv; b < nkb; b += WAVES)
-    __builtin_amdgcn_global_load_lds((const void*)(wb + (base + b) * 64 + lane),
-                                     (lds_void_t*)(slot + b * 64), 16, 0, 0);
-}
 
 // rounded bf16 operands of the next layer from one finished output tile; the
 // bias is already in the accumulators; ReLU acts on the packed bf16 pairs
@@ -186,7 +146,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
   __shared__ uint4 s_gd[WAVES][NTL * S::KBD * 64];
   __shared__ float4 s_bias[S::BIASES / 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int n = lane & 31, h = lane >> 5;
+  const int h = lane >> 5;
   const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
   // weights of layer 0's first chunk group start loading while the inputs
   // are encoded; biases go to LDS (visible after the first barrier)
@@ -197,37 +157,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
   const long tile = (long)blockIdx.x * WAVES + wv;
   long sidx[NTL];
   bool valid[NTL];
-#pragma unroll
-  for (int nt = 0; nt < NTL; ++nt) {
-    const long s = tile * (32 * NTL) + nt * 32 + n;
-    valid[nt] = s < a.n_samples;
-    sidx[nt] = s;
-    const long sc = valid[nt] ? s : a.n_samples - 1;
-    const int ray = (int)(sc / a.spr);
-    const int k = (int)(sc - (long)ray * a.spr);
-    const float4 o = a.ray_o[ray];
-    const float4 d = a.ray_d[ray];
-    float t;
-    if (a.t_in) {
-      t = a.t_in[sc];
-    } else {
-      float xi = 0.0f;
-      if (a.jitter) {
-        const int i = ray / a.B, j = ray - (ray / a.B) * a.B;
-        xi = unit24(pick(draw(a.seed, a.iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
-      }
-      t = a.near_ + ((float)k + xi) * a.dt;
-      if (valid[nt] && h == 0) a.t_out[s] = t;
-    }
-    bf16x8 gx[S::KBX], gd[S::KBD];
-    posenc_b<S::LX>(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z), h, gx);
-    posenc_b<S::LD>(d.x, d.y, d.z, h, gd);
-    // each lane reads back only its own entries: no barrier needed
-#pragma unroll
-    for (int kb = 0; kb < S::KBX; ++kb) s_gx[wv][(nt * S::KBX + kb) * 64 + lane] = __builtin_bit_cast(uint4, gx[kb]);
-#pragma unroll
-    for (int kb = 0; kb < S::KBD; ++kb) s_gd[wv][(nt * S::KBD + kb) * 64 + lane] = __builtin_bit_cast(uint4, gd[kb]);
-  }
+  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid);
 
   const float* bias = reinterpret_cast<const float*>(s_bias);
   bf16x8 xa[NTL][S::KBH], xb[NTL][S::KBH];

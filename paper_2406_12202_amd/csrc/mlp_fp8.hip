@@ -1,0 +1,354 @@
+// FP8 map evaluation of the 8x256 map: hidden-to-hidden products on
+// v_mfma_scale_f32_32x32x64_f8f6f4 with OCP E4M3 operands under per-layer
+// power-of-two scaling, encoding products on v_mfma_f32_32x32x16_bf16, both
+// accumulating in float32 (layout in maplayout_fp8.h).
+//
+// The structure follows the BF16 kernel: a workgroup of WAVES waves streams
+// the weight chunks of MPC output tiles at a time through two LDS slots with
+// direct global->LDS loads, and each wave evaluates NTL column tiles of 32
+// samples.  E4M3 activations take half the registers of bf16 ones, so two
+// column tiles fit per wave at two waves per SIMD, and every 32-byte weight
+// fragment read from LDS feeds two MFMAs.  The output of a tile is scaled by
+// 2^ea of the next layer, clamped to the E4M3 range (the conversion returns
+// NaN above it) and rounded to E4M3 in place of the bf16 epilogue.  The
+// density and colour heads act on the float32 accumulators of the last trunk
+// layer and of the direction layer in the epilogues, so they see unrounded
+// activations.  Calibration of the activation ranges (a float32 evaluation
+// with per-layer maxima) sits at the end of this file.
+#include "mfma_util.h"
+#include "maplayout_fp8.h"
+
+namespace fl {
+
+enum : int { kEpiRelu = 0, kEpiReluSigma = 1, kEpiLinear = 2, kEpiRgb = 3 };
+
+// E4M3 operands of the next layer from one finished output tile (bytes
+// 16 (mt % 2) .. + 15 of k-block mt / 2)
+template <int NTL, int K8, bool RELU>
+__device__ __forceinline__ void quantize_f8(const f32x16 (&acc)[NTL], const float q, const int mt,
+                                            i32x8 (&y)[NTL][K8]) {
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    float v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float t = acc[nt][i];
+      if (RELU) t = fmaxf(t, 0.0f);
+      t = fminf(t * q, 448.0f);
+      if (!RELU) t = fmaxf(t, -448.0f);
+      v[i] = t;
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      int d = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w], v[4 * w + 1], 0, false);
+      d = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w + 2], v[4 * w + 3], d, true);
+      y[nt][mt >> 1][4 * (mt & 1) + w] = d;
+    }
+  }
+}
+
+// partial dot products of a head with the ReLU'd float32 outputs of tile mt:
+// lane (n, h) holds rows 32 mt + 8 (v / 4) + 4 h + v % 4
+template <int NTL>
+__device__ __forceinline__ void head_partial(const f32x16 (&acc)[NTL], const float* w, const int mt, const int h,
+                                             float (&p)[NTL]) {
+  float4 wv[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) wv[g] = *reinterpret_cast<const float4*>(w + 32 * mt + 8 * g + 4 * h);
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    float s = p[nt];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      s = fmaf(wv[g].x, fmaxf(acc[nt][4 * g], 0.0f), s);
+      s = fmaf(wv[g].y, fmaxf(acc[nt][4 * g + 1], 0.0f), s);
+      s = fmaf(wv[g].z, fmaxf(acc[nt][4 * g + 2], 0.0f), s);
+      s = fmaf(wv[g].w, fmaxf(acc[nt][4 * g + 3], 0.0f), s);
+    }
+    p[nt] = s;
+  }
+}
+
+// One layer: MTO output tiles of 32 rows.  Chunk groups of MPC tiles
+// alternate between slot0 and slot1 (every layer has an even number of
+// groups).  On entry the loads of this layer's first group are in flight.
+// FIRST: the input layer (bf16 encoding products only).  Otherwise the FP8
+// products with x, then, if use_enc, the bf16 products with the encoding
+// blocks xe ([column tile][k-block][lane], KBE k-blocks).
+template <class S, int NTL, int WAVES, int MPC, int MTO, int KBE, int EPI, bool FIRST>
+__device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const float* bias_lds, const float* head_lds,
+                                         const int l, const bool use_enc, uint4* slot0, uint4* slot1,
+                                         const i32x8 (&x)[NTL][S::K8], const uint4* xe, i32x8 (&y)[NTL][S::K8],
+                                         float (&hp)[NTL][3], const int sw, const int sx, const float q,
+                                         const int wv, const int lane) {
+  static_assert(MTO % (2 * MPC) == 0, "layout");
+  const int h = lane >> 5;
+  constexpr int U8 = FIRST ? 0 : 2 * S::K8;
+  const int u_tot = U8 + ((FIRST || use_enc) ? KBE : 0);
+  const long base = S::unit_base(l);
+  const float* bl = bias_lds + S::BS::bias_base(l) + h * 16;
+#pragma unroll
+  for (int mt = 0; mt < MTO; ++mt) {
+    uint4* grp = ((mt / MPC) & 1) ? slot1 : slot0;
+    if (mt % MPC == 0) {
+      uint4* nxt = ((mt / MPC) & 1) ? slot0 : slot1;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (mt + MPC < MTO)
+        issue_blocks<WAVES>(wb, base + (long)(mt + MPC) * u_tot, MPC * u_tot, nxt, wv, lane);
+      else if (l + 1 < S::NL)
+        issue_blocks<WAVES>(wb, S::unit_base(l + 1), MPC * S::layer_units(l + 1), nxt, wv, lane);
+    }
+    const uint4* cur = grp + (mt % MPC) * u_tot * 64;
+    f32x16 binit;
+    {
+      const float4* b4 = reinterpret_cast<const float4*>(bl + mt * 32);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float4 v = b4[i];
+        binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
+      }
+    }
+    f32x16 acc[NTL];
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int kb = 0; kb < S::K8; ++kb) {
+        const uint4 lo = cur[(2 * kb) * 64 + lane], hi = cur[(2 * kb + 1) * 64 + lane];
+        const i32x8 a = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt)
+          acc[nt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, x[nt][kb], acc[nt], 0, 0, 0, sw, 0, sx);
+      }
+    }
+    if (FIRST || use_enc) {
+#pragma unroll
+      for (int kb = 0; kb < KBE; ++kb) {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, cur[(U8 + kb) * 64 + lane]);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) {
+          const bf16x8 bx = __builtin_bit_cast(bf16x8, xe[(nt * KBE + kb) * 64 + lane]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (EPI == kEpiRgb) {
+      float p[NTL];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) p[nt] = hp[nt][c];
+        head_partial<NTL>(acc, head_lds + c * S::DW, mt, h, p);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) hp[nt][c] = p[nt];
+      }
+    } else {
+      if constexpr (EPI == kEpiReluSigma) {
+        float p[NTL];
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) p[nt] = hp[nt][0];
+        head_partial<NTL>(acc, head_lds, mt, h, p);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) hp[nt][0] = p[nt];
+      }
+      quantize_f8<NTL, S::K8, EPI != kEpiLinear>(acc, q, mt, y);
+    }
+  }
+}
+
+__device__ __forceinline__ float softplus_f(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoid_f(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+template <class S, int NTL, int WAVES, int MPC>
+__global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
+  constexpr int SLOT_U = MPC * S::MAX_U;
+  constexpr int THREADS = 64 * WAVES;
+  __shared__ uint4 slot0[SLOT_U * 64];
+  __shared__ uint4 slot1[SLOT_U * 64];
+  __shared__ uint4 s_gx[WAVES][NTL * S::KBX * 64];
+  __shared__ uint4 s_gd[WAVES][NTL * S::KBD * 64];
+  __shared__ float4 s_bias[S::BIASES / 4];
+  __shared__ float4 s_heads[S::HEADS / 4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
+  issue_blocks<WAVES>(wb, 0, MPC * S::layer_units(0), slot0, wv, lane);
+  for (int i = threadIdx.x; i < S::BIASES / 4; i += THREADS) s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
+  for (int i = threadIdx.x; i < S::HEADS / 4; i += THREADS) s_heads[i] = reinterpret_cast<const float4*>(a.heads)[i];
+
+  const long tile = (long)blockIdx.x * WAVES + wv;
+  long sidx[NTL];
+  bool valid[NTL];
+  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid);
+
+  const float* bias = reinterpret_cast<const float*>(s_bias);
+  const float* heads = reinterpret_cast<const float*>(s_heads);
+  i32x8 xa[NTL][S::K8], xb[NTL][S::K8];
+  float sp[NTL][3], rp[NTL][3];   // density partial in sp[.][0]; colour partials
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sp[nt][c] = rp[nt][c] = 0.0f;
+  // input layer: bf16 products with gamma(x)
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, true>(wb, bias, heads, 0, true, slot0, slot1, xb, s_gx[wv],
+                                                               xa, sp, 0, 0, a.f8_qout[0], wv, lane);
+#pragma unroll 1
+  for (int l = 1; l < S::D - 1; ++l) {
+    dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, false>(wb, bias, heads, l, l == S::SKIP, slot0, slot1, xa,
+                                                                  s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l],
+                                                                  a.f8_qout[l], wv, lane);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+      for (int i = 0; i < S::K8; ++i) xa[nt][i] = xb[nt][i];
+  }
+  // last trunk layer: density head on its float32 outputs
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiReluSigma, false>(
+      wb, bias, heads + S::SIG_OFF, S::D - 1, S::D - 1 == S::SKIP, slot0, slot1, xa, s_gx[wv], xb, sp,
+      a.f8_sw[S::D - 1], a.f8_sx[S::D - 1], a.f8_qout[S::D - 1], wv, lane);
+  // feature layer (no activation)
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiLinear, false>(wb, bias, heads, S::D, false, slot0, slot1, xb,
+                                                                  nullptr, xa, sp, a.f8_sw[S::D], a.f8_sx[S::D],
+                                                                  a.f8_qout[S::D], wv, lane);
+  // direction layer with gamma(d); colour head on its float32 outputs
+  dense_f8<S, NTL, WAVES, MPC, S::MTD, S::KBD, kEpiRgb, false>(wb, bias, heads + S::RGB_OFF, S::D + 1, true, slot0,
+                                                                slot1, xa, s_gd[wv], xb, rp, a.f8_sw[S::D + 1],
+                                                                a.f8_sx[S::D + 1], 1.0f, wv, lane);
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+    float zs = sp[nt][0];
+    zs += __shfl_xor(zs, 32, 64);
+    const float sigma = softplus_f(zs + heads[S::SIG_OFF + S::W]);
+    float rgb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float z = rp[nt][c];
+      z += __shfl_xor(z, 32, 64);
+      rgb[c] = sigmoid_f(z + heads[S::RGB_OFF + 3 * S::DW + c]);
+    }
+    if (valid[nt] && h == 0) a.out[sidx[nt]] = make_float4(sigma, rgb[0], rgb[1], rgb[2]);
+  }
+}
+
+template <class S, int NTL, int WAVES, int MPC>
+hipError_t launch_mlp_fp8_t(const MlpArgs& a, hipStream_t st) {
+  constexpr int SAMPLES = 32 * NTL * WAVES;
+  const long blocks = (a.n_samples + SAMPLES - 1) / SAMPLES;
+  hipLaunchKernelGGL((k_mlp_fp8<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, st, a);
+  return hipGetLastError();
+}
+
+#ifndef FL_FP8_NTL
+#define FL_FP8_NTL 2
+#endif
+#ifndef FL_FP8_WAVES
+#define FL_FP8_WAVES 8
+#endif
+#ifndef FL_FP8_MPC
+#define FL_FP8_MPC 2
+#endif
+
+hipError_t launch_mlp_fp8(int map_kind, const MlpArgs& a, hipStream_t st) {
+  if (a.n_samples <= 0) return hipSuccess;
+  if (map_kind != kMapNerf) return hipErrorInvalidValue;
+  return launch_mlp_fp8_t<NerfMapF8, FL_FP8_NTL, FL_FP8_WAVES, FL_FP8_MPC>(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// calibration: float32 map evaluation, 16 samples per workgroup of 256
+// threads; thread j computes output j of every layer for the 16 samples,
+// reading transposed weights (coalesced across threads) and activations from
+// LDS as [feature][sample] (broadcast reads)
+constexpr int kCalSamples = 16;
+constexpr int kCalThreads = 256;
+
+template <class S>
+__global__ __launch_bounds__(kCalThreads) void k_calibrate(const CalibArgs a) {
+  constexpr int IN_X = 3 + 6 * S::LX, IN_D = 3 + 6 * S::LD;
+  constexpr int MAXIN = S::W + (IN_X > IN_D ? IN_X : IN_D);
+  __shared__ float s_in[MAXIN][kCalSamples];     // current layer input
+  __shared__ float s_ex[IN_X][kCalSamples];      // gamma(x)
+  __shared__ float s_ed[IN_D][kCalSamples];      // gamma(d)
+  __shared__ float s_red[kCalThreads];
+  const int tid = threadIdx.x;
+  const long s0 = (long)blockIdx.x * kCalSamples;
+  const long n_samples = (long)a.n_rays * a.spr;
+  // encodings: thread tid < 16 * 3 handles (sample, coordinate)
+  for (int e = tid; e < kCalSamples * 3; e += kCalThreads) {
+    const int sl = e / 3, c = e % 3;
+    long s = s0 + sl;
+    if (s >= n_samples) s = n_samples - 1;
+    const int ray = (int)(s / a.spr), k = (int)(s - (long)ray * a.spr);
+    const float t = a.near_ + ((float)k + 0.5f) * a.dt;
+    const float dc = a.d[3 * ray + c];
+    const float xc = fmaf(t, dc, a.o[3 * ray + c]);
+    s_ex[c][sl] = xc;
+    s_ed[c][sl] = dc;
+    for (int b = 0; b < S::LX; ++b) {
+      float sn, cs;
+      sincospif(ldexpf(xc, b), &sn, &cs);
+      s_ex[3 + 6 * b + c][sl] = sn;
+      s_ex[3 + 6 * b + 3 + c][sl] = cs;
+    }
+    for (int b = 0; b < S::LD; ++b) {
+      float sn, cs;
+      sincospif(ldexpf(dc, b), &sn, &cs);
+      s_ed[3 + 6 * b + c][sl] = sn;
+      s_ed[3 + 6 * b + 3 + c][sl] = cs;
+    }
+  }
+  __syncthreads();
+  const float* w = a.wt;
+  for (int l = 0; l < S::NL; ++l) {
+    // input: [hidden (W) | encoding] per layer kind
+    const int n_h = l == 0 ? 0 : S::W;
+    const int n_e = l == 0 ? IN_X : (l == S::SKIP ? IN_X : (l == S::D + 1 ? IN_D : 0));
+    const int nin = n_h + n_e;
+    const int nout = l == S::D + 1 ? S::DW : S::W;
+    const bool relu = l != S::D;
+    float acc[kCalSamples];
+    const float bj = tid < nout ? w[(long)nin * nout + tid] : 0.0f;
+#pragma unroll
+    for (int s = 0; s < kCalSamples; ++s) acc[s] = bj;
+    if (tid < nout) {
+      for (int k = 0; k < nin; ++k) {
+        const float wk = w[(long)k * nout + tid];
+        const float* xin = k < n_h ? s_in[k] : (l == S::D + 1 ? s_ed[k - n_h] : s_ex[k - n_h]);
+#pragma unroll
+        for (int s = 0; s < kCalSamples; ++s) acc[s] = fmaf(wk, xin[s], acc[s]);
+      }
+    }
+    float m = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kCalSamples; ++s) {
+      if (relu) acc[s] = fmaxf(acc[s], 0.0f);
+      if (s0 + s < n_samples) m = fmaxf(m, fabsf(acc[s]));
+    }
+    __syncthreads();   // every thread has read this layer's input
+    if (tid < nout)
+#pragma unroll
+      for (int s = 0; s < kCalSamples; ++s) s_in[tid][s] = acc[s];
+    if (l <= S::D) {
+      s_red[tid] = tid < nout ? m : 0.0f;
+      __syncthreads();
+      for (int o = kCalThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) s_red[tid] = fmaxf(s_red[tid], s_red[tid + o]);
+        __syncthreads();
+      }
+      if (tid == 0) atomicMax(a.amax + l, __float_as_uint(s_red[0]));
+    }
+    __syncthreads();
+    w += (long)nin * nout + nout;
+  }
+}
+
+hipError_t launch_calibrate_fp8(const CalibArgs& a, hipStream_t st) {
+  const long n = (long)a.n_rays * a.spr;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_calibrate<NerfMapF8>, dim3((unsigned)((n + kCalSamples - 1) / kCalSamples)),
+                     dim3(kCalThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fl

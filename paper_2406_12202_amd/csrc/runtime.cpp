@@ -15,17 +15,18 @@
 #include "kernels.h"
 #include "maplayout.h"
 #include "maplayout_bf16.h"
+#include "maplayout_fp8.h"
 
 using namespace fl;
 
 namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
-                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_COUNT };
+                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
-                                     "pose_estimate"};
+                                     "pose_estimate", "fp8_calibration"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -47,6 +48,14 @@ struct loc_ctx {
   void* wblocks = nullptr;        // BF16 weight chunks
   float* bias_b = nullptr;        // BF16 path biases
   float* heads_b = nullptr;       // BF16 path heads
+  // FP8 path: canonical parameters (kept for packing after calibration),
+  // E4M3/BF16 weight units, natural-order heads, per-layer exponents
+  std::vector<float> params_host;
+  void* wunits = nullptr;
+  float* heads_f8 = nullptr;
+  bool f8_ready = false;
+  int f8_ew[12] = {}, f8_ea[12] = {};
+  float f8_amax[12] = {};
   // workspace
   DevBuf<float4> ray_o, ray_d, obs, out_c, out_f, rgba;
   DevBuf<float2> fe;
@@ -322,7 +331,119 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
 }
 
 hipError_t mlp_launch(loc_ctx* c, const MlpArgs& a) {
+  if (c->desc.precision == LOC_FP8_E4M3) {
+    MlpArgs b = a;
+    b.wblocks = c->wunits;
+    b.heads = c->heads_f8;
+    for (int l = 0; l < 12; ++l) {
+      b.f8_sw[l] = 127 - c->f8_ew[l];
+      b.f8_sx[l] = 127 - c->f8_ea[l];
+      b.f8_qout[l] = (l + 1 < 12) ? std::ldexp(1.0f, c->f8_ea[l + 1]) : 1.0f;
+    }
+    return launch_mlp_fp8(c->kind, b, c->stream);
+  }
   return c->desc.precision == LOC_BF16 ? launch_mlp_bf16(c->kind, a, c->stream) : launch_mlp(c->kind, a, c->stream);
+}
+
+// OCP E4M3 (FN) encoding, round to nearest even, saturating at 448; the
+// format: 1 sign, 4 exponent (bias 7), 3 mantissa bits, subnormals below
+// 2^-6, no infinities, 0x7f / 0xff NaN
+uint8_t to_e4m3(double v) {
+  if (std::isnan(v)) return 0x7f;
+  const uint8_t sgn = std::signbit(v) ? 0x80 : 0;
+  const double a = std::fabs(v);
+  if (a == 0.0) return sgn;
+  if (a >= 464.0) return sgn | 0x7e;
+  int e = (int)std::floor(std::log2(a));
+  if (e < -6) e = -6;
+  double m = std::nearbyint(a / std::ldexp(1.0, e - 3));   // quantum 2^(e-3), m in [0, 16]
+  if (m >= 16.0) { e += 1; m = 8.0; }
+  if (m < 8.0) return sgn | (uint8_t)m;                    // subnormal (e == -6)
+  return sgn | (uint8_t)((e + 7) << 3) | (uint8_t)(m - 8.0);
+}
+
+// exponent e with amax * 2^e <= 448, 2^e as large as possible
+int fp8_exponent(double amax) {
+  if (!(amax > 0.0) || !std::isfinite(amax)) return 0;
+  int e = (int)std::floor(std::log2(448.0 / amax));
+  if (std::ldexp(amax, e) > 448.0) --e;
+  return e < -60 ? -60 : (e > 60 ? 60 : e);
+}
+
+// E4M3 hidden-weight units and BF16 encoding units (maplayout_fp8.h);
+// fills ew[l] for l = 1..NL-1
+template <class S>
+std::vector<uint8_t> pack_map_fp8(const loc_map_desc& d, int* ew) {
+  Canon cn;
+  canon_split(d, cn);
+  std::vector<uint8_t> U((size_t)S::UNITS * 1024, 0);
+  for (int l = 0; l < S::NL; ++l) {
+    const int ci = l < S::D ? l : l + 1;
+    const float* W = cn.W[ci];
+    const int nin = cn.nin[ci], nout = cn.nout[ci];
+    const int n_h = l == 0 ? 0 : S::W;
+    const int L = (l == S::D + 1) ? S::LD : S::LX;
+    int e = 0;
+    if (l > 0) {
+      double am = 0.0;
+      for (int r = 0; r < nout; ++r)
+        for (int k = 0; k < n_h; ++k) am = std::fmax(am, std::fabs((double)W[(long)r * nin + k]));
+      e = fp8_exponent(am);
+      ew[l] = e;
+    }
+    const int u8 = S::fp8_units(l), ue = S::enc_units(l);
+    for (int mt = 0; mt < S::layer_mt(l); ++mt) {
+      const long ub = S::unit_base(l) + (long)mt * S::layer_units(l);
+      for (int lane = 0; lane < 64; ++lane) {
+        const int row = 32 * mt + lane % 32, h = lane / 32;
+        for (int kb = 0; kb < u8 / 2; ++kb)
+          for (int j = 0; j < 32; ++j) {
+            const int col = chain_feature_f8(kb, h, j);
+            const long unit = ub + 2 * kb + j / 16;
+            U[(size_t)(unit * 64 + lane) * 16 + j % 16] = to_e4m3(std::ldexp((double)W[(long)row * nin + col], e));
+          }
+        for (int kb = 0; kb < ue; ++kb)
+          for (int q = 0; q < 8; ++q) {
+            const int f = posenc_feature_b(L, kb, h, q);
+            const uint16_t v = f >= 0 ? to_bf16(W[(long)row * nin + n_h + f]) : 0;
+            const long unit = ub + u8 + kb;
+            std::memcpy(&U[(size_t)(unit * 64 + lane) * 16 + 2 * q], &v, 2);
+          }
+      }
+    }
+  }
+  return U;
+}
+
+// natural-order heads of the FP8 path: density (W + bias), colour (3 x DW + 3)
+template <class S>
+std::vector<float> pack_heads_fp8(const loc_map_desc& d) {
+  Canon cn;
+  canon_split(d, cn);
+  std::vector<float> H((size_t)S::HEADS, 0.0f);
+  for (int k = 0; k < S::W; ++k) H[S::SIG_OFF + k] = cn.W[S::D][k];
+  H[S::SIG_OFF + S::W] = cn.b[S::D][0];
+  const int ci = (int)cn.W.size() - 1;
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < S::DW; ++k) H[S::RGB_OFF + c * S::DW + k] = cn.W[ci][c * S::DW + k];
+  for (int c = 0; c < 3; ++c) H[S::RGB_OFF + 3 * S::DW + c] = cn.b[ci][c];
+  return H;
+}
+
+// per execution-order layer: transposed weights (in x out), then the bias
+template <class S>
+std::vector<float> transpose_layers(const loc_map_desc& d) {
+  Canon cn;
+  canon_split(d, cn);
+  std::vector<float> T;
+  for (int l = 0; l < S::NL; ++l) {
+    const int ci = l < S::D ? l : l + 1;
+    const int nin = cn.nin[ci], nout = cn.nout[ci];
+    for (int k = 0; k < nin; ++k)
+      for (int r = 0; r < nout; ++r) T.push_back(cn.W[ci][(long)r * nin + k]);
+    for (int r = 0; r < nout; ++r) T.push_back(cn.b[ci][r]);
+  }
+  return T;
 }
 
 bool same_shape(const loc_map_desc& d, int W, int D, int skip, int lx, int ld, int dw) {
@@ -357,12 +478,13 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
   if (!(d->near_ >= 0.0f && d->far_ > d->near_)) return LOC_E_ARG;
   if (d->n_coarse < 1 || d->n_coarse > 256 || d->n_fine < 0 || d->n_fine > 256) return LOC_E_ARG;
   if (!(d->alpha > 0.0f && d->alpha < 0.5f) || !(d->tau > 0.0f)) return LOC_E_ARG;
-  if (d->precision != LOC_FP32 && d->precision != LOC_BF16) return LOC_E_UNSUPPORTED;
+  if (d->precision != LOC_FP32 && d->precision != LOC_BF16 && d->precision != LOC_FP8_E4M3) return LOC_E_UNSUPPORTED;
   int kind;
   long macs, total;
   if (same_shape(*d, 64, 4, -1, 6, 2, 0)) { kind = kMapSmall; macs = SmallMap::macs(); total = SmallMap::TOTAL; }
   else if (same_shape(*d, 256, 8, 5, 10, 4, 128)) { kind = kMapNerf; macs = NerfMap::macs(); total = NerfMap::TOTAL; }
   else return LOC_E_UNSUPPORTED;
+  if (d->precision == LOC_FP8_E4M3 && kind != kMapNerf) return LOC_E_UNSUPPORTED;
   Canon cn;
   if (!canon_split(*d, cn)) return LOC_E_ARG;
   loc_ctx* c = new (std::nothrow) loc_ctx();
@@ -383,6 +505,16 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
     std::vector<float> P = kind == kMapSmall ? pack_map<SmallMap>(*d) : pack_map<NerfMap>(*d);
     ok = hipMalloc(&c->weights, sizeof(float) * total) == hipSuccess &&
          hipMemcpy(c->weights, P.data(), sizeof(float) * total, hipMemcpyHostToDevice) == hipSuccess;
+  } else if (d->precision == LOC_FP8_E4M3) {
+    // biases as in the BF16 layout; weights are packed by loc_calibrate_fp8
+    PackedB P = pack_map_bf16<NerfMapB>(*d);
+    std::vector<float> H = pack_heads_fp8<NerfMapF8>(*d);
+    c->params_host.assign(d->params, d->params + d->n_params);
+    ok = hipMalloc(&c->bias_b, P.bias.size() * 4) == hipSuccess &&
+         hipMalloc(&c->heads_f8, H.size() * 4) == hipSuccess &&
+         hipMalloc(&c->wunits, (size_t)NerfMapF8::UNITS * 1024) == hipSuccess &&
+         hipMemcpy(c->bias_b, P.bias.data(), P.bias.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(c->heads_f8, H.data(), H.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
   } else {
     PackedB P = kind == kMapSmall ? pack_map_bf16<SmallMapB>(*d) : pack_map_bf16<NerfMapB>(*d);
     ok = hipMalloc(&c->wblocks, P.blocks.size() * 2) == hipSuccess &&
@@ -409,6 +541,8 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->wblocks);
   hipFree(c->bias_b);
   hipFree(c->heads_b);
+  hipFree(c->wunits);
+  hipFree(c->heads_f8);
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
@@ -429,6 +563,8 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
     return fail(c, LOC_E_ARG, "null pointer argument");
   if (inv_R != 1 && inv_R != 2 && inv_R != 4 && inv_R != 8) return fail(c, LOC_E_ARG, "inv_R must be 1, 2, 4 or 8");
   if (c->fine_mode == 1 && !c->prop) return fail(c, LOC_E_STATE, "proposal mode without proposal parameters");
+  if (c->desc.precision == LOC_FP8_E4M3 && !c->f8_ready)
+    return fail(c, LOC_E_STATE, "FP8 map used before loc_calibrate_fp8");
   if (cam->W <= 0 || cam->H <= 0 || cam->W % inv_R || cam->H % inv_R)
     return fail(c, LOC_E_ARG, "image %dx%d not divisible by level factor %d", cam->W, cam->H, inv_R);
   if (!(cam->fx > 0 && cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
@@ -702,6 +838,8 @@ loc_status loc_teacher_histograms(loc_ctx* c, const float* ray_o, const float* r
   if (!ray_o || !ray_d || !hist) return fail(c, LOC_E_ARG, "null pointer argument");
   if (n < 1 || n > (1 << 24)) return fail(c, LOC_E_ARG, "n out of range");
   if (n_fine < 0 || n_fine > 256) return fail(c, LOC_E_ARG, "n_fine must be in [0, 256]");
+  if (c->desc.precision == LOC_FP8_E4M3 && !c->f8_ready)
+    return fail(c, LOC_E_STATE, "FP8 map used before loc_calibrate_fp8");
   const loc_map_desc& d = c->desc;
   const int Sc = d.n_coarse, Sf = n_fine;
   loc_status s;
@@ -942,6 +1080,76 @@ loc_status loc_pose_estimate(loc_ctx* c, const double* pose, const double* weigh
   if (!pose || !weight || !est) return fail(c, LOC_E_ARG, "null pointer argument");
   if (N < 1 || N > (1 << 24)) return fail(c, LOC_E_ARG, "N must be in [1, 2^24]");
   return timed(c, K_ESTIMATE, 0, 104.0 * N, [&] { return launch_pose_estimate(pose, weight, N, est, c->flags, c->stream); });
+}
+
+
+loc_status loc_calibrate_fp8(loc_ctx* c, const float* o, const float* d, int n_rays) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (c->desc.precision != LOC_FP8_E4M3) return fail(c, LOC_E_STATE, "context precision is not FP8");
+  if (!o || !d) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n_rays < 1 || n_rays > (1 << 20)) return fail(c, LOC_E_ARG, "n_rays must be in [1, 2^20]");
+  using S = NerfMapF8;
+  loc_map_desc pd = c->desc;
+  pd.params = c->params_host.data();
+  std::vector<float> T = transpose_layers<S>(pd);
+  float* wt = nullptr;
+  unsigned* am = nullptr;
+  auto cleanup = [&] { hipFree(wt); hipFree(am); };
+  if (hipMalloc(&wt, T.size() * 4) != hipSuccess || hipMalloc(&am, 16 * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(c, LOC_E_OOM, "calibration buffers");
+  }
+  CalibArgs ca{};
+  ca.o = o;
+  ca.d = d;
+  ca.n_rays = n_rays;
+  ca.spr = c->desc.n_coarse;
+  ca.near_ = c->desc.near_;
+  ca.dt = (c->desc.far_ - c->desc.near_) / (float)c->desc.n_coarse;
+  ca.wt = wt;
+  ca.amax = am;
+  unsigned h_am[16] = {};
+  hipError_t e = hipMemcpyAsync(wt, T.data(), T.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(am, 0, 16 * sizeof(unsigned), c->stream);
+  if (e == hipSuccess) {
+    loc_status s = timed(c, K_CALIB, 2.0 * (double)c->macs * n_rays * ca.spr, 0.0,
+                         [&] { return launch_calibrate_fp8(ca, c->stream); });
+    if (s) { hipStreamSynchronize(c->stream); cleanup(); return s; }
+    e = hipMemcpyAsync(h_am, am, sizeof h_am, hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) return fail(c, LOC_E_HIP, "calibration: %s", hipGetErrorString(e));
+  // activation exponent of layer l's input = output range of layer l - 1
+  for (int l = 0; l < 12; ++l) { c->f8_ea[l] = 0; c->f8_ew[l] = 0; c->f8_amax[l] = 0.0f; }
+  for (int l = 0; l <= S::D; ++l) {
+    float v;
+    std::memcpy(&v, &h_am[l], 4);
+    c->f8_amax[l] = v;
+    c->f8_ea[l + 1] = fp8_exponent(v);
+  }
+  std::vector<uint8_t> U = pack_map_fp8<S>(pd, c->f8_ew);
+  e = hipMemcpyAsync(c->wunits, U.data(), U.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, LOC_E_HIP, "FP8 weight upload: %s", hipGetErrorString(e));
+  c->f8_ready = true;
+  return LOC_OK;
+}
+
+loc_status loc_fp8_scales(loc_ctx* c, int* ew, int* ea, float* amax, int n) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (c->desc.precision != LOC_FP8_E4M3) return fail(c, LOC_E_STATE, "context precision is not FP8");
+  if (!c->f8_ready) return fail(c, LOC_E_STATE, "no calibration has run");
+  if (n < NerfMapF8::NL) return fail(c, LOC_E_ARG, "n must be at least %d", NerfMapF8::NL);
+  for (int l = 0; l < NerfMapF8::NL; ++l) {
+    if (ew) ew[l] = c->f8_ew[l];
+    if (ea) ea[l] = c->f8_ea[l];
+    if (amax) amax[l] = c->f8_amax[l];
+  }
+  return LOC_OK;
 }
 
 }  // extern "C"

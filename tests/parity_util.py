@@ -5,6 +5,7 @@ import math
 import numpy as np
 
 from oracle import mcl
+from oracle import render as rd
 from paper_2406_12202_amd import synth
 
 
@@ -57,3 +58,19 @@ def stats(name, a, b):
 def frac_over(a, b, tol):
     d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))
     return float((d > tol).mean())
+
+
+def gt_observation(spec, params, cam, gt, B, seed, iterations, base_image, n_coarse=64, n_fine=128):
+    """Observation whose query pixels for iterations 0..iterations-1 (level 1)
+    hold the oracle's render of the map from pose gt (64 + 128 hierarchical
+    samples, no jitter); every other pixel keeps base_image."""
+    W, H, fx, fy, cx, cy = cam
+    s = dict(spec, n_coarse=n_coarse, n_fine=n_fine, jitter=0)
+    P = rd.unpack(s, params)
+    img = np.array(base_image, dtype=np.float32, copy=True)
+    pix = sorted({p for it in range(iterations) for p in mcl.pixel_indices(seed, it, B, W * H)})
+    rays = mcl.particle_rays(gt, pix, W, (fx, fy, cx, cy))
+    r = mcl.render_rays(s, P, rays, [(0, j) for j in range(len(pix))], 0, 0)
+    for p, c in zip(pix, r["C"]):
+        img[p // W, p % W] = c
+    return img

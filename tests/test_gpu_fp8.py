@@ -1,0 +1,225 @@
+"""GPU tests of the FP8 map path (8x256 map; hidden-to-hidden products in OCP
+E4M3 under per-layer power-of-two amax scaling, encoding products in bf16,
+float32 accumulation and heads) against the FP64 oracle.
+
+FP8 approximates the map on purpose.  E4M3 keeps 3 mantissa bits, a unit
+roundoff of 2^-4 against bf16's 2^-8, so the per-ray bars are the BF16 path's
+scaled by 16:
+  colour C            : p99 <= 0.16, p50 <= 3e-2
+  uncertainty F       : |dF| <= EPS_TAU (|ln(1-alpha)| / sigma_trans +
+                        |ln alpha| / sigma_opaque) + 2e-3 for 95% of rays with
+                        EPS_TAU = 1.6 (16 x the bf16 value); no separate
+                        median bar: on the forward-facing workload many rays
+                        cross Eq. 5's levels where the density is low, and the
+                        conditioning bound is what scales with that
+  log-likelihood l    : within the bound propagated from the per-ray errors
+                        and consistent with the GPU's own per-ray E and F
+The requirement on the method's output is the pose: over ten filter
+iterations of the large forward-facing workload, run in lockstep (both sides
+weight the same particle set, the oracle's resampling carries it on), the
+pose read out from the GPU's weights stays within 1 cm and 0.5 degree of the
+oracle's.  Calibration maxima are checked against a float64 forward pass.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mcl, se3
+from oracle import render as rd
+from paper_2406_12202_amd import synth
+from parity_util import ctx, gt_observation, inputs, run_gpu, run_oracle, stats
+
+pytestmark = pytest.mark.gpu
+
+EPS_TAU = 1.6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _dev(x, torch):
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _calibrated(s, p, workload, seed, torch, n_poses=1024):
+    c = ctx(s, p, "fp8")
+    cam = synth.camera(workload)
+    tp = _dev(synth.training_poses(workload, seed, n_poses), torch)
+    O, D = c.loc_cast_rays(cam, 1, 16, tp, seed=seed, iter=0)
+    c.loc_calibrate_fp8(O, D)
+    return c, O, D
+
+
+def _layer_maxima(s, p, O, D):
+    """Largest |output| per layer (trunk 0..D-1, feature) at the midpoints of
+    the coarse strata, in float64 from the oracle's unpacked parameters."""
+    P = rd.unpack(s, p)
+    Sc = s["n_coarse"]
+    t = s["near"] + (np.arange(Sc) + 0.5) * (s["far"] - s["near"]) / Sc
+    x = (O[:, None, :] + t[None, :, None] * D[:, None, :]).reshape(-1, 3)
+    gx = rd.posenc(x, s["L_xyz"])
+    h = gx
+    out = []
+    for l in range(s["n_layers"]):
+        if l == s["skip_layer"] and l > 0:
+            h = np.concatenate([h, gx], axis=-1)
+        W, b = P["h%d" % l]
+        h = np.maximum(h @ W.T + b, 0.0)
+        out.append(np.abs(h).max())
+    Wf, bf = P["feature"]
+    out.append(np.abs(h @ Wf.T + bf).max())
+    return np.array(out)
+
+
+def _check(g, o, alpha=0.05):
+    rC = stats("C", g["C"], o["C"])
+    stats("F", g["F"], o["F"])
+    stats("A", g["A"], o["A"])
+    stats("loglik", g["loglik"], o["loglik"])
+    dw = np.abs(g["weight"] - o["weight"])
+    print("per-particle weight: max |dw| %.3e (max w %.3e)" % (dw.max(), o["weight"].max()))
+    assert np.allclose(g["pose"].reshape(-1, 12), o["pose"].reshape(-1, 12), atol=1e-12, rtol=0)
+    assert rC["p99"] <= 0.16 and rC["p50"] <= 3e-2
+    kt = np.where(np.isnan(o["sig_trans"]), 0.0, abs(math.log1p(-alpha)) / o["sig_trans"])
+    ko = np.where(np.isnan(o["sig_opaque"]), 0.0, abs(math.log(alpha)) / o["sig_opaque"])
+    dF = np.abs(g["F"] - o["F"])
+    inside = (dF <= EPS_TAU * (kt + ko) + 2e-3).mean()
+    print("F within conditioning bound: %.4f of %d rays" % (inside, dF.size))
+    assert inside >= 0.95
+    EFg = (g["E"] * g["F"]).astype(np.float64)
+    EFo = o["E"] * o["F"]
+    B = EFg.shape[1]
+    Sg, So = EFg.sum(1), EFo.sum(1)
+    assert np.allclose(g["loglik"], 4 * (math.log(B) - np.log(np.maximum(Sg, 1e-12))), atol=1e-4, rtol=0)
+    assert np.all(np.abs(g["loglik"] - o["loglik"]) <= 4 * np.abs(EFg - EFo).sum(1) / np.minimum(Sg, So) + 1e-3)
+
+
+def test_fp8_needs_calibration(torch_dev):
+    torch = torch_dev
+    s, p, cam, poses, img = inputs("nerf", 61, N=2)
+    c = ctx(s, p, "fp8")
+    with pytest.raises(RuntimeError, match="calibrate"):
+        run_gpu(c, img, cam, 1, 8, poses)
+    with pytest.raises(RuntimeError):
+        c.loc_fp8_scales()
+
+
+def test_fp8_calibration_maxima_and_scales(torch_dev):
+    torch = torch_dev
+    s, p, _, _, _ = inputs("nerf", 62)
+    c, O, D = _calibrated(s, p, "nerf", 62, torch, n_poses=64)
+    ew, ea, am = c.loc_fp8_scales()
+    ref = _layer_maxima(s, p, O.cpu().numpy().astype(np.float64), D.cpu().numpy().astype(np.float64))
+    print("amax gpu", np.array(am)); print("amax f64", ref); print("ew", ew, "ea", ea)
+    assert np.allclose(am, ref, rtol=1e-4, atol=0)
+    for l in range(1, 10):
+        x = ref[l - 1] * 2.0 ** ea[l]
+        assert 224.0 < x <= 448.0, (l, x)
+    P = rd.unpack(s, p)
+    names = ["h%d" % l for l in range(8)] + ["feature", "dir"]
+    for l in range(1, 10):
+        W, _ = P[names[l]]
+        wmax = np.abs(W[:, :256]).max() * 2.0 ** ew[l]
+        assert 224.0 < wmax <= 448.0, (l, wmax)
+
+
+def test_fp8_update_matches_oracle(torch_dev):
+    """Hierarchical 64 + 128 on the NeRF-sized map, 12 particles x 32 rays."""
+    torch = torch_dev
+    s, p, cam, poses, img = inputs("nerf", 63, N=12)
+    c, _, _ = _calibrated(s, p, "nerf", 63, torch)
+    kw = dict(seed=4, it=2)
+    g = run_gpu(c, img, cam, 1, 32, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 32, poses, **kw)
+    _check(g, o)
+
+
+def test_fp8_proposal_update_matches_oracle(torch_dev):
+    """64 coarse + 32 proposal-placed samples (the large workload's sampling),
+    with motion noise, ragged ray count."""
+    torch = torch_dev
+    s = synth.spec("large")
+    p = synth.map_params(s, 64)
+    c, _, _ = _calibrated(s, p, "large", 64, torch)
+    theta = synth.proposal_params(64)
+    c.loc_set_proposal(theta)
+    c.loc_set_fine_mode(1)
+    cam = synth.camera("large")
+    poses = synth.particles("large", 64, N=10)
+    img = synth.observation("large", 64)
+    kw = dict(sigma_t=0.02, sigma_r=math.radians(1.0), seed=6, it=1)
+    g = run_gpu(c, img, cam, 1, 29, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 29, poses, proposal=theta, **kw)
+    _check(g, o)
+
+
+def test_fp8_full_size_sampled_particles(torch_dev):
+    """The large workload at full size (2000 particles x 256 rays x (64 + 32)
+    samples): weights normalise, and three sampled particles' renders and
+    log-likelihoods match the oracle's to the per-ray bars."""
+    torch = torch_dev
+    s = synth.spec("large")
+    p = synth.map_params(s, 65)
+    c, _, _ = _calibrated(s, p, "large", 65, torch)
+    theta = synth.proposal_params(65)
+    c.loc_set_proposal(theta)
+    c.loc_set_fine_mode(1)
+    cam = synth.camera("large")
+    poses = synth.particles("large", 65)
+    img = synth.observation("large", 65)
+    kw = dict(sigma_t=0.02, sigma_r=math.radians(1.0), seed=7, it=0)
+    g = run_gpu(c, img, cam, 1, 256, poses, **kw)
+    assert g["flags"] == 0 and np.isfinite(g["loglik"]).all()
+    assert abs(g["weight"].sum() - 1.0) <= 1e-12
+    sub = [0, 977, 1999]
+    o = run_oracle(s, p, img, cam, 1, 256, poses, subset=sub, proposal=theta, **kw)
+    gs = {k: g[k][sub] for k in ("C", "A", "F", "E", "loglik", "pose")}
+    gs["weight"] = np.exp(g["loglik"][sub] - g["loglik"][sub].max())
+    gs["weight"] /= gs["weight"].sum()
+    _check(gs, o)
+
+
+def test_fp8_lockstep_pose_large_workload(torch_dev):
+    """Ten iterations of the large workload's filter (sigma_t = 0.02 m,
+    sigma_r = 1 deg, O = I, 64 + 32 proposal-placed samples, trained
+    proposal) on 24 particles x 256 rays against an observation whose query
+    pixels are the oracle's render from the true pose.  Both sides weight the
+    same particle set; the oracle's resampling carries it to the next
+    iteration.  The GPU's pose estimate stays within 1 cm / 0.5 deg of the
+    oracle's."""
+    torch = torch_dev
+    wl, seed, N, B, iters = "large", 66, 24, 256, 10
+    s = synth.spec(wl)
+    p = synth.map_params(s, seed)
+    cam = synth.camera(wl)
+    c, O, D = _calibrated(s, p, wl, seed, torch)
+    # proposal trained on the map's own compositing weights
+    T = c.loc_teacher_histograms(O, D, 128, seed=seed, iter=1)
+    c.loc_set_proposal(synth.proposal_params(seed))
+    c.loc_train_proposal(O, D, T, 4096, 1500, lr=2e-3)
+    theta = c.loc_get_proposal()
+    c.loc_set_fine_mode(1)
+    gt = synth.gt_pose(wl, seed)
+    img = gt_observation(s, p, cam, gt, B, seed, iters, synth.observation(wl, seed))
+    X = synth.particles(wl, seed, N=N)
+    sig_t, sig_r = 0.02, math.radians(1.0)
+    worst = (0.0, 0.0)
+    for it in range(iters):
+        g = run_gpu(c, img, cam, 1, B, X, sigma_t=sig_t, sigma_r=sig_r, seed=seed, it=it)
+        o = run_oracle(s, p, img, cam, 1, B, X, sigma_t=sig_t, sigma_r=sig_r, seed=seed, it=it, proposal=theta)
+        assert np.allclose(g["pose"].reshape(N, 12), o["pose"].reshape(N, 12), atol=1e-12, rtol=0)
+        est_g = c.loc_pose_estimate(_dev(g["pose"], torch), _dev(g["weight"], torch)).cpu().numpy()
+        est_o = se3.pose_estimate(o["pose"], o["weight"])
+        dt, dr = se3.pose_errors(est_g, est_o)
+        gt_t, gt_r = se3.pose_errors(est_o, gt)
+        print("iter %d: GPU vs oracle %.4f m %.4f deg | max |dw| %.3e | oracle vs truth %.3f m %.2f deg"
+              % (it, dt, dr, np.abs(g["weight"] - o["weight"]).max(), gt_t, gt_r), flush=True)
+        worst = (max(worst[0], dt), max(worst[1], dr))
+        X = o["pose"][mcl.resample(o["weight"], N, seed, it)]
+    print("worst over iterations: %.4f m %.4f deg (final %.4f m %.4f deg)" % (worst + (dt, dr)))
+    assert dt <= 0.01 and dr <= 0.5
