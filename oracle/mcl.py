@@ -268,3 +268,53 @@ def resample(weight, n_out, seed, it):
                 lo = mid + 1
         out.append(lo)
     return out
+
+
+# ----------------------------------------------------------------------------
+# coarse-to-fine levels with 1-sigma rejection (Alg. 1 with per-iteration
+# R_t, B_t, N_t; Sec. III-C)
+
+def reject_1sigma(uncert, loglik):
+    """Rejection at a 1-sigma uncertainty threshold (a reading; the paper's own
+    rejection is the soft weighting of Eq. 6): with U_i the mean F of particle
+    i's rays, particles with U_i > mean(U) + std(U) get log-likelihood -inf
+    (weight 0).  mean and the population standard deviation run over the
+    particles with finite U and finite l; the others are rejected too."""
+    U = np.asarray(uncert, dtype=np.float64)
+    ll = np.asarray(loglik, dtype=np.float64).copy()
+    ok = np.isfinite(U) & np.isfinite(ll)
+    if not ok.any():
+        return np.full_like(ll, -np.inf), np.ones(ll.shape, dtype=bool)
+    mu = U[ok].mean()
+    sd = math.sqrt(((U[ok] - mu) ** 2).mean())
+    rejected = ~ok | (U > mu + sd)
+    ll[rejected] = -np.inf
+    return ll, rejected
+
+
+def update_levels(spec, params, image, cam, levels, poses, motion=None, sigma_t=0.0, sigma_r=0.0,
+                  seed=0, it=0, reject=True, proposal=None):
+    """One coarse-to-fine update: for level L = 0, 1, ... with (inv_R, B,
+    n_out) = levels[L], the particle set is predicted, weighted with B rays
+    at scale 1/inv_R (update_particles, iteration counter it + L), optionally
+    1-sigma rejected, normalised, and resampled to n_out particles (iteration
+    counter it + L) that carry on to the next level.  Returns the per-level
+    records and the final resampled poses; the pose read-out is that of the
+    last level's weighted set."""
+    X = np.asarray(poses, dtype=np.float64).reshape(-1, 3, 4)
+    recs = []
+    for L, (inv_R, B, n_out) in enumerate(levels):
+        o = update_particles(spec, params, image, cam, inv_R, B, X, motion, sigma_t, sigma_r, seed, it + L,
+                             proposal=proposal)
+        ll = o["loglik"]
+        rejected = np.zeros(ll.shape, dtype=bool)
+        if reject:
+            ll, rejected = reject_1sigma(o["uncert"], o["loglik"])
+        w = normalise(ll)
+        idx = resample(w, n_out, seed, it + L)
+        recs.append(dict(out=o, loglik=ll, rejected=rejected, weight=w, index=idx))
+        if idx is None:
+            return dict(levels=recs, pose=None, estimate=None)
+        est = se3.pose_estimate(o["pose"], w)
+        X = o["pose"][idx]
+    return dict(levels=recs, pose=X, estimate=est)

@@ -528,3 +528,63 @@ def test_paper_settings_fixture():
     # the likelihood exponent of Eq. 4 / Eq. 6
     assert mcl.score(np.zeros((1, 3)), np.full((1, 3), 1.0), np.ones(1), 1)[2] == \
         pytest.approx(g["likelihood_exponent"] * (0.0 - math.log(3.0)), abs=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# coarse-to-fine levels and 1-sigma rejection
+
+def test_reject_1sigma_constructed():
+    # U = (1, 1, 1, 5): mean 2, population std sqrt(3) = 1.732: only the last
+    # particle lies above 3.732
+    ll, rej = mcl.reject_1sigma([1.0, 1.0, 1.0, 5.0], [0.5, 1.0, 2.0, 3.0])
+    assert list(rej) == [False, False, False, True]
+    assert ll[3] == -np.inf and list(ll[:3]) == [0.5, 1.0, 2.0]
+    # equal U: std 0, nothing strictly above the mean
+    ll, rej = mcl.reject_1sigma([2.0] * 5, [0.0] * 5)
+    assert not rej.any()
+    # two clusters (0 x 3, 1 x 1): mean .25, std .433; 1 > .683 -> rejected
+    _, rej = mcl.reject_1sigma([0.0, 0.0, 0.0, 1.0], [0.0] * 4)
+    assert list(rej) == [False, False, False, True]
+    # a NaN U or l is rejected and left out of the statistics
+    ll, rej = mcl.reject_1sigma([1.0, np.nan, 1.0, 3.0], [0.0, 0.0, np.nan, 0.0])
+    assert list(rej) == [False, True, True, False]     # stats over {1, 3}: 2 + 1 = 3, 3 > 3 is false
+
+
+def test_reject_1sigma_fraction_for_normal_uncertainty():
+    # for normally distributed U about 15.9% of particles lie above mean + std
+    rng = np.random.default_rng(3)
+    _, rej = mcl.reject_1sigma(rng.standard_normal(200000), np.zeros(200000))
+    assert abs(rej.mean() - 0.1587) < 0.004
+
+
+def test_levels_single_level_equals_update_and_resample():
+    s = synth.spec("small")
+    p = synth.map_params(s, 5)
+    cam = synth.camera("small")
+    poses = synth.particles("small", 5, N=6)
+    img = synth.observation("small", 5)
+    r = mcl.update_levels(s, p, img, cam, [(2, 4, 5)], poses, seed=9, it=3, reject=False)
+    o = mcl.update_particles(s, p, img, cam, 2, 4, poses, seed=9, it=3)
+    assert np.array_equal(r["levels"][0]["weight"], o["weight"])
+    idx = mcl.resample(o["weight"], 5, 9, 3)
+    assert r["levels"][0]["index"] == idx
+    assert np.array_equal(r["pose"], o["pose"][idx])
+
+
+def test_levels_rejected_particles_are_never_drawn():
+    s = synth.spec("small")
+    p = synth.map_params(s, 6)
+    cam = synth.camera("small")
+    poses = synth.particles("small", 6, N=12)
+    img = synth.observation("small", 6)
+    r = mcl.update_levels(s, p, img, cam, [(2, 8, 9), (1, 16, 4)], poses, seed=2, it=0)
+    for lev in r["levels"]:
+        U = lev["out"]["uncert"]
+        thr = U.mean() + U.std()
+        assert np.array_equal(lev["rejected"], U > thr)
+        assert all(not lev["rejected"][i] for i in lev["index"])
+        assert np.all(lev["weight"][lev["rejected"]] == 0.0)
+        assert abs(lev["weight"].sum() - 1.0) < 1e-12
+    assert r["pose"].shape == (4, 3, 4)
+    # level 1 starts from level 0's resampled set
+    assert len(r["levels"][1]["out"]["index"]) == 9
