@@ -187,6 +187,71 @@ loc_status loc_calibrate_fp8(loc_ctx* ctx, const float* o, const float* d, int n
  * calibrated largest |output| of layer l (l <= 8). */
 loc_status loc_fp8_scales(loc_ctx* ctx, int* ew, int* ea, float* amax, int n);
 
+/* ---------------------------------------------------------------- levels
+ * Coarse-to-fine update (Alg. 1 with per-iteration R_t, B_t, N_t, Sec. III-C)
+ * for the 4x64 map in BF16 with 32 coarse and no fine samples.  Level L of a
+ * call is one MCL iteration with counter iter + L: the N_L particles are
+ * predicted (motion O, noise sigma_t, sigma_r, as loc_update_particles), each
+ * casts B rays at scale 1/inv_R, S_i and l_i follow Eq. 6, and with `reject`
+ * particles whose mean F exceeds mean + one (population) standard deviation
+ * over the particles are given weight 0 (1-sigma rejection); the weights are
+ * normalised (Eq. 3) and n_out particles are drawn (systematic, integer-exact,
+ * as loc_resample) to carry on: N_0 = N, N_{L+1} = levels[L].n_out.
+ * Per level the work is one persistent fused kernel over the level's rays
+ * (ray generation, samples, encoding, map, compositing, F, E) and one
+ * single-workgroup kernel (scores, rejection, normalisation, read-out,
+ * resampling, gather, next prediction). */
+typedef struct {
+  int inv_R;   /* level scale R = 1 / inv_R, inv_R in {1, 2, 4, 8} */
+  int B;       /* rays per particle, [1, 1024] */
+  int n_out;   /* particles drawn at the end of the level, [1, 2^20] */
+} loc_level;
+
+/* image: DEVICE H x W x 3 float32; levels: HOST array of n_levels (1..8);
+ * pose_in: DEVICE N x 12 float64 (N in [1, 2^20]); motion: HOST 12 float64 or
+ * NULL; pose_out: DEVICE levels[n_levels-1].n_out x 12 float64, the last
+ * level's drawn poses; est_out: DEVICE 12 float64 or NULL, the pose read-out
+ * (loc_pose_estimate) of the last level's weighted set.  Per-level results are
+ * kept until the next level call (loc_level_outputs).  N_L * B <= 2^26.
+ * LOC_E_UNSUPPORTED for another map or sampling.  All weights zero at a level:
+ * LOC_FLAG_DEGENERATE_RESAMPLE and NaN poses for the next level.  In graph
+ * mode the sequence after a small key upload is a captured hipGraph, replayed
+ * while image, camera, levels, N, pointers, `reject` and tile choices stay the
+ * same (seed, iter, motion and noise may change). */
+loc_status loc_update_levels(loc_ctx* ctx, const float* image, const loc_camera* cam, int n_levels,
+                             const loc_level* levels, int N, const double* pose_in, const double* motion,
+                             double sigma_t, double sigma_r, uint64_t seed, uint64_t iter, int reject,
+                             double* pose_out, double* est_out);
+
+/* enable (1) or disable (0) graph capture and replay of loc_update_levels */
+loc_status loc_set_graph_mode(loc_ctx* ctx, int enable);
+
+/* Results of level `level` of the last level call, copied on the context's
+ * stream into DEVICE buffers (any may be NULL): loglik N_L float64 (-inf for
+ * rejected particles), weight N_L float64, uncert N_L float32 (mean F), idx
+ * n_out int32 (drawn indices), pose N_L x 12 float64 (predicted poses). */
+loc_status loc_level_outputs(loc_ctx* ctx, int level, double* loglik, double* weight, float* uncert,
+                             int32_t* idx, double* pose);
+
+/* Per-ray results of level `level` (as loc_ray_outputs): N_L * B entries. */
+loc_status loc_level_ray_outputs(loc_ctx* ctx, int level, float* rgb, float* opacity, float* F, float* E);
+
+/* Autotuner of the fused ray kernel for the given level schedule (the same
+ * arguments as loc_update_levels): times every tile configuration and grid
+ * size on the level's real particles over `reps` launches and keeps the
+ * fastest per level.  cache_path (HOST string or NULL): a file of one JSON
+ * object per line {"key", "ntl", "waves", "blocks", "us_per_launch"}, read for
+ * known levels and appended with new choices.  chosen: HOST 3 * n_levels ints
+ * (column tiles per wave, waves per workgroup, workgroups) or NULL.
+ * Synchronous.  Every configuration computes identical results. */
+loc_status loc_autotune_levels(loc_ctx* ctx, const float* image, const loc_camera* cam, int n_levels,
+                               const loc_level* levels, int N, const double* pose_in, int reps,
+                               const char* cache_path, int* chosen);
+
+/* Set level `level`'s tile choice by hand: (ntl, waves) in {(1,4), (1,8),
+ * (1,16), (2,4), (2,8)}, blocks >= 1; (0, 0, 0) restores the default. */
+loc_status loc_set_level_tiles(loc_ctx* ctx, int level, int ntl, int waves, int blocks);
+
 /* Poses of the resampled set (Alg. 1, "add x_t^[i] to X_t"): pose_out[k] =
  * pose_in[idx[k]], DEVICE N x 12 float64 arrays and DEVICE int32 indices (an
  * index outside [0, n_in) leaves pose_out[k] unchanged). */

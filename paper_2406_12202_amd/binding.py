@@ -20,7 +20,9 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outp
            "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error",
            "loc_cast_rays", "loc_teacher_histograms", "loc_set_proposal", "loc_get_proposal",
            "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal",
-           "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales"]
+           "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
+           "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
+           "loc_autotune_levels", "loc_set_level_tiles"]
 PROPOSAL_PARAMS = 11296
 
 
@@ -46,6 +48,10 @@ class KernelStat(ctypes.Structure):
 class TrainCfg(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int), ("steps", ctypes.c_int), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("n_out", ctypes.c_int)]
 
 
 class LocError(RuntimeError):
@@ -92,10 +98,20 @@ def load(path=LIB_PATH):
     lib.loc_pose_estimate.argtypes = [vp, vp, vp, c_int, vp]
     lib.loc_calibrate_fp8.argtypes = [vp, vp, vp, c_int]
     lib.loc_fp8_scales.argtypes = [vp, vp, vp, vp, c_int]
+    lib.loc_update_levels.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Level), c_int, vp, vp,
+                                      c_dbl, c_dbl, c_u64, c_u64, c_int, vp, vp]
+    lib.loc_set_graph_mode.argtypes = [vp, c_int]
+    lib.loc_level_outputs.argtypes = [vp, c_int, vp, vp, vp, vp, vp]
+    lib.loc_level_ray_outputs.argtypes = [vp, c_int, vp, vp, vp, vp]
+    lib.loc_autotune_levels.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Level), c_int, vp,
+                                        c_int, ctypes.c_char_p, vp]
+    lib.loc_set_level_tiles.argtypes = [vp, c_int, c_int, c_int, c_int]
     for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
               "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
               "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
-              "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales"):
+              "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
+              "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
+              "loc_autotune_levels", "loc_set_level_tiles"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -340,3 +356,90 @@ class Context:
         am = (ctypes.c_float * 12)()
         self._check(self.lib.loc_fp8_scales(self.h, ew, ea, am, 12), "loc_fp8_scales")
         return list(ew[:10]), list(ea[:10]), list(am[:9])
+
+    # ----------------------------------------------------------------- levels
+
+    @staticmethod
+    def _levels(levels):
+        arr = (Level * len(levels))()
+        for k, (r, b, n) in enumerate(levels):
+            arr[k] = Level(int(r), int(b), int(n))
+        return arr
+
+    @staticmethod
+    def _cam(cam):
+        W, H, fx, fy, cx, cy = cam
+        return Camera(W=int(W), H=int(H), fx=fx, fy=fy, cx=cx, cy=cy)
+
+    def loc_update_levels(self, image, cam, levels, pose_in, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0, iter=0,
+                          reject=True, pose_out=None, est_out=None):
+        """Coarse-to-fine update; levels = [(inv_R, B, n_out), ...]; returns (pose_out, est)."""
+        import numpy as np
+        import torch
+        W, H = int(cam[0]), int(cam[1])
+        N = pose_in.shape[0]
+        dev = pose_in.device
+        if pose_out is None:
+            pose_out = torch.empty((levels[-1][2], 3, 4), dtype=torch.float64, device=dev)
+        if est_out is None:
+            est_out = torch.empty((3, 4), dtype=torch.float64, device=dev)
+        c = self._cam(cam)
+        lv = self._levels(levels)
+        mo = None
+        if motion is not None:
+            self._mo = np.ascontiguousarray(np.asarray(motion, dtype=np.float64).reshape(12))
+            mo = ctypes.c_void_p(self._mo.ctypes.data)
+        st = self.lib.loc_update_levels(
+            self.h, _ptr(image, torch.float32, H * W * 3, "image"), ctypes.byref(c), len(levels), lv, int(N),
+            _ptr(pose_in, torch.float64, N * 12, "pose_in"), mo, float(sigma_t), float(sigma_r), int(seed), int(iter),
+            int(bool(reject)), _ptr(pose_out, torch.float64, levels[-1][2] * 12, "pose_out"),
+            _ptr(est_out, torch.float64, 12, "est_out"))
+        self._check(st, "loc_update_levels")
+        self.last_levels = [(N if k == 0 else levels[k - 1][2], levels[k][1], levels[k][2]) for k in range(len(levels))]
+        return pose_out, est_out
+
+    def loc_set_graph_mode(self, enable):
+        self._check(self.lib.loc_set_graph_mode(self.h, int(bool(enable))), "loc_set_graph_mode")
+
+    def loc_level_outputs(self, level):
+        import torch
+        N, B, n_out = self.last_levels[level]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = dict(loglik=torch.empty(N, dtype=torch.float64, device=dev),
+                   weight=torch.empty(N, dtype=torch.float64, device=dev),
+                   uncert=torch.empty(N, dtype=torch.float32, device=dev),
+                   idx=torch.empty(n_out, dtype=torch.int32, device=dev),
+                   pose=torch.empty((N, 3, 4), dtype=torch.float64, device=dev))
+        self._check(self.lib.loc_level_outputs(self.h, int(level), out["loglik"].data_ptr(), out["weight"].data_ptr(),
+                                               out["uncert"].data_ptr(), out["idx"].data_ptr(),
+                                               out["pose"].data_ptr()), "loc_level_outputs")
+        return out
+
+    def loc_level_ray_outputs(self, level):
+        import torch
+        N, B, _ = self.last_levels[level]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rgb = torch.empty((N, B, 3), dtype=torch.float32, device=dev)
+        op = torch.empty((N, B), dtype=torch.float32, device=dev)
+        F = torch.empty((N, B), dtype=torch.float32, device=dev)
+        E = torch.empty((N, B), dtype=torch.float32, device=dev)
+        self._check(self.lib.loc_level_ray_outputs(self.h, int(level), rgb.data_ptr(), op.data_ptr(), F.data_ptr(),
+                                                   E.data_ptr()), "loc_level_ray_outputs")
+        return rgb, op, F, E
+
+    def loc_autotune_levels(self, image, cam, levels, pose_in, reps=5, cache_path=None):
+        import torch
+        W, H = int(cam[0]), int(cam[1])
+        N = pose_in.shape[0]
+        c = self._cam(cam)
+        lv = self._levels(levels)
+        chosen = (ctypes.c_int * (3 * len(levels)))()
+        st = self.lib.loc_autotune_levels(self.h, _ptr(image, torch.float32, H * W * 3, "image"), ctypes.byref(c),
+                                          len(levels), lv, int(N), _ptr(pose_in, torch.float64, N * 12, "pose_in"),
+                                          int(reps), cache_path.encode() if cache_path else None, chosen)
+        self._check(st, "loc_autotune_levels")
+        return [tuple(chosen[3 * k:3 * k + 3]) for k in range(len(levels))]
+
+    def loc_set_level_tiles(self, level, ntl, waves, blocks):
+        self._check(self.lib.loc_set_level_tiles(self.h, int(level), int(ntl), int(waves), int(blocks)),
+                    "loc_set_level_tiles")

@@ -1,71 +1,15 @@
-// Particle-filter kernels in float64: prediction (SE(3) motion with Gaussian
-// noise), weight normalisation and integer-exact systematic resampling.
-#include "common.h"
-#include "kernels.h"
+// Per-step particle-filter kernels in float64: prediction, weight
+// normalisation, integer-exact systematic resampling, the gather of resampled
+// poses and the pose read-out (device functions in filter_dev.h).
+#include "filter_dev.h"
 
 namespace fl {
 
-// ---------------------------------------------------------------------------
-// x_t = x_{t-1} O_t Exp(delta), delta = (rho, phi) ~ N(0, diag(sigma_t^2 I,
-// sigma_r^2 I)) (Sec. III-A, prediction step); Exp by Rodrigues' formula and
-// the left Jacobian, Taylor coefficients for |phi| < 1e-4.
 __global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.N) return;
-  double x[12];
-  for (int q = 0; q < 12; ++q) x[q] = a.pose_in[(long)i * 12 + q];
-  const u32x4 w0 = draw(a.seed, a.iter, kStreamMotion, (uint32_t)i, 0, 0);
-  const u32x4 w1 = draw(a.seed, a.iter, kStreamMotion, (uint32_t)i, 0, 1);
-  const uint32_t ws[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
-  double g[6];
-  for (int p = 0; p < 3; ++p) {
-    const double u1 = unit_open(ws[2 * p]), u2 = unit_open(ws[2 * p + 1]);
-    const double r = sqrt(-2.0 * log(u1));
-    g[2 * p] = r * cos(2.0 * M_PI * u2);
-    g[2 * p + 1] = r * sin(2.0 * M_PI * u2);
-  }
-  const double rho[3] = {a.sigma_t * g[0], a.sigma_t * g[1], a.sigma_t * g[2]};
-  const double ph[3] = {a.sigma_r * g[3], a.sigma_r * g[4], a.sigma_r * g[5]};
-  const double th2 = ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2];
-  const double th = sqrt(th2);
-  double A, Bc, C;
-  if (th < 1e-4) {
-    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-    Bc = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
-  } else {
-    A = sin(th) / th;
-    Bc = (1.0 - cos(th)) / th2;
-    C = (th - sin(th)) / (th2 * th);
-  }
-  const double K[3][3] = {{0.0, -ph[2], ph[1]}, {ph[2], 0.0, -ph[0]}, {-ph[1], ph[0], 0.0}};
-  double K2[3][3];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) K2[r][c] = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
-  double E[12];
-  for (int r = 0; r < 3; ++r) {
-    double tv = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      const double id = (r == c) ? 1.0 : 0.0;
-      E[4 * r + c] = id + A * K[r][c] + Bc * K2[r][c];
-      tv += (id + Bc * K[r][c] + C * K2[r][c]) * rho[c];
-    }
-    E[4 * r + 3] = tv;
-  }
-  // y = x * O, then y * E
-  const double* O = a.motion.m;
-  double y[12], z[12];
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c)
-      y[4 * r + c] = x[4 * r + 0] * O[c] + x[4 * r + 1] * O[4 + c] + x[4 * r + 2] * O[8 + c];
-    y[4 * r + 3] = x[4 * r + 0] * O[3] + x[4 * r + 1] * O[7] + x[4 * r + 2] * O[11] + x[4 * r + 3];
-  }
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c)
-      z[4 * r + c] = y[4 * r + 0] * E[c] + y[4 * r + 1] * E[4 + c] + y[4 * r + 2] * E[8 + c];
-    z[4 * r + 3] = y[4 * r + 0] * E[3] + y[4 * r + 1] * E[7] + y[4 * r + 2] * E[11] + y[4 * r + 3];
-  }
-  for (int q = 0; q < 12; ++q) a.pose_out[(long)i * 12 + q] = z[q];
+  predict_pose(a.pose_in + (long)i * 12, a.pose_out + (long)i * 12, a.motion.m, a.sigma_t, a.sigma_r, a.seed,
+               a.iter, i);
 }
 
 hipError_t launch_predict(const PredictArgs& a, hipStream_t st) {
@@ -73,46 +17,9 @@ hipError_t launch_predict(const PredictArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// w_i = exp(l_i - m) / sum_k exp(l_k - m), m = max over finite l (Eq. 3).
-// One workgroup; fixed strided assignment and a fixed tree, so the sums are
-// deterministic.
-constexpr int kRedThreads = 1024;
-
 __global__ __launch_bounds__(kRedThreads) void k_normalize(const double* ll, double* w, int N, int* flags) {
   __shared__ double s[kRedThreads];
-  const int tid = threadIdx.x;
-  double m = -INFINITY;
-  for (int i = tid; i < N; i += kRedThreads) {
-    const double v = ll[i];
-    if (isfinite(v)) m = fmax(m, v);
-  }
-  s[tid] = m;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
-    __syncthreads();
-  }
-  m = s[0];
-  __syncthreads();
-  const bool none = !(m > -INFINITY);
-  double acc = 0.0;
-  for (int i = tid; i < N; i += kRedThreads) {
-    const double v = ll[i];
-    if (!none && isfinite(v)) acc += exp(v - m);
-  }
-  s[tid] = acc;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s[tid] += s[tid + o];
-    __syncthreads();
-  }
-  const double tot = s[0];
-  for (int i = tid; i < N; i += kRedThreads) {
-    const double v = ll[i];
-    w[i] = (!none && isfinite(v)) ? exp(v - m) / tot : 0.0;
-  }
-  if (none && tid == 0) atomicOr(flags, 1);
+  normalize_block(ll, w, N, flags, s);
 }
 
 hipError_t launch_normalize(const double* loglik, double* weight, int N, int* flags, hipStream_t st) {
@@ -120,83 +27,12 @@ hipError_t launch_normalize(const double* loglik, double* weight, int N, int* fl
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// systematic resampling with integer thresholds (Alg. 1, draw loop):
-// q_i = floor(w_i / w_max 2^40), inclusive prefix P (exact uint64),
-// theta_k = floor((k 2^32 + r0) Q / (n_out 2^32)), idx_k = min{i : P_i > theta_k}.
-typedef unsigned long long u64;
-
-__device__ inline double clean_weight(double w) { return (isfinite(w) && w > 0.0) ? w : 0.0; }
-
-// floor(a * Q / (n 2^32)) for a < 2^63, Q < 2^64, n < 2^31, as 32-bit limbs
-__device__ inline u64 threshold(u64 a, u64 Q, u64 n) {
-  const u64 lo = a * Q;
-  const u64 hi = __umul64hi(a, Q);
-  // x = (hi:lo) >> 32, a 96-bit number with limbs x2 x1 x0
-  const u64 x2 = hi >> 32, x1 = hi & 0xffffffffull, x0 = lo >> 32;
-  u64 r = 0, q = 0;
-  const u64 limbs[3] = {x2, x1, x0};
-  for (int i = 0; i < 3; ++i) {
-    const u64 cur = (r << 32) | limbs[i];
-    q = (q << 32) | (cur / n);
-    r = cur % n;
-  }
-  return q;
-}
-
 __global__ __launch_bounds__(kRedThreads) void k_resample(const double* weight, int n_in, int n_out,
                                                           uint64_t seed, uint64_t iter, u64* prefix,
                                                           int32_t* idx, int* flags) {
   __shared__ double s_max[kRedThreads];
   __shared__ u64 s_sum[kRedThreads];
-  const int tid = threadIdx.x;
-  double m = 0.0;
-  for (int i = tid; i < n_in; i += kRedThreads) m = fmax(m, clean_weight(weight[i]));
-  s_max[tid] = m;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s_max[tid] = fmax(s_max[tid], s_max[tid + o]);
-    __syncthreads();
-  }
-  const double wmax = s_max[0];
-  // contiguous chunk per thread: local sums, block exclusive scan, local prefixes
-  const int chunk = (n_in + kRedThreads - 1) / kRedThreads;
-  const int b0 = min(tid * chunk, n_in), b1 = min(b0 + chunk, n_in);
-  u64 local = 0;
-  if (wmax > 0.0)
-    for (int i = b0; i < b1; ++i) local += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
-  s_sum[tid] = local;
-  __syncthreads();
-  for (int o = 1; o < kRedThreads; o <<= 1) {     // Hillis-Steele inclusive scan
-    const u64 v = (tid >= o) ? s_sum[tid - o] : 0;
-    __syncthreads();
-    s_sum[tid] += v;
-    __syncthreads();
-  }
-  const u64 Q = s_sum[kRedThreads - 1];
-  u64 run = s_sum[tid] - local;
-  if (wmax > 0.0)
-    for (int i = b0; i < b1; ++i) {
-      run += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
-      prefix[i] = run;
-    }
-  __syncthreads();
-  __threadfence_block();
-  if (Q == 0) {
-    for (int k = tid; k < n_out; k += kRedThreads) idx[k] = -1;
-    if (tid == 0) atomicOr(flags, 2);
-    return;
-  }
-  const u64 r0 = draw(seed, iter, kStreamResample, 0, 0, 0).x;
-  for (int k = tid; k < n_out; k += kRedThreads) {
-    const u64 th = threshold(((u64)k << 32) + r0, Q, (u64)n_out);
-    int lo = 0, hi = n_in - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (prefix[mid] > th) hi = mid; else lo = mid + 1;
-    }
-    idx[k] = lo;
-  }
+  resample_block(weight, n_in, n_out, seed, iter, prefix, idx, flags, s_max, s_sum);
 }
 
 hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
@@ -206,12 +42,7 @@ hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t s
   return hipGetLastError();
 }
 
-}  // namespace fl
-
-namespace fl {
-
-// ---------------------------------------------------------------------------
-// pose gather after resampling: out[k] = in[idx[k]] (idx < 0 copies nothing)
+// out[k] = in[idx[k]] (idx < 0 copies nothing)
 __global__ void k_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_out * 12) return;
@@ -227,132 +58,10 @@ hipError_t launch_gather_poses(const double* in, const int32_t* idx, int n_in, i
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// pose read-out: weighted mean position and chordal L2 mean rotation
-// R = U diag(1, 1, det(U V^T)) V^T for sum_i w_i R_i = U S V^T.
-__device__ void mat3_mul(const double* A, const double* B, double* C) {
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
-}
-__device__ double mat3_det(const double* A) {
-  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
-}
-
-// smallest-eigenvalue eigenvector of a symmetric 3x3 matrix by cyclic Jacobi rotations
-__device__ void sym3_min_eigvec(const double* Ain, double* v) {
-  double A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  for (int i = 0; i < 9; ++i) A[i] = Ain[i];
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    for (int p = 0; p < 2; ++p)
-      for (int q = p + 1; q < 3; ++q) {
-        const double apq = A[3 * p + q];
-        if (fabs(apq) < 1e-300) continue;
-        const double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < 3; ++k) {     // A <- J^T A J
-          const double akp = A[3 * k + p], akq = A[3 * k + q];
-          A[3 * k + p] = c * akp - s * akq;
-          A[3 * k + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const double apk = A[3 * p + k], aqk = A[3 * q + k];
-          A[3 * p + k] = c * apk - s * aqk;
-          A[3 * q + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < 3; ++k) {     // V <- V J
-          const double vkp = V[3 * k + p], vkq = V[3 * k + q];
-          V[3 * k + p] = c * vkp - s * vkq;
-          V[3 * k + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  int m = 0;
-  if (A[4] < A[3 * m + m]) m = 1;
-  if (A[8] < A[3 * m + m]) m = 2;
-  for (int k = 0; k < 3; ++k) v[k] = V[3 * k + m];
-}
-
-constexpr int kEstThreads = 256;
-
 __global__ __launch_bounds__(kEstThreads) void k_pose_estimate(const double* pose, const double* w, int N,
                                                                double* est, int* flags) {
   __shared__ double s[kEstThreads][13];
-  const int tid = threadIdx.x;
-  double acc[13];
-  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
-  for (int i = tid; i < N; i += kEstThreads) {
-    const double wi = (isfinite(w[i]) && w[i] > 0.0) ? w[i] : 0.0;
-    const double* P = pose + (long)i * 12;
-    for (int r = 0; r < 3; ++r) {
-      for (int c = 0; c < 3; ++c) acc[3 * r + c] += wi * P[4 * r + c];
-      acc[9 + r] += wi * P[4 * r + 3];
-    }
-    acc[12] += wi;
-  }
-  for (int q = 0; q < 13; ++q) s[tid][q] = acc[q];
-  __syncthreads();
-  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
-    if (tid < o)
-      for (int q = 0; q < 13; ++q) s[tid][q] += s[tid + o][q];
-    __syncthreads();
-  }
-  if (tid != 0) return;
-  const double W = s[0][12];
-  if (!(W > 0.0)) {
-    atomicOr(flags, 1);
-    for (int q = 0; q < 12; ++q) est[q] = NAN;
-    return;
-  }
-  double M[9];
-  for (int q = 0; q < 9; ++q) M[q] = s[0][q] / W;
-  // orthogonal polar factor Q of M by scaled Newton iteration
-  // Q <- (g Q + Q^{-T} / g) / 2 with g = (|det Q|)^(-1/3)
-  double Q[9];
-  for (int q = 0; q < 9; ++q) Q[q] = M[q];
-  double d = mat3_det(Q);
-  if (!(fabs(d) > 1e-300)) {
-    atomicOr(flags, 4);
-    for (int q = 0; q < 12; ++q) est[q] = NAN;
-    return;
-  }
-  for (int it = 0; it < 60; ++it) {
-    d = mat3_det(Q);
-    const double g = pow(fabs(d), -1.0 / 3.0);
-    // inverse transpose = cofactor matrix / det
-    double C[9];
-    C[0] = Q[4] * Q[8] - Q[5] * Q[7]; C[1] = Q[5] * Q[6] - Q[3] * Q[8]; C[2] = Q[3] * Q[7] - Q[4] * Q[6];
-    C[3] = Q[2] * Q[7] - Q[1] * Q[8]; C[4] = Q[0] * Q[8] - Q[2] * Q[6]; C[5] = Q[1] * Q[6] - Q[0] * Q[7];
-    C[6] = Q[1] * Q[5] - Q[2] * Q[4]; C[7] = Q[2] * Q[3] - Q[0] * Q[5]; C[8] = Q[0] * Q[4] - Q[1] * Q[3];
-    double diff = 0.0;
-    for (int q = 0; q < 9; ++q) {
-      const double nq = 0.5 * (g * Q[q] + C[q] / (d * g));
-      diff = fmax(diff, fabs(nq - Q[q]));
-      Q[q] = nq;
-    }
-    if (diff < 1e-15) break;
-  }
-  double R[9];
-  for (int q = 0; q < 9; ++q) R[q] = Q[q];
-  if (mat3_det(Q) < 0.0) {
-    // reflection: flip the direction of the smallest singular value,
-    // R = Q - 2 (Q v) v^T with v the smallest eigenvector of H = Q^T M
-    double QT[9], H[9], v[3];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) QT[3 * r + c] = Q[3 * c + r];
-    mat3_mul(QT, M, H);
-    for (int r = 0; r < 3; ++r)
-      for (int c = r + 1; c < 3; ++c) H[3 * r + c] = H[3 * c + r] = 0.5 * (H[3 * r + c] + H[3 * c + r]);
-    sym3_min_eigvec(H, v);
-    double u[3];
-    for (int r = 0; r < 3; ++r) u[r] = Q[3 * r] * v[0] + Q[3 * r + 1] * v[1] + Q[3 * r + 2] * v[2];
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) R[3 * r + c] = Q[3 * r + c] - 2.0 * u[r] * v[c];
-  }
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c) est[4 * r + c] = R[3 * r + c];
-    est[4 * r + 3] = s[0][9 + r] / W;
-  }
+  pose_estimate_block(pose, w, N, est, flags, s);
 }
 
 hipError_t launch_pose_estimate(const double* pose, const double* w, int N, double* est, int* flags, hipStream_t st) {

@@ -150,4 +150,56 @@ hipError_t launch_pose_estimate(const double* pose, const double* w, int N, doub
 hipError_t launch_split_ray_outputs(const float4* rgba, const float2* fe, int n, float* rgb,
                                     float* opacity, float* F, float* E, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// coarse-to-fine path (small map in bf16, 32 stratified samples per ray).
+// The per-call values live in a device-side key so that a captured graph of
+// the level sequence replays with new seeds, motion and noise.
+struct LevelKey {
+  uint64_t seed, iter;    // level L uses iteration counter iter + L
+  double motion[12];      // O_t (3 x 4)
+  double sigma_t, sigma_r;
+};
+
+struct LevelRayArgs {
+  const LevelKey* key;
+  int level;
+  const double* pose;     // N x 12 predicted poses of this level
+  const float* image;     // full-resolution H x W x 3
+  int W_full, s, Wl, Hl;  // level factor s, level resolution
+  double fx, fy, cx, cy;  // level intrinsics
+  int N, B;
+  const void* wblocks;    // BF16 small-map chunks, biases, heads (maplayout_bf16.h)
+  const float* bias;
+  const float* heads;
+  float near_, dt, far_, log_trans, log_opq, tau;
+  int jitter;
+  float4* ray_rgba;       // per ray (C, A)
+  float2* ray_fe;         // per ray (F, E)
+};
+
+struct LevelFinishArgs {
+  const LevelKey* key;
+  int level;
+  const float2* ray_fe;   // this level's per-ray (F, E)
+  int N, B, reject;
+  const double* pose;     // this level's predicted poses
+  double* loglik;         // N (after rejection: -inf for rejected particles)
+  float* uncert;          // N mean F
+  double* weight;         // N
+  int32_t* idx;           // n_out resampled indices
+  unsigned long long* prefix;  // N scratch
+  int n_out;
+  double* next_pose;      // n_out x 12
+  int predict_next;       // apply the next level's prediction to the drawn poses
+  double* est;            // 12: pose read-out of this level's weighted set, or NULL
+  int* flags;
+};
+
+hipError_t launch_set_key(LevelKey* key, const LevelKey& v, hipStream_t st);
+hipError_t launch_level_predict(const LevelKey* key, const double* pose_in, double* pose_out, int N, hipStream_t st);
+// tile configuration (column tiles per wave, waves per workgroup), grid size
+hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int blocks, hipStream_t st);
+bool level_rays_config_ok(int ntl, int waves);
+hipError_t launch_level_finish(const LevelFinishArgs& a, hipStream_t st);
+
 }  // namespace fl

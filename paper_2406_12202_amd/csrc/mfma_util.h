@@ -89,4 +89,49 @@ __device__ __forceinline__ void stage_samples(const MlpArgs& a, const long tile,
   }
 }
 
+// rounded bf16 operands of the next layer from one finished output tile; the
+// bias is already in the accumulators; ReLU acts on the packed bf16 pairs
+// (a non-negative bf16 is a non-negative int16, a negative one a negative
+// int16, so max with 0 as int16 is ReLU)
+template <int NTL, int NY>
+__device__ __forceinline__ void epilogue_b(const f32x16 (&acc)[NTL], const bool relu, const int mt,
+                                           bf16x8 (&y)[NTL][NY]) {
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      bf16x8 v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)acc[nt][8 * c + q];
+      if (relu) {
+        s16x2 w[4];
+        __builtin_memcpy(w, &v, 16);
+        const s16x2 z = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = __builtin_elementwise_max(w[i], z);
+        __builtin_memcpy(&v, w, 16);
+      }
+      y[nt][2 * mt + c] = v;
+    }
+  }
+}
+
+template <int KB, int N>
+__device__ __forceinline__ float dot_b(const float* __restrict__ w, const bf16x8 (&x)[N]) {
+  float s = 0.0f;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const float4* w4 = reinterpret_cast<const float4*>(w + kb * 8);
+    const float4 u = w4[0], v = w4[1];
+    s = fmaf(u.x, (float)x[kb][0], s); s = fmaf(u.y, (float)x[kb][1], s);
+    s = fmaf(u.z, (float)x[kb][2], s); s = fmaf(u.w, (float)x[kb][3], s);
+    s = fmaf(v.x, (float)x[kb][4], s); s = fmaf(v.y, (float)x[kb][5], s);
+    s = fmaf(v.z, (float)x[kb][6], s); s = fmaf(v.w, (float)x[kb][7], s);
+  }
+  return s;
+}
+
+__device__ __forceinline__ float softplus_b(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoid_b(float z) { return 1.0f / (1.0f + expf(-z)); }
+
 }  // namespace fl

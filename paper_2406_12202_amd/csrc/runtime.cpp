@@ -3,6 +3,7 @@
 // management, launch sequencing and per-kernel event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,11 +23,13 @@ using namespace fl;
 namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
-                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_COUNT };
+                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
+                K_LV_PREDICT, K_LV_RAYS, K_LV_FINISH, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
-                                     "pose_estimate", "fp8_calibration"};
+                                     "pose_estimate", "fp8_calibration", "level_key", "level_predict",
+                                     "level_rays", "level_finish"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -69,6 +72,26 @@ struct loc_ctx {
   int fine_mode = 0;              // 0 hierarchical, 1 proposal
   DevBuf<float> prop_partial, prop_loss;
   DevBuf<float4> tr_o, tr_d;      // rays of teacher / training calls
+  // coarse-to-fine path: per-level buffers, device-side key, tile choices,
+  // captured graph of the level sequence
+  struct Level {
+    DevBuf<double> pose, loglik, weight;
+    DevBuf<float> uncert;
+    DevBuf<int32_t> idx;
+    DevBuf<float4> rgba;
+    DevBuf<float2> fe;
+    int N = 0, B = 0, n_out = 0;
+    int ntl = 0, waves = 0, blocks = 0;   // 0: default choice
+  };
+  Level lv[8];
+  int n_lv = 0;
+  LevelKey* key = nullptr;
+  int n_cu = 0;
+  bool graph_mode = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> graph_sig;
   int* flags = nullptr;
   int last_N = 0, last_B = 0;
   // profiling
@@ -548,6 +571,14 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
   hipFree(c->prop); hipFree(c->prop_m); hipFree(c->prop_v); hipFree(c->prop_partial.p); hipFree(c->prop_loss.p);
   hipFree(c->tr_o.p); hipFree(c->tr_d.p);
+  for (auto& L : c->lv) {
+    hipFree(L.pose.p); hipFree(L.loglik.p); hipFree(L.weight.p); hipFree(L.uncert.p); hipFree(L.idx.p);
+    hipFree(L.rgba.p); hipFree(L.fe.p);
+  }
+  hipFree(c->key);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (auto& p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
   for (auto e : c->free_events) hipEventDestroy(e);
   delete c;
@@ -1149,6 +1180,425 @@ loc_status loc_fp8_scales(loc_ctx* c, int* ew, int* ea, float* amax, int n) {
     if (ea) ea[l] = c->f8_ea[l];
     if (amax) amax[l] = c->f8_amax[l];
   }
+  return LOC_OK;
+}
+
+
+// ------------------------------------------------------------- coarse-to-fine
+
+}  // extern "C"
+
+namespace {
+
+// default tile choice: one 32-sample tile per wave, 8 waves, two workgroups per CU
+void level_default_cfg(const loc_ctx* c, long n_rays, int& ntl, int& waves, int& blocks) {
+  ntl = 1;
+  waves = 8;
+  const long tiles = (n_rays + ntl * waves - 1) / (ntl * waves);
+  blocks = (int)std::max(1L, std::min(tiles, 2L * c->n_cu));
+}
+
+void level_cfg(const loc_ctx* c, int L, int& ntl, int& waves, int& blocks) {
+  const auto& lv = c->lv[L];
+  if (lv.ntl > 0) { ntl = lv.ntl; waves = lv.waves; blocks = lv.blocks; return; }
+  level_default_cfg(c, (long)lv.N * lv.B, ntl, waves, blocks);
+}
+
+struct LevelCall {
+  const float* image;
+  loc_camera cam;
+  int n_levels;
+  loc_level levels[8];
+  int N;
+  const double* pose_in;
+  int reject;
+  double* pose_out;
+  double* est_out;
+};
+
+LevelRayArgs level_ray_args(const loc_ctx* c, const LevelCall& q, int L) {
+  const loc_map_desc& d = c->desc;
+  const int s = q.levels[L].inv_R;
+  LevelRayArgs a{};
+  a.key = c->key;
+  a.level = L;
+  a.pose = c->lv[L].pose.p;
+  a.image = q.image;
+  a.W_full = q.cam.W;
+  a.s = s;
+  a.Wl = q.cam.W / s;
+  a.Hl = q.cam.H / s;
+  a.fx = q.cam.fx / s;
+  a.fy = q.cam.fy / s;
+  a.cx = q.cam.cx / s;
+  a.cy = q.cam.cy / s;
+  a.N = c->lv[L].N;
+  a.B = c->lv[L].B;
+  a.wblocks = c->wblocks;
+  a.bias = c->bias_b;
+  a.heads = c->heads_b;
+  a.near_ = d.near_;
+  a.dt = (d.far_ - d.near_) / (float)d.n_coarse;
+  a.far_ = d.far_;
+  a.log_trans = (float)std::log1p(-(double)d.alpha);
+  a.log_opq = (float)std::log((double)d.alpha);
+  a.tau = d.tau;
+  a.jitter = d.jitter;
+  a.ray_rgba = c->lv[L].rgba.p;
+  a.ray_fe = c->lv[L].fe.p;
+  return a;
+}
+
+// the level sequence (everything after the key upload) on stream st; with
+// `prof`, every launch is timed
+loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof) {
+  auto run = [&](int kid, double flop, double bytes, auto fn) -> loc_status {
+    if (prof) return timed(c, kid, flop, bytes, fn);
+    hipError_t e = fn();
+    return e == hipSuccess ? LOC_OK : fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
+  };
+  loc_status s;
+  if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
+               [&] { return launch_level_predict(c->key, q.pose_in, c->lv[0].pose.p, q.N, st); })))
+    return s;
+  for (int L = 0; L < q.n_levels; ++L) {
+    auto& lv = c->lv[L];
+    const LevelRayArgs ra = level_ray_args(c, q, L);
+    int ntl, waves, blocks;
+    level_cfg(c, L, ntl, waves, blocks);
+    const double nr = (double)lv.N * lv.B;
+    if ((s = run(K_LV_RAYS, 2.0 * (double)c->macs * nr * 32, nr * (24.0 + 12.0 * ra.s * ra.s), [&] {
+           return launch_level_rays(ra, ntl, waves, blocks, st);
+         })))
+      return s;
+    LevelFinishArgs fa{};
+    fa.key = c->key;
+    fa.level = L;
+    fa.ray_fe = lv.fe.p;
+    fa.N = lv.N;
+    fa.B = lv.B;
+    fa.reject = q.reject;
+    fa.pose = lv.pose.p;
+    fa.loglik = lv.loglik.p;
+    fa.uncert = lv.uncert.p;
+    fa.weight = lv.weight.p;
+    fa.idx = lv.idx.p;
+    fa.prefix = c->prefix.p;
+    fa.n_out = lv.n_out;
+    const bool last = L + 1 == q.n_levels;
+    fa.next_pose = last ? q.pose_out : c->lv[L + 1].pose.p;
+    fa.predict_next = last ? 0 : 1;
+    fa.est = last ? q.est_out : nullptr;
+    fa.flags = c->flags;
+    if ((s = run(K_LV_FINISH, 0, nr * 8.0 + lv.N * 120.0 + lv.n_out * 100.0,
+                 [&] { return launch_level_finish(fa, st); })))
+      return s;
+  }
+  return LOC_OK;
+}
+
+std::vector<double> level_signature(const loc_ctx* c, const LevelCall& q) {
+  std::vector<double> v = {(double)(uintptr_t)q.image, (double)q.cam.W, (double)q.cam.H, q.cam.fx, q.cam.fy,
+                           q.cam.cx, q.cam.cy, (double)q.n_levels, (double)q.N, (double)(uintptr_t)q.pose_in,
+                           (double)q.reject, (double)(uintptr_t)q.pose_out, (double)(uintptr_t)q.est_out};
+  for (int L = 0; L < q.n_levels; ++L) {
+    int ntl, waves, blocks;
+    level_cfg(c, L, ntl, waves, blocks);
+    for (double x : {(double)q.levels[L].inv_R, (double)q.levels[L].B, (double)q.levels[L].n_out, (double)ntl,
+                     (double)waves, (double)blocks, (double)(uintptr_t)c->lv[L].pose.p})
+      v.push_back(x);
+  }
+  return v;
+}
+
+void drop_graph(loc_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_sig.clear();
+}
+
+// argument checks and workspace of a level call; fills q
+loc_status prepare_levels(loc_ctx* c, const float* image, const loc_camera* cam, int n_levels,
+                          const loc_level* levels, int N, const double* pose_in, int reject, double* pose_out,
+                          double* est_out, LevelCall& q) {
+  if (!image || !cam || !levels || !pose_in || !pose_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  const loc_map_desc& d = c->desc;
+  if (c->kind != kMapSmall || d.precision != LOC_BF16 || d.n_coarse != 32 || d.n_fine != 0)
+    return fail(c, LOC_E_UNSUPPORTED, "the level path needs the 4x64 map in BF16 with 32 coarse and 0 fine samples");
+  if (n_levels < 1 || n_levels > 8) return fail(c, LOC_E_ARG, "n_levels must be in [1, 8]");
+  if (N < 1 || N > (1 << 20)) return fail(c, LOC_E_ARG, "N must be in [1, 2^20]");
+  if (!(cam->fx > 0 && cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || cam->W <= 0 ||
+      cam->H <= 0)
+    return fail(c, LOC_E_ARG, "invalid camera");
+  q.image = image;
+  q.cam = *cam;
+  q.n_levels = n_levels;
+  q.N = N;
+  q.pose_in = pose_in;
+  q.reject = reject ? 1 : 0;
+  q.pose_out = pose_out;
+  q.est_out = est_out;
+  int n_in = N;
+  size_t max_n = 0;
+  for (int L = 0; L < n_levels; ++L) {
+    const loc_level& v = levels[L];
+    if (v.inv_R != 1 && v.inv_R != 2 && v.inv_R != 4 && v.inv_R != 8)
+      return fail(c, LOC_E_ARG, "level %d: inv_R must be 1, 2, 4 or 8", L);
+    if (cam->W % v.inv_R || cam->H % v.inv_R) return fail(c, LOC_E_ARG, "level %d: image not divisible", L);
+    if (v.B < 1 || v.B > 1024) return fail(c, LOC_E_ARG, "level %d: B must be in [1, 1024]", L);
+    if (v.n_out < 1 || v.n_out > (1 << 20)) return fail(c, LOC_E_ARG, "level %d: n_out must be in [1, 2^20]", L);
+    if ((long)n_in * v.B > (1L << 26)) return fail(c, LOC_E_ARG, "level %d: too many rays", L);
+    q.levels[L] = v;
+    auto& lv = c->lv[L];
+    loc_status s;
+    if ((s = ensure(c, lv.pose, (size_t)n_in * 12)) || (s = ensure(c, lv.loglik, n_in)) ||
+        (s = ensure(c, lv.weight, n_in)) || (s = ensure(c, lv.uncert, n_in)) || (s = ensure(c, lv.idx, v.n_out)) ||
+        (s = ensure(c, lv.rgba, (size_t)n_in * v.B)) || (s = ensure(c, lv.fe, (size_t)n_in * v.B)))
+      return s;
+    if (lv.N != n_in || lv.B != v.B || lv.n_out != v.n_out) lv.ntl = lv.waves = lv.blocks = 0;   // retune
+    lv.N = n_in;
+    lv.B = v.B;
+    lv.n_out = v.n_out;
+    max_n = std::max(max_n, (size_t)n_in);
+    n_in = v.n_out;
+  }
+  c->n_lv = n_levels;
+  loc_status s;
+  if ((s = ensure(c, c->prefix, max_n))) return s;
+  if (!c->key && hipMalloc(&c->key, sizeof(LevelKey)) != hipSuccess) {
+    (void)hipGetLastError();
+    c->key = nullptr;
+    return fail(c, LOC_E_OOM, "level key");
+  }
+  if (!c->n_cu) {
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    c->n_cu = prop.multiProcessorCount;
+  }
+  return LOC_OK;
+}
+
+loc_status upload_key(loc_ctx* c, const double* motion, double sigma_t, double sigma_r, uint64_t seed,
+                      uint64_t iter) {
+  if (!(sigma_t >= 0.0) || !(sigma_r >= 0.0)) return fail(c, LOC_E_ARG, "negative noise scale");
+  LevelKey kv{};
+  kv.seed = seed;
+  kv.iter = iter;
+  for (int qd = 0; qd < 12; ++qd) kv.motion[qd] = motion ? motion[qd] : ((qd % 5 == 0) ? 1.0 : 0.0);
+  kv.sigma_t = sigma_t;
+  kv.sigma_r = sigma_r;
+  return timed(c, K_LV_KEY, 0, sizeof(LevelKey), [&] { return launch_set_key(c->key, kv, c->stream); });
+}
+
+}  // namespace
+
+extern "C" {
+
+loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* cam, int n_levels,
+                             const loc_level* levels, int N, const double* pose_in, const double* motion,
+                             double sigma_t, double sigma_r, uint64_t seed, uint64_t iter, int reject,
+                             double* pose_out, double* est_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  LevelCall q{};
+  loc_status s;
+  if ((s = prepare_levels(c, image, cam, n_levels, levels, N, pose_in, reject, pose_out, est_out, q))) return s;
+  {
+    hipError_t pe = hipGetLastError();
+    if (pe != hipSuccess) return fail(c, LOC_E_HIP, "pending HIP error: %s", hipGetErrorString(pe));
+  }
+  if ((s = upload_key(c, motion, sigma_t, sigma_r, seed, iter))) return s;
+  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof);
+  std::vector<double> sig = level_signature(c, q);
+  if (!c->gexec || sig != c->graph_sig) {
+    drop_graph(c);
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    loc_status cs = enqueue_levels(c, q, c->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (cs) { if (g) hipGraphDestroy(g); return cs; }
+    if (e != hipSuccess) return fail(c, LOC_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    c->graph = g;
+    e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_graph(c); return fail(c, LOC_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
+    c->graph_sig = sig;
+  }
+  HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+  return LOC_OK;
+}
+
+loc_status loc_set_graph_mode(loc_ctx* c, int enable) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  c->graph_mode = enable != 0;
+  if (!c->graph_mode) drop_graph(c);
+  return LOC_OK;
+}
+
+loc_status loc_level_outputs(loc_ctx* c, int level, double* loglik, double* weight, float* uncert, int32_t* idx,
+                             double* pose) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (level < 0 || level >= c->n_lv) return fail(c, LOC_E_STATE, "no level %d in the last level call", level);
+  const auto& L = c->lv[level];
+  if (loglik) HIP_TRY(c, hipMemcpyAsync(loglik, L.loglik.p, 8 * (size_t)L.N, hipMemcpyDeviceToDevice, c->stream));
+  if (weight) HIP_TRY(c, hipMemcpyAsync(weight, L.weight.p, 8 * (size_t)L.N, hipMemcpyDeviceToDevice, c->stream));
+  if (uncert) HIP_TRY(c, hipMemcpyAsync(uncert, L.uncert.p, 4 * (size_t)L.N, hipMemcpyDeviceToDevice, c->stream));
+  if (idx) HIP_TRY(c, hipMemcpyAsync(idx, L.idx.p, 4 * (size_t)L.n_out, hipMemcpyDeviceToDevice, c->stream));
+  if (pose) HIP_TRY(c, hipMemcpyAsync(pose, L.pose.p, 96 * (size_t)L.N, hipMemcpyDeviceToDevice, c->stream));
+  return LOC_OK;
+}
+
+loc_status loc_level_ray_outputs(loc_ctx* c, int level, float* rgb, float* opacity, float* F, float* E) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (level < 0 || level >= c->n_lv) return fail(c, LOC_E_STATE, "no level %d in the last level call", level);
+  const auto& L = c->lv[level];
+  const int n = L.N * L.B;
+  return timed(c, K_SPLIT, 0, 24.0 * n, [&] {
+    return launch_split_ray_outputs(L.rgba.p, L.fe.p, n, rgb, opacity, F, E, c->stream);
+  });
+}
+
+
+// Autotuner of the fused ray kernel: for every level of the given call, each
+// tile configuration (column tiles per wave x waves per workgroup) and grid
+// size (1, 2, 4 or 8 workgroups per CU, capped by the work) is timed over
+// `reps` launches after one warm-up on the level's real particles (an update
+// runs first to produce them), and the fastest is kept for the level.  With a
+// cache file, a level whose key (arch, map, N, B, scale) is already recorded
+// takes the recorded choice without timing, and new choices are appended as
+// one JSON object per line.
+loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera* cam, int n_levels,
+                               const loc_level* levels, int N, const double* pose_in, int reps,
+                               const char* cache_path, int* chosen) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (reps < 1 || reps > 1000) return fail(c, LOC_E_ARG, "reps must be in [1, 1000]");
+  const bool gm = c->graph_mode;
+  c->graph_mode = false;
+  drop_graph(c);
+  if (!levels || n_levels < 1 || n_levels > 8) {
+    c->graph_mode = gm;
+    return fail(c, LOC_E_ARG, "levels: NULL or n_levels outside [1, 8]");
+  }
+  const int n_last = levels[n_levels - 1].n_out;
+  if (n_last < 1 || n_last > (1 << 20)) {
+    c->graph_mode = gm;
+    return fail(c, LOC_E_ARG, "last level: n_out must be in [1, 2^20]");
+  }
+  double* pose_out = nullptr;
+  double* est = nullptr;
+  if (hipMalloc(&pose_out, (size_t)n_last * 96) != hipSuccess || hipMalloc(&est, 96) != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(pose_out);
+    c->graph_mode = gm;
+    return fail(c, LOC_E_OOM, "autotune buffers");
+  }
+  LevelCall q{};
+  loc_status s = prepare_levels(c, image, cam, n_levels, levels, N, pose_in, 1, pose_out, est, q);
+  if (s) {
+    hipFree(pose_out);
+    hipFree(est);
+    c->graph_mode = gm;
+    return s;
+  }
+  for (int L = 0; L < n_levels; ++L) c->lv[L].ntl = c->lv[L].waves = c->lv[L].blocks = 0;
+  const bool prof = c->prof;
+  c->prof = false;
+  s = upload_key(c, nullptr, 0.0, 0.0, 12345, 0);
+  if (!s) s = enqueue_levels(c, q, c->stream, false);
+  // cached choices
+  std::vector<std::string> cache_lines;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof line, f)) cache_lines.push_back(line);
+      std::fclose(f);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!s && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    s = fail(c, LOC_E_HIP, "event creation failed");
+  static const int kCand[5][2] = {{1, 4}, {1, 8}, {1, 16}, {2, 4}, {2, 8}};
+  for (int L = 0; !s && L < n_levels; ++L) {
+    auto& lv = c->lv[L];
+    char key[160];
+    std::snprintf(key, sizeof key, "gfx950/small-bf16-32/N%d/B%d/s%d", lv.N, lv.B, q.levels[L].inv_R);
+    bool found = false;
+    for (const auto& ln : cache_lines) {
+      char k2[160];
+      int ntl, waves, blocks;
+      if (std::sscanf(ln.c_str(), "{\"key\": \"%159[^\"]\", \"ntl\": %d, \"waves\": %d, \"blocks\": %d", k2, &ntl,
+                      &waves, &blocks) == 4 &&
+          std::strcmp(k2, key) == 0 && level_rays_config_ok(ntl, waves) && blocks >= 1) {
+        lv.ntl = ntl; lv.waves = waves; lv.blocks = blocks;
+        found = true;
+      }
+    }
+    if (found) continue;
+    const LevelRayArgs ra = level_ray_args(c, q, L);
+    const long n_rays = (long)lv.N * lv.B;
+    float best = 1e30f;
+    int bn = 1, bw = 8, bb = 1;
+    for (const auto& cd : kCand) {
+      const long tiles = (n_rays + (long)cd[0] * cd[1] - 1) / ((long)cd[0] * cd[1]);
+      int last_blocks = -1;
+      for (int mult : {1, 2, 4, 8}) {
+        const int blocks = (int)std::max(1L, std::min(tiles, (long)mult * c->n_cu));
+        if (blocks == last_blocks) continue;
+        last_blocks = blocks;
+        hipError_t e = launch_level_rays(ra, cd[0], cd[1], blocks, c->stream);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; e == hipSuccess && r < reps; ++r) e = launch_level_rays(ra, cd[0], cd[1], blocks, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { s = fail(c, LOC_E_HIP, "autotune launch: %s", hipGetErrorString(e)); break; }
+        if (ms < best) { best = ms; bn = cd[0]; bw = cd[1]; bb = blocks; }
+      }
+      if (s) break;
+    }
+    if (s) break;
+    lv.ntl = bn; lv.waves = bw; lv.blocks = bb;
+    if (cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "{\"key\": \"%s\", \"ntl\": %d, \"waves\": %d, \"blocks\": %d, \"us_per_launch\": %.3f}\n", key,
+                     bn, bw, bb, 1000.0 * best / reps);
+        std::fclose(f);
+      }
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(c->stream);
+  hipFree(pose_out);
+  hipFree(est);
+  c->prof = prof;
+  c->graph_mode = gm;
+  if (s) return s;
+  if (chosen)
+    for (int L = 0; L < n_levels; ++L) {
+      chosen[3 * L] = c->lv[L].ntl;
+      chosen[3 * L + 1] = c->lv[L].waves;
+      chosen[3 * L + 2] = c->lv[L].blocks;
+    }
+  return LOC_OK;
+}
+
+loc_status loc_set_level_tiles(loc_ctx* c, int level, int ntl, int waves, int blocks) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (level < 0 || level >= 8) return fail(c, LOC_E_ARG, "level out of range");
+  if (!(ntl == 0 && waves == 0 && blocks == 0) && (!level_rays_config_ok(ntl, waves) || blocks < 1))
+    return fail(c, LOC_E_ARG, "unsupported tile configuration");
+  c->lv[level].ntl = ntl;
+  c->lv[level].waves = waves;
+  c->lv[level].blocks = blocks;
   return LOC_OK;
 }
 
