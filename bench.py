@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLP samples/s & particle updates/s, BF16+proposal vs plain FP32, 1 GPU"
-PEAK = {"fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s")}
+PEAK = {"fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s"), "fp8": (5000.0, "TFLOP/s")}
 
 # HBM bytes per map-kernel launch (mean of the coarse and fine launches of one
 # step at 400 particles x 64 rays) from rocprofv3 FETCH_SIZE and WRITE_SIZE
@@ -66,9 +66,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large"],
                     help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision); "
-                         "copy: a plain 1 GiB device copy, the reference for HBM byte counters")
+                         "copy: a plain 1 GiB device copy, the reference for HBM byte counters; "
+                         "levels: the coarse-to-fine workload (eager and graph); large: the FP8 workload")
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--train-poses", type=int, default=31250, help="proposal training poses (x 64 rays)")
@@ -144,7 +145,8 @@ def summarize(spec, precision, N, B, steps, ms_total, kstats, counted=None):
     mlp_flop = sum(m["flop"] for m in mlp)
     achieved = (mlp_flop / launches) / (mlp_ms / launches * 1e-3) / 1e12
     peak, unit = PEAK[precision]
-    kname = ("k_mlp_f32" if precision == "fp32" else "k_mlp_bf16") + " (%dx%d map)" % (spec["n_layers"], spec["width"])
+    kname = {"fp32": "k_mlp_f32", "bf16": "k_mlp_bf16", "fp8": "k_mlp_fp8"}[precision] + \
+        " (%dx%d map)" % (spec["n_layers"], spec["width"])
     total_k = sum(x["ms"] for x in kstats.values())
     kernels = {k: {"launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1), "share": v["ms"] / total_k}
                for k, v in kstats.items()}
@@ -188,6 +190,108 @@ def copy_reference(args, torch):
     return 0
 
 
+def bench_levels(args, torch):
+    """The coarse-to-fine workload: 800x800 image, levels 1/4, 1/2, 1 with 16,
+    64, 256 rays per particle, 1000 -> 300 -> 100 particles, 1-sigma
+    rejection, 4x64 map in bf16, 32 samples per ray.  Tiles autotuned first
+    (untimed); then K updates eager (with per-kernel events) and K updates
+    replayed from the captured graph."""
+    from paper_2406_12202_amd import binding, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    levels = [(4, 16, 300), (2, 64, 100), (1, 256, 100)]
+    spec = synth.spec("c2f")
+    params = synth.map_params(spec, args.seed)
+    cam = synth.camera("c2f")
+    img_d = torch.as_tensor(synth.observation("c2f", args.seed), device=dev)
+    pose_d = torch.as_tensor(synth.particles("c2f", args.seed), device=dev)
+    N = pose_d.shape[0]
+    ctx = binding.Context(spec, params, precision="bf16", stream=stream)
+    chosen = ctx.loc_autotune_levels(img_d, cam, levels, pose_d, reps=10)
+    po = torch.empty((levels[-1][2], 3, 4), dtype=torch.float64, device=dev)
+    est = torch.empty((3, 4), dtype=torch.float64, device=dev)
+    kw = dict(sigma_t=0.02, sigma_r=0.0174533, reject=True, pose_out=po, est_out=est)
+
+    def run(mode, prof):
+        ctx.loc_set_graph_mode(mode == "graph")
+        for k in range(args.warmup):
+            ctx.loc_update_levels(img_d, cam, levels, pose_d, seed=args.seed, iter=3 * k, **kw)
+        torch.cuda.synchronize()
+        ctx.loc_set_profiling(prof)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(args.steps):
+            ctx.loc_update_levels(img_d, cam, levels, pose_d, seed=args.seed, iter=3 * (args.warmup + k), **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ks = ctx.loc_kernel_stats() if prof else {}
+        ctx.loc_set_profiling(False)
+        return e0.elapsed_time(e1) / args.steps, ks
+
+    ms_eager, ks = run("eager", True)
+    ms_eager_np, _ = run("eager", False)
+    ms_graph, _ = run("graph", False)
+    flags = ctx.loc_sync()
+    n_part = N + levels[0][2] + levels[1][2]
+    n_samples = 32 * (N * levels[0][1] + levels[0][2] * levels[1][1] + levels[1][2] * levels[2][1])
+    kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1)}
+               for k, v in ks.items() if v["launches"]}
+    rays = ks.get("level_rays", {"flop": 0, "ms": 1, "launches": 1})
+    out = {"metric": "coarse-to-fine update time", "value": ms_graph * 1e3, "unit": "us/update", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": False,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "c2f: 800x800, levels 1/4, 1/2, 1 with 16/64/256 rays, 1000 -> 300 -> 100 "
+                                  "particles, 1-sigma rejection, 4x64 map in bf16, 32 samples per ray"},
+           "us_per_update": {"graph": ms_graph * 1e3, "eager": ms_eager_np * 1e3, "eager_with_events": ms_eager * 1e3},
+           "particle_updates_per_s": n_part / (ms_graph * 1e-3), "samples_per_s": n_samples / (ms_graph * 1e-3),
+           "level_rays_TFLOPs": rays["flop"] / (rays["ms"] * 1e-3) / 1e12 if rays["ms"] else None,
+           "tiles": chosen, "kernels": kernels, "flags": flags}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def bench_large(args, torch):
+    """The FP8 workload: 2000 particles x 256 rays x (64 + 32 proposal-placed)
+    samples, 1008x756 forward-facing view; map calibrated and proposal
+    trained beforehand (untimed); K steps of update, read-out, resampling and
+    gather with the library's per-kernel events."""
+    from paper_2406_12202_amd import binding, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    spec = synth.spec("large")
+    params = synth.map_params(spec, args.seed)
+    cam = synth.camera("large")
+    W = synth.WORKLOADS["large"]
+    N, B = W["N"], W["B"]
+    ctx = binding.Context(spec, params, precision="fp8", stream=stream)
+    tp = torch.as_tensor(synth.training_poses("large", args.seed, 4096), device=dev)
+    O, D = ctx.loc_cast_rays(cam, 1, 64, tp, seed=args.seed + 1, iter=0)
+    ctx.loc_calibrate_fp8(O, D)
+    T = ctx.loc_teacher_histograms(O, D, 128, seed=args.seed + 1, iter=1)
+    ctx.loc_set_proposal(synth.proposal_params(args.seed))
+    ctx.loc_train_proposal(O, D, T, 8192, 1500, lr=2e-3)
+    ctx.loc_set_fine_mode(1)
+    del O, D, T, tp
+    img_d = torch.as_tensor(synth.observation("large", args.seed), device=dev)
+    pose_a = torch.as_tensor(synth.particles("large", args.seed), device=dev).contiguous()
+    ms, ks, flags = time_path(ctx, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
+    r = summarize(spec, "fp8", N, B, args.steps, ms, ks)
+    out = {"metric": "MLP samples/s (FP8 map, large workload)", "value": r["samples_per_s"], "unit": "samples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+           "higher_is_better": True, "dtype": "fp8-e4m3", "data": "synthetic",
+           "config": {"workload": "large: 2000 particles x 256 rays x (64 + 32 proposal-placed) samples, 8x256 map "
+                                  "with E4M3 hidden layers, 1008x756 forward-facing"},
+           "particle_updates_per_s": r["particle_updates_per_s"], "roofline": r["roofline"],
+           "kernels": r["kernels"], "flags": flags}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -197,6 +301,10 @@ def main():
     import torch
     if args.mode == "copy":
         return copy_reference(args, torch)
+    if args.mode == "levels":
+        return bench_levels(args, torch)
+    if args.mode == "large":
+        return bench_large(args, torch)
     from paper_2406_12202_amd import binding, synth
 
     wl = args.workload if args.mode == "single" else "nerf"

@@ -198,9 +198,9 @@ loc_status loc_fp8_scales(loc_ctx* ctx, int* ew, int* ea, float* amax, int n);
  * normalised (Eq. 3) and n_out particles are drawn (systematic, integer-exact,
  * as loc_resample) to carry on: N_0 = N, N_{L+1} = levels[L].n_out.
  * Per level the work is one persistent fused kernel over the level's rays
- * (ray generation, samples, encoding, map, compositing, F, E) and one
- * single-workgroup kernel (scores, rejection, normalisation, read-out,
- * resampling, gather, next prediction). */
+ * (ray generation, samples, encoding, map, compositing, F, E), a kernel of
+ * per-particle scores, and one single-workgroup kernel (rejection,
+ * normalisation, read-out, resampling, gather, next prediction). */
 typedef struct {
   int inv_R;   /* level scale R = 1 / inv_R, inv_R in {1, 2, 4, 8} */
   int B;       /* rays per particle, [1, 1024] */
@@ -248,8 +248,9 @@ loc_status loc_autotune_levels(loc_ctx* ctx, const float* image, const loc_camer
                                const loc_level* levels, int N, const double* pose_in, int reps,
                                const char* cache_path, int* chosen);
 
-/* Set level `level`'s tile choice by hand: (ntl, waves) in {(1,4), (1,8),
- * (1,16), (2,4), (2,8)}, blocks >= 1; (0, 0, 0) restores the default. */
+/* Set level `level`'s tile choice by hand: ntl = 2 (rays per wave pass),
+ * waves per workgroup in {2, 4, 8}, blocks >= 1; (0, 0, 0) restores the
+ * default. */
 loc_status loc_set_level_tiles(loc_ctx* ctx, int level, int ntl, int waves, int blocks);
 
 /* Poses of the resampled set (Alg. 1, "add x_t^[i] to X_t"): pose_out[k] =

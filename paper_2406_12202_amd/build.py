@@ -19,6 +19,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # no packed FP32 instructions in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-add fusion only within one expression: kernels that share
+         # a formula (ray, sample depth, compositing) then round it alike
+         "-ffp-contract=on",
          "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

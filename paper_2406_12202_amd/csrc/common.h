@@ -48,6 +48,25 @@ __host__ __device__ inline float unit24(uint32_t w) { return (float)(w >> 8) * 5
 // uniform in (0, 1): (w + 1/2) 2^-32, exact in double
 __host__ __device__ inline double unit_open(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
 
+// ---------------------------------------------------------------- camera rays
+// Ray of pixel (u, v) for a camera-to-world pose P (3 x 4, row-major): OpenGL
+// camera looking along -z, pixel centres at +1/2 (Eq. 4's r(p, x) with
+// intrinsics K); the rotation is applied in float64 with explicit fused
+// multiply-adds (so every kernel that forms a ray gets the same bits) and the
+// unit direction is rounded once to float32.
+__device__ __forceinline__ void camera_ray(const double* P, int u, int v, double fx, double fy, double cx, double cy,
+                                           float (&o)[3], float (&d)[3]) {
+  const double dc0 = ((double)u + 0.5 - cx) / fx;
+  const double dc1 = -((double)v + 0.5 - cy) / fy;
+  double d0 = fma(P[0], dc0, fma(P[1], dc1, -P[2]));
+  double d1 = fma(P[4], dc0, fma(P[5], dc1, -P[6]));
+  double d2 = fma(P[8], dc0, fma(P[9], dc1, -P[10]));
+  const double inv = 1.0 / sqrt(fma(d0, d0, fma(d1, d1, d2 * d2)));
+  d0 *= inv; d1 *= inv; d2 *= inv;
+  o[0] = (float)P[3]; o[1] = (float)P[7]; o[2] = (float)P[11];
+  d[0] = (float)d0; d[1] = (float)d1; d[2] = (float)d2;
+}
+
 // ---------------------------------------------------------------- wave primitives
 __device__ inline float wave_incl_scan(float v, int lane) {
 #pragma unroll
@@ -66,6 +85,36 @@ __device__ inline int wave_min_int(int v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
   return v;
+}
+
+// Eq. 6's per-particle sums in one fixed order, shared by every kernel that
+// forms them: with G = particle_group(B) lanes per particle, lane g adds
+// E_j F_j and F_j for j = g, g + G, ... in float64, then a butterfly (xor
+// G/2, ..., 1) within the group combines the G partial sums; addition being
+// commutative, every lane of the group ends with the same totals.
+// get(j, ef, f) supplies the float32 E_j F_j and F_j.  The G lanes must be an
+// aligned group of a wave, and all lanes of the wave must call together.
+__host__ __device__ inline int particle_group(int B) {
+  int G = 1;
+  while (G * 2 <= B && G < kWave) G *= 2;
+  return G;
+}
+
+template <class Get>
+__device__ inline void particle_sums(Get get, int B, int G, int g, double& S, double& Fs) {
+  double s = 0.0, f = 0.0;
+  for (int j = g; j < B; j += G) {
+    float ef, fj;
+    get(j, ef, fj);
+    s += (double)ef;
+    f += (double)fj;
+  }
+  for (int o = G / 2; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, kWave);
+    f += __shfl_xor(f, o, kWave);
+  }
+  S = s;
+  Fs = f;
 }
 
 }  // namespace fl

@@ -200,6 +200,7 @@ hipError_t launch_level_predict(const LevelKey* key, const double* pose_in, doub
 // tile configuration (column tiles per wave, waves per workgroup), grid size
 hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int blocks, hipStream_t st);
 bool level_rays_config_ok(int ntl, int waves);
+hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st);
 hipError_t launch_level_finish(const LevelFinishArgs& a, hipStream_t st);
 
 }  // namespace fl

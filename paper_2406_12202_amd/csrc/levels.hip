@@ -79,19 +79,81 @@ __device__ __forceinline__ void dense_res(const uint4* w, const float* bl, const
   }
 }
 
-template <int NTL, int WAVES>
-struct LevelCfg {
-  static constexpr int THREADS = 64 * WAVES;
-  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + LS::HEADS * 4 +
-                              (long)WAVES * NTL * (LS::KBX + LS::KBD) * 1024;
+// per-lane set-up of ray r as k_raygen computes it: query pixel p_j, the
+// unit direction through it (rotation in float64, one rounding to float32),
+// the origin, and the S x S box average of the observation (row-major sum in
+// float64); S is the level factor
+constexpr int kRayBatch = 8;   // rays set up per wave at once (one per lane)
+
+struct RaySetup {
+  float o[3], d[3], obs[3];
+  int i, j;
 };
 
-template <int NTL, int WAVES>
+template <int S>
+__device__ __forceinline__ void ray_setup(const LevelRayArgs& a, uint64_t seed, uint64_t iter, long r, RaySetup& rs) {
+  const int i = (int)(r / a.B), j = (int)(r - (r / a.B) * a.B);
+  rs.i = i;
+  rs.j = j;
+  const uint32_t w = draw(seed, iter, kStreamPix, (uint32_t)j, 0, 0).x;
+  const uint32_t npix = (uint32_t)a.Wl * (uint32_t)a.Hl;
+  const uint32_t p = (uint32_t)(((uint64_t)w * npix) >> 32);
+  const int u = (int)(p % (uint32_t)a.Wl), v = (int)(p / (uint32_t)a.Wl);
+  camera_ray(a.pose + (long)i * 12, u, v, a.fx, a.fy, a.cx, a.cy, rs.o, rs.d);
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll
+  for (int yy = 0; yy < S; ++yy) {
+    const float* row = a.image + ((long)(v * S + yy) * a.W_full + (long)u * S) * 3;
+    float px[3 * S];
+#pragma unroll
+    for (int e = 0; e < 3 * S; ++e) px[e] = row[e];
+#pragma unroll
+    for (int xx = 0; xx < S; ++xx) { c0 += px[3 * xx]; c1 += px[3 * xx + 1]; c2 += px[3 * xx + 2]; }
+  }
+  const double sc = 1.0 / ((double)S * S);
+  rs.obs[0] = (float)(c0 * sc); rs.obs[1] = (float)(c1 * sc); rs.obs[2] = (float)(c2 * sc);
+}
+
+// segmented wave primitives over the two 32-lane halves (for lanes of half 0
+// they give bitwise the results of the full-wave primitives when lanes 32..63
+// hold zeros, which is how the unfused compositing kernel uses them)
+__device__ __forceinline__ float half_incl_scan(float v, int n) {
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const float u = __shfl_up(v, o, 32);
+    if (n >= o) v += u;
+  }
+  return v;
+}
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+  return v;
+}
+__device__ __forceinline__ int half_min_int(int v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 32));
+  return v;
+}
+
+template <int WAVES>
+struct LevelCfg {
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + (long)WAVES * 2 * (LS::KBX + LS::KBD) * 1024;
+};
+
+// Rays go through the wave in pairs: lane (n, h) = lane n + 32 h owns sample
+// n of ray h of the pair for everything outside the MFMAs (jitter, depth,
+// encoding, head nonlinearities, compositing), so no lane repeats another's
+// work; the encodings are written in the MFMA operand layout of column tile h
+// (both k-halves of sample n), the map runs on the two tiles, and the head
+// rows of tile 1 are moved from half 0 to half 1 by one shuffle per row.
+template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a) {
-  using C = LevelCfg<NTL, WAVES>;
+  using C = LevelCfg<WAVES>;
+  constexpr int NTL = 2;
   __shared__ uint4 s_w[LS::BLOCKS * 64];
   __shared__ float4 s_bias[LS::BIASES / 4];
-  __shared__ float s_heads[LS::HEADS];
   __shared__ uint4 s_gx[WAVES][NTL * LS::KBX * 64];
   __shared__ uint4 s_gd[WAVES][NTL * LS::KBD * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -101,161 +163,172 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
     for (int i = threadIdx.x; i < LS::BLOCKS * 64; i += C::THREADS) s_w[i] = wb[i];
     for (int i = threadIdx.x; i < LS::BIASES / 4; i += C::THREADS)
       s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
-    for (int i = threadIdx.x; i < LS::HEADS; i += C::THREADS) s_heads[i] = a.heads[i];
   }
   __syncthreads();
   const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
   const float* bias = reinterpret_cast<const float*>(s_bias);
   const long n_rays = (long)a.N * a.B;
-  const long n_tiles = (n_rays + NTL - 1) / NTL;
+  const long n_batches = (n_rays + kRayBatch - 1) / kRayBatch;
   const long n_waves = (long)gridDim.x * WAVES;
-  for (long tile = (long)blockIdx.x * WAVES + wv; tile < n_tiles; tile += n_waves) {
-    long ray[NTL];
-    bool act[NTL];
-    float t[NTL], obs[NTL][3];
-#pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) {
-      const long r0 = tile * NTL + nt;
-      act[nt] = r0 < n_rays;
-      const long r = act[nt] ? r0 : n_rays - 1;
-      ray[nt] = r;
-      const int i = (int)(r / a.B), j = (int)(r - (r / a.B) * a.B);
-      // ray of query pixel p_j (as k_raygen)
-      const uint32_t w = draw(seed, iter, kStreamPix, (uint32_t)j, 0, 0).x;
-      const uint64_t npix = (uint64_t)a.Wl * (uint64_t)a.Hl;
-      const uint64_t p = ((uint64_t)w * npix) >> 32;
-      const int u = (int)(p % (uint64_t)a.Wl), v = (int)(p / (uint64_t)a.Wl);
-      const double* P = a.pose + (long)i * 12;
-      const double dc0 = ((double)u + 0.5 - a.cx) / a.fx;
-      const double dc1 = -((double)v + 0.5 - a.cy) / a.fy;
-      const double dc2 = -1.0;
-      double d0 = P[0] * dc0 + P[1] * dc1 + P[2] * dc2;
-      double d1 = P[4] * dc0 + P[5] * dc1 + P[6] * dc2;
-      double d2 = P[8] * dc0 + P[9] * dc1 + P[10] * dc2;
-      const double inv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      d0 *= inv; d1 *= inv; d2 *= inv;
-      const float4 o = make_float4((float)P[3], (float)P[7], (float)P[11], 0.0f);
-      const float4 d = make_float4((float)d0, (float)d1, (float)d2, 0.0f);
-      // downscale(I_t, R_t) at the query pixel
-      double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-      for (int yy = 0; yy < a.s; ++yy) {
-        const float* row = a.image + ((long)(v * a.s + yy) * a.W_full + (long)u * a.s) * 3;
-        for (int xx = 0; xx < a.s; ++xx) {
-          c0 += row[3 * xx + 0]; c1 += row[3 * xx + 1]; c2 += row[3 * xx + 2];
-        }
+  for (long bt = (long)blockIdx.x * WAVES + wv; bt < n_batches; bt += n_waves) {
+    // lane q (mod kRayBatch) sets up ray bt * kRayBatch + q
+    RaySetup rs;
+    {
+      long r = bt * kRayBatch + (lane & (kRayBatch - 1));
+      if (r >= n_rays) r = n_rays - 1;
+      switch (a.s) {
+        case 1: ray_setup<1>(a, seed, iter, r, rs); break;
+        case 2: ray_setup<2>(a, seed, iter, r, rs); break;
+        case 4: ray_setup<4>(a, seed, iter, r, rs); break;
+        default: ray_setup<8>(a, seed, iter, r, rs); break;
       }
-      const double sc = 1.0 / ((double)a.s * a.s);
-      obs[nt][0] = (float)(c0 * sc); obs[nt][1] = (float)(c1 * sc); obs[nt][2] = (float)(c2 * sc);
-      // stratified sample k = n of this ray (as the coarse pass of k_mlp_bf16)
+    }
+    for (int q0 = 0; q0 < kRayBatch; q0 += 2) {
+      // this lane's ray (q0 + h) and sample n
+      const int q = q0 + h;
+      const long ray = bt * kRayBatch + q;
+      const float4 o = make_float4(__shfl(rs.o[0], q, 64), __shfl(rs.o[1], q, 64), __shfl(rs.o[2], q, 64), 0.0f);
+      const float4 d = make_float4(__shfl(rs.d[0], q, 64), __shfl(rs.d[1], q, 64), __shfl(rs.d[2], q, 64), 0.0f);
+      const float ob0 = __shfl(rs.obs[0], q, 64), ob1 = __shfl(rs.obs[1], q, 64), ob2 = __shfl(rs.obs[2], q, 64);
+      const int i = __shfl(rs.i, q, 64), j = __shfl(rs.j, q, 64);
       const int k = n;
       float xi = 0.0f;
       if (a.jitter) xi = unit24(pick(draw(seed, iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
-      t[nt] = a.near_ + ((float)k + xi) * a.dt;
-      bf16x8 gx[LS::KBX], gd[LS::KBD];
-      posenc_b<LS::LX>(fmaf(t[nt], d.x, o.x), fmaf(t[nt], d.y, o.y), fmaf(t[nt], d.z, o.z), h, gx);
-      posenc_b<LS::LD>(d.x, d.y, d.z, h, gd);
+      const float tk = a.near_ + ((float)k + xi) * a.dt;
+      {
+        bf16x8 gx[2][LS::KBX], gd[2][LS::KBD];
+        posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), gx);
+        posenc_both<LS::LD, LS::KBD>(d.x, d.y, d.z, gd);
 #pragma unroll
-      for (int kb = 0; kb < LS::KBX; ++kb) s_gx[wv][(nt * LS::KBX + kb) * 64 + lane] = __builtin_bit_cast(uint4, gx[kb]);
+        for (int hh = 0; hh < 2; ++hh) {
 #pragma unroll
-      for (int kb = 0; kb < LS::KBD; ++kb) s_gd[wv][(nt * LS::KBD + kb) * 64 + lane] = __builtin_bit_cast(uint4, gd[kb]);
-    }
-    // the map (layer order and arithmetic of k_mlp_bf16 for this shape)
-    bf16x8 xa[NTL][LS::KBH], xb[NTL][LS::KBH];
-    dense_res<NTL, LS::MT, LS::KBX, LS::KBH, true, LS::KBH>(s_w + LS::block_base(0) * 64, bias + LS::bias_base(0) + h * 16,
-                                                           true, xb, s_gx[wv], xa, lane);
+          for (int kb = 0; kb < LS::KBX; ++kb)
+            s_gx[wv][(h * LS::KBX + kb) * 64 + n + 32 * hh] = __builtin_bit_cast(uint4, gx[hh][kb]);
 #pragma unroll
-    for (int l = 1; l < LS::D; ++l) {
-      dense_res<NTL, LS::MT, LS::KBH, LS::KBH, false, LS::KBH>(s_w + LS::block_base(l) * 64,
-                                                              bias + LS::bias_base(l) + h * 16, true, xa, nullptr,
-                                                              xb, lane);
-#pragma unroll
-      for (int nt = 0; nt < NTL; ++nt)
-#pragma unroll
-        for (int q = 0; q < LS::KBH; ++q) xa[nt][q] = xb[nt][q];
-    }
-    const float* hs = s_heads + LS::SIG_OFF;
-    const float* hr = s_heads + LS::RGB_OFF;
-#pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) {
-      float z = dot_b<LS::KBH>(hs + h * LS::KBH * 8, xa[nt]);
-      z += __shfl_xor(z, 32, 64);
-      const float sg = softplus_b(z + hs[16 * LS::KBH]);
-      float rgb[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float* w = hr + (c * 2 + h) * LS::KBG * 8;
-        bf16x8 gd[LS::KBD];
-#pragma unroll
-        for (int kb = 0; kb < LS::KBD; ++kb)
-          gd[kb] = __builtin_bit_cast(bf16x8, s_gd[wv][(nt * LS::KBD + kb) * 64 + lane]);
-        float zc = dot_b<LS::KBH>(w, xa[nt]) + dot_b<LS::KBD>(w + LS::KBH * 8, gd);
-        zc += __shfl_xor(zc, 32, 64);
-        rgb[c] = sigmoid_b(zc + hr[48 * LS::KBG + c]);
+          for (int kb = 0; kb < LS::KBD; ++kb)
+            s_gd[wv][(h * LS::KBD + kb) * 64 + n + 32 * hh] = __builtin_bit_cast(uint4, gd[hh][kb]);
+        }
       }
-      // compositing along the ray (as k_composite with one sample per lane):
-      // lanes 0..31 hold samples 0..31, lanes 32..63 contribute nothing
-      const bool mine = h == 0;
-      const float tk = t[nt];
-      float tn = __shfl_down(tk, 1, 64);
+      // the encodings written by other lanes of this wave are read below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // the map on both column tiles (layer order and arithmetic of k_mlp_bf16)
+      bf16x8 xa[NTL][LS::KBH], xb[NTL][LS::KBH];
+      dense_res<NTL, LS::MT, LS::KBX, LS::KBH, true, LS::KBH>(s_w + LS::block_base(0) * 64,
+                                                             bias + LS::bias_base(0) + h * 16, true, xb, s_gx[wv],
+                                                             xa, lane);
+#pragma unroll
+      for (int l = 1; l < LS::D; ++l) {
+        dense_res<NTL, LS::MT, LS::KBH, LS::KBH, false, LS::KBH>(s_w + LS::block_base(l) * 64,
+                                                                bias + LS::bias_base(l) + h * 16, true, xa, nullptr,
+                                                                xb, lane);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt)
+#pragma unroll
+          for (int qq = 0; qq < LS::KBH; ++qq) xa[nt][qq] = xb[nt][qq];
+      }
+      f32x16 hacc[NTL];
+      head_tile<LS, NTL>(s_w + LS::HEAD_BLOCK * 64, bias + LS::HEAD_BIAS + h * 16, xa, s_gd[wv], lane, hacc);
+      // head rows 0..3 of tile h: half 0 holds them for both tiles
+      float hv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float t1 = __shfl(hacc[1][v], n, 64);
+        hv[v] = h ? t1 : hacc[0][v];
+      }
+      // everything below reads only lanes of the same half before the
+      // shuffles of the next pair
+      __builtin_amdgcn_wave_barrier();
+      const float sg = softplus_b(hv[0]);
+      const float cr0 = sigmoid_b(hv[1]), cg0 = sigmoid_b(hv[2]), cb0 = sigmoid_b(hv[3]);
+      // compositing along the ray (as k_composite with one sample per lane)
+      float tn = __shfl_down(tk, 1, 32);
       if (n + 1 >= kLevelSpr) tn = a.far_;
       float lsum = 0.0f;
-      if (mine) lsum += sg * (tn - tk);
-      const float incl = wave_incl_scan(lsum, lane);
+      lsum += sg * (tn - tk);
+      const float incl = half_incl_scan(lsum, n);
       float run = -(incl - lsum);
-      float cr = 0.0f, cg = 0.0f, cb = 0.0f, accw = 0.0f, lt = 0.0f;
+      float cr = 0.0f, cg = 0.0f, cb = 0.0f, accw = 0.0f;
       int ktr = 1 << 30, kop = 1 << 30;
-      if (mine) {
-        const float tau = sg * (tn - tk);
-        const float w = expf(run) * -expm1f(-tau);
-        lt = run;
-        cr = fmaf(w, rgb[0], cr); cg = fmaf(w, rgb[1], cg); cb = fmaf(w, rgb[2], cb);
-        accw += w;
-        run -= tau;
-        if (run <= a.log_trans) ktr = n;
-        if (run < a.log_opq) kop = n;
-      }
-      cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb); accw = wave_sum(accw);
-      ktr = wave_min_int(ktr);
-      kop = wave_min_int(kop);
+      const float tau = sg * (tn - tk);
+      const float w = expf(run) * -expm1f(-tau);
+      const float lt = run;
+      cr = fmaf(w, cr0, cr); cg = fmaf(w, cg0, cg); cb = fmaf(w, cb0, cb);
+      accw += w;
+      run -= tau;
+      if (run <= a.log_trans) ktr = n;
+      if (run < a.log_opq) kop = n;
+      cr = half_sum(cr); cg = half_sum(cg); cb = half_sum(cb); accw = half_sum(accw);
+      ktr = half_min_int(ktr);
+      kop = half_min_int(kop);
       float F = a.tau;
       if (ktr < kLevelSpr) {
-        const float t_tr = __shfl(tk, ktr, 64), l_tr = __shfl(lt, ktr, 64), s_tr = __shfl(sg, ktr, 64);
+        const float t_tr = __shfl(tk, ktr, 32), l_tr = __shfl(lt, ktr, 32), s_tr = __shfl(sg, ktr, 32);
         const int ko = kop < kLevelSpr ? kop : 0;
-        const float t_op = __shfl(tk, ko, 64), l_op = __shfl(lt, ko, 64), s_op = __shfl(sg, ko, 64);
+        const float t_op = __shfl(tk, ko, 32), l_op = __shfl(lt, ko, 32), s_op = __shfl(sg, ko, 32);
         const float zt = t_tr + (l_tr - a.log_trans) / s_tr;
         const float zo = (kop < kLevelSpr) ? t_op + (l_op - a.log_opq) / s_op : a.far_;
         F = fmaxf(zo - zt, a.tau);
       }
-      const float er = obs[nt][0] - cr, eg = obs[nt][1] - cg, eb = obs[nt][2] - cb;
+      const float er = ob0 - cr, eg = ob1 - cg, eb = ob2 - cb;
       const float E = er * er + eg * eg + eb * eb;
-      if (act[nt] && lane == 0) {
-        a.ray_rgba[ray[nt]] = make_float4(cr, cg, cb, accw);
-        a.ray_fe[ray[nt]] = make_float2(F, E);
+      if (ray < n_rays && n == 0) {
+        a.ray_rgba[ray] = make_float4(cr, cg, cb, accw);
+        a.ray_fe[ray] = make_float2(F, E);
       }
     }
   }
 }
 
-template <int NTL, int WAVES>
+template <int WAVES>
 hipError_t launch_level_rays_t(const LevelRayArgs& a, int blocks, hipStream_t st) {
-  static_assert(LevelCfg<NTL, WAVES>::LDS <= 160 * 1024, "LDS budget");
-  hipLaunchKernelGGL((k_level_rays<NTL, WAVES>), dim3(blocks), dim3(64 * WAVES), 0, st, a);
+  static_assert(LevelCfg<WAVES>::LDS <= 160 * 1024, "LDS budget");
+  hipLaunchKernelGGL((k_level_rays<WAVES>), dim3(blocks), dim3(64 * WAVES), 0, st, a);
   return hipGetLastError();
 }
 
-bool level_rays_config_ok(int ntl, int waves) {
-  return (ntl == 1 && (waves == 4 || waves == 8 || waves == 16)) || (ntl == 2 && (waves == 4 || waves == 8));
-}
+bool level_rays_config_ok(int ntl, int waves) { return ntl == 2 && (waves == 2 || waves == 4 || waves == 8); }
 
 hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int blocks, hipStream_t st) {
   if ((long)a.N * a.B <= 0) return hipSuccess;
-  if (blocks < 1) return hipErrorInvalidValue;
-  if (ntl == 1 && waves == 4) return launch_level_rays_t<1, 4>(a, blocks, st);
-  if (ntl == 1 && waves == 8) return launch_level_rays_t<1, 8>(a, blocks, st);
-  if (ntl == 1 && waves == 16) return launch_level_rays_t<1, 16>(a, blocks, st);
-  if (ntl == 2 && waves == 4) return launch_level_rays_t<2, 4>(a, blocks, st);
-  if (ntl == 2 && waves == 8) return launch_level_rays_t<2, 8>(a, blocks, st);
+  if (blocks < 1 || ntl != 2) return hipErrorInvalidValue;
+  if (waves == 2) return launch_level_rays_t<2>(a, blocks, st);
+  if (waves == 4) return launch_level_rays_t<4>(a, blocks, st);
+  if (waves == 8) return launch_level_rays_t<8>(a, blocks, st);
   return hipErrorInvalidValue;
+}
+
+// per-particle scores: groups of G lanes per particle (the order of
+// particle_sums), 256 threads per workgroup; the float64 mean F waits in
+// weight[] for the rejection statistics
+constexpr int kScoreThreads = 256;
+
+__global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a) {
+  const int G = particle_group(a.B);
+  const int tid = blockIdx.x * kScoreThreads + threadIdx.x;
+  const int g = threadIdx.x & (G - 1);
+  const int i = tid / G;
+  if (i >= a.N) return;   // whole groups leave together
+  double S_i, Fs;
+  particle_sums([&](int jj, float& ef, float& f) {
+    const float2 fe = a.ray_fe[(long)i * a.B + jj];
+    ef = fe.y * fe.x;
+    f = fe.x;
+  }, a.B, G, g, S_i, Fs);
+  if (g == 0) {
+    const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
+    a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
+    a.uncert[i] = (float)(Fs / a.B);
+    a.weight[i] = Fs / a.B;
+  }
+}
+
+hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
+  const long threads = (long)a.N * particle_group(a.B);
+  hipLaunchKernelGGL(k_level_scores, dim3((unsigned)((threads + kScoreThreads - 1) / kScoreThreads)),
+                     dim3(kScoreThreads), 0, st, a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -265,22 +338,7 @@ __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishA
   __shared__ double s_stat[2];
   const int tid = threadIdx.x;
   const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
-  // per-particle score (fixed order over the rays, as k_composite) and mean F;
-  // the float64 mean F waits in weight[] for the rejection statistics
-  for (int i = tid; i < a.N; i += kRedThreads) {
-    double S_i = 0.0, Fs = 0.0;
-    for (int j = 0; j < a.B; ++j) {
-      const float2 fe = a.ray_fe[(long)i * a.B + j];
-      S_i += (double)(fe.y * fe.x);
-      Fs += (double)fe.x;
-    }
-    const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
-    a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
-    a.uncert[i] = (float)(Fs / a.B);
-    a.weight[i] = Fs / a.B;
-  }
-  __threadfence_block();
-  __syncthreads();
+  // scores, mean F (in weight[]) come from k_level_scores
   if (a.reject) {
     // mean and population standard deviation of the mean F over particles
     // with finite mean F and finite l; particles above mean + std get -inf

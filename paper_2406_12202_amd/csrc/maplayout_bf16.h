@@ -16,7 +16,11 @@
 //
 // Weights are stored as "chunks", one per (layer, output m-tile) in execution
 // order; a chunk is kb 1 KB blocks, block k holding the 64 lanes' 16-byte A
-// operands of k-block k.  Biases and the density / colour heads stay float32.
+// operands of k-block k.  Biases stay float32.  Maps without a direction
+// layer evaluate both heads as one more MFMA tile after the trunk: rows 0
+// (density, over the trunk output) and 1..3 (colour, over the trunk output
+// and gamma(d)), KBH + KBD blocks after the layers and 32 biases after the
+// layers' biases.  Maps with a direction layer keep float32 heads.
 #pragma once
 
 namespace fl {
@@ -49,8 +53,11 @@ struct ShapeB {
     for (int i = 0; i < l; ++i) o += 32L * layer_mt(i);
     return o;
   }
-  static constexpr long BLOCKS = block_base(NL);
-  static constexpr long BIASES = bias_base(NL);
+  static constexpr int HEAD_KB = DW > 0 ? 0 : KBH + KBD;   // head tile (maps without direction layer)
+  static constexpr long HEAD_BLOCK = block_base(NL);
+  static constexpr long HEAD_BIAS = bias_base(NL);
+  static constexpr long BLOCKS = block_base(NL) + HEAD_KB;
+  static constexpr long BIASES = bias_base(NL) + (DW > 0 ? 0 : 32);
   static constexpr int MAX_KB = (KBH + KBX) > (KBH + KBD) ? (KBH + KBX) : (KBH + KBD);
   static constexpr long SIG_OFF = 0;              // float offsets in the head buffer
   static constexpr long SIG_SIZE = 16L * KBH + 4;

@@ -14,29 +14,57 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// bf16 operands of the encoding gamma(p) (pseudo-pair layout of maplayout_bf16.h)
+// bf16 operands of the encoding gamma(p) (pseudo-pair layout of
+// maplayout_bf16.h).  sin and cos of band 0 come from sincospif; band b + 1
+// follows from band b by the double-angle identities sin 2a = 2 sin a cos a,
+// cos 2a = (cos a - sin a)(cos a + sin a).  Each doubling at most doubles the
+// absolute error, so band L - 1 is within 2^(L-1) float32 roundings
+// (6e-5 for L = 10) of the exact value, far inside the bf16 rounding of the
+// operands (2^-9 relative).
+// values of both lane halves: out[hh][kb] is the operand of half hh
+template <int L, int KB>
+__device__ __forceinline__ void posenc_both(const float p0, const float p1, const float p2, bf16x8 (&out)[2][KB]) {
+  float sn[3][L], cs[3][L];
+  const float pc[3] = {p0, p1, p2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    sincospif(pc[c], &sn[c][0], &cs[c][0]);
+#pragma unroll
+    for (int l = 1; l < L; ++l) {
+      const float sa = sn[c][l - 1], ca = cs[c][l - 1];
+      sn[c][l] = 2.0f * sa * ca;
+      cs[c][l] = (ca - sa) * (ca + sa);
+    }
+  }
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = 8 * kb + 4 * hh + j;
+        float a = 0.0f, b = 0.0f;
+        if (p < 3 * L) {
+          a = sn[p % 3][p / 3];
+          b = cs[p % 3][p / 3];
+        } else if (p == 3 * L) {
+          a = p0; b = p1;
+        } else if (p == 3 * L + 1) {
+          a = p2;
+        }
+        out[hh][kb][2 * j] = (__bf16)a;
+        out[hh][kb][2 * j + 1] = (__bf16)b;
+      }
+}
+
+// the operands of lane half h
 template <int L, int KB>
 __device__ __forceinline__ void posenc_b(const float p0, const float p1, const float p2, const int h,
                                          bf16x8 (&out)[KB]) {
+  bf16x8 both[2][KB];
+  posenc_both<L, KB>(p0, p1, p2, both);
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int p = 8 * kb + 4 * h + j;
-      float a = 0.0f, b = 0.0f;
-      if (p < 3 * L) {
-        const int c = p % 3;
-        const float x = c == 0 ? p0 : (c == 1 ? p1 : p2);
-        sincospif(ldexpf(x, p / 3), &a, &b);
-      } else if (p == 3 * L) {
-        a = p0; b = p1;
-      } else if (p == 3 * L + 1) {
-        a = p2;
-      }
-      out[kb][2 * j] = (__bf16)a;
-      out[kb][2 * j + 1] = (__bf16)b;
-    }
-  }
+  for (int kb = 0; kb < KB; ++kb) out[kb] = h ? both[1][kb] : both[0][kb];
 }
 
 // issue the direct loads of nkb consecutive 1 KB units into an LDS slot;
@@ -133,5 +161,37 @@ __device__ __forceinline__ float dot_b(const float* __restrict__ w, const bf16x8
 
 __device__ __forceinline__ float softplus_b(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
 __device__ __forceinline__ float sigmoid_b(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// both heads of a map without direction layer as one MFMA tile: acc rows 0
+// (density) and 1..3 (colour) in lanes of half 0, from the head chunk w
+// (KBH blocks over the trunk output x, then KBD over gamma(d) in gd_lds)
+template <class S, int NTL>
+__device__ __forceinline__ void head_tile(const uint4* w, const float* bl, const bf16x8 (&x)[NTL][S::KBH],
+                                          const uint4* gd_lds, const int lane, f32x16 (&acc)[NTL]) {
+  f32x16 binit;
+  const float4* b4 = reinterpret_cast<const float4*>(bl);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 v = b4[i];
+    binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
+  }
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+#pragma unroll
+  for (int kb = 0; kb < S::KBH; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, w[kb * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[nt][kb], acc[nt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int kb = 0; kb < S::KBD; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, w[(S::KBH + kb) * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) {
+      const bf16x8 bx = __builtin_bit_cast(bf16x8, gd_lds[(nt * S::KBD + kb) * 64 + lane]);
+      acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+    }
+  }
+}
 
 }  // namespace fl

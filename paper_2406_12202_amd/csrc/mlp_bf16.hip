@@ -43,6 +43,8 @@ __device__ __forceinline__ void dense_b(const uint4* __restrict__ wb, const floa
         issue_blocks<WAVES>(wb, base + (long)(mt + MPC) * kb_tot, MPC * kb_tot, nxt, wv, lane);
       else if (l + 1 < S::NL)
         issue_blocks<WAVES>(wb, S::block_base(l + 1), MPC * S::layer_kb(l + 1), nxt, wv, lane);
+      else if (S::HEAD_KB > 0)
+        issue_blocks<WAVES>(wb, S::HEAD_BLOCK, S::HEAD_KB, nxt, wv, lane);
     }
     const uint4* cur = grp + (mt % MPC) * kb_tot * 64;
     // bias of this tile's 16 rows (lane half h), used as the accumulator input
@@ -127,16 +129,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
 #pragma unroll
       for (int i = 0; i < S::KBH; ++i) xa[nt][i] = xb[nt][i];
   }
-  const float* __restrict__ hs = a.heads + S::SIG_OFF;
   float sigma[NTL], rgb[NTL][3];
+  if constexpr (S::HEAD_KB > 0) {
+    // both heads as one MFMA tile (rows 0: density, 1..3: colour) from the
+    // chunk that follows the last layer's; it sits in slot0 (each layer has
+    // an even number of chunk groups)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    f32x16 acc[NTL];
+    head_tile<S, NTL>(slot0, bias + S::HEAD_BIAS + h * 16, xa, s_gd[wv], lane, acc);
 #pragma unroll
-  for (int nt = 0; nt < NTL; ++nt) {
-    float z = dot_b<S::KBH>(hs + h * S::KBH * 8, xa[nt]);
-    z += __shfl_xor(z, 32, 64);
-    sigma[nt] = softplus_b(z + hs[16 * S::KBH]);
-  }
-  const float* __restrict__ hr = a.heads + S::RGB_OFF;
-  if constexpr (S::DW > 0) {
+    for (int nt = 0; nt < NTL; ++nt) {
+      sigma[nt] = softplus_b(acc[nt][0]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(acc[nt][1 + c]);
+    }
+  } else {
+    const float* __restrict__ hs = a.heads + S::SIG_OFF;
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) {
+      float z = dot_b<S::KBH>(hs + h * S::KBH * 8, xa[nt]);
+      z += __shfl_xor(z, 32, 64);
+      sigma[nt] = softplus_b(z + hs[16 * S::KBH]);
+    }
+    const float* __restrict__ hr = a.heads + S::RGB_OFF;
     dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D, false, false, slot0, slot1,
                                                                      xa, nullptr, s_gd[wv], xb, wv, lane);
     dense_b<S, NTL, WAVES, MPC, S::MTD, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D + 1, true, true, slot0,
@@ -146,19 +162,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         float z = dot_b<S::KBG>(hr + (c * 2 + h) * S::KBG * 8, xa[nt]);
-        z += __shfl_xor(z, 32, 64);
-        rgb[nt][c] = sigmoid_b(z + hr[48 * S::KBG + c]);
-      }
-  } else {
-#pragma unroll
-    for (int nt = 0; nt < NTL; ++nt)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float* w = hr + (c * 2 + h) * S::KBG * 8;
-        bf16x8 gd[S::KBD];
-#pragma unroll
-        for (int kb = 0; kb < S::KBD; ++kb) gd[kb] = __builtin_bit_cast(bf16x8, s_gd[wv][(nt * S::KBD + kb) * 64 + lane]);
-        float z = dot_b<S::KBH>(w, xa[nt]) + dot_b<S::KBD>(w + S::KBH * 8, gd);
         z += __shfl_xor(z, 32, 64);
         rgb[nt][c] = sigmoid_b(z + hr[48 * S::KBG + c]);
       }

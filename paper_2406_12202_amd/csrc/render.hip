@@ -18,17 +18,10 @@ __global__ __launch_bounds__(256) void k_raygen(const RaygenArgs a) {
   const uint64_t npix = (uint64_t)a.Wl * (uint64_t)a.Hl;
   const uint64_t p = ((uint64_t)w * npix) >> 32;
   const int u = (int)(p % (uint64_t)a.Wl), v = (int)(p / (uint64_t)a.Wl);
-  const double* P = a.pose + (long)i * 12;
-  const double dc0 = ((double)u + 0.5 - a.cx) / a.fx;
-  const double dc1 = -((double)v + 0.5 - a.cy) / a.fy;
-  const double dc2 = -1.0;
-  double d0 = P[0] * dc0 + P[1] * dc1 + P[2] * dc2;
-  double d1 = P[4] * dc0 + P[5] * dc1 + P[6] * dc2;
-  double d2 = P[8] * dc0 + P[9] * dc1 + P[10] * dc2;
-  const double inv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  d0 *= inv; d1 *= inv; d2 *= inv;
-  a.ray_o[r] = make_float4((float)P[3], (float)P[7], (float)P[11], 0.0f);
-  a.ray_d[r] = make_float4((float)d0, (float)d1, (float)d2, 0.0f);
+  float o[3], d[3];
+  camera_ray(a.pose + (long)i * 12, u, v, a.fx, a.fy, a.cx, a.cy, o, d);
+  a.ray_o[r] = make_float4(o[0], o[1], o[2], 0.0f);
+  a.ray_d[r] = make_float4(d[0], d[1], d[2], 0.0f);
   if (!a.image) return;
   // downscale(I_t, R_t): mean of the s x s block behind level pixel (u, v)
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
@@ -261,12 +254,17 @@ __global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  if (threadIdx.x == 0 && a.loglik) {
+  if (wv == 0 && a.loglik) {
+    // lanes 0 .. G-1 form the particle's group; the rest add nothing
+    const int G = particle_group(a.B);
     double S_i = 0.0, Fs = 0.0;
-    for (int j = 0; j < a.B; ++j) { S_i += (double)s_ef[j]; Fs += (double)s_f[j]; }
-    const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
-    a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
-    if (a.uncert) a.uncert[i] = (float)(Fs / a.B);
+    particle_sums([&](int j, float& ef, float& f) { ef = s_ef[j]; f = s_f[j]; }, lane < G ? a.B : 0, G, lane,
+                  S_i, Fs);
+    if (lane == 0) {
+      const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
+      a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
+      if (a.uncert) a.uncert[i] = (float)(Fs / a.B);
+    }
   }
 }
 

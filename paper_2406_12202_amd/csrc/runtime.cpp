@@ -24,12 +24,12 @@ namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
                 K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
-                K_LV_PREDICT, K_LV_RAYS, K_LV_FINISH, K_COUNT };
+                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
                                      "pose_estimate", "fp8_calibration", "level_key", "level_predict",
-                                     "level_rays", "level_finish"};
+                                     "level_rays", "level_scores", "level_finish"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -327,6 +327,34 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
       for (int h = 0; h < 2; ++h)
         for (int v = 0; v < 16; ++v)
           P.bias[S::bias_base(l) + (mt * 2 + h) * 16 + v] = cn.b[ci][32 * mt + 8 * (v / 4) + 4 * h + v % 4];
+  }
+  if constexpr (S::HEAD_KB > 0) {
+    // head tile: row 0 density (trunk output), rows 1..3 colour (trunk output, gamma(d))
+    const int ci = (int)cn.W.size() - 1;
+    for (int kb = 0; kb < S::HEAD_KB; ++kb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int q = 0; q < 8; ++q) {
+          const int row = lane % 32, h = lane / 32;
+          float v = 0.0f;
+          if (row == 0 && kb < S::KBH) {
+            v = cn.W[S::D][chain_feature_b(kb, h, q)];
+          } else if (row >= 1 && row <= 3) {
+            const int c = row - 1, nin = cn.nin[ci];
+            int col;
+            if (kb < S::KBH) col = chain_feature_b(kb, h, q);
+            else {
+              const int f = posenc_feature_b(S::LD, kb - S::KBH, h, q);
+              col = f >= 0 ? S::W + f : -1;
+            }
+            v = col >= 0 ? cn.W[ci][c * nin + col] : 0.0f;
+          }
+          P.blocks[(size_t)((S::HEAD_BLOCK + kb) * 64 + lane) * 8 + q] = to_bf16(v);
+        }
+    for (int h = 0; h < 2; ++h)
+      for (int v = 0; v < 16; ++v) {
+        const int row = 8 * (v / 4) + 4 * h + v % 4;
+        P.bias[S::HEAD_BIAS + h * 16 + v] = row == 0 ? cn.b[S::D][0] : (row <= 3 ? cn.b[ci][row - 1] : 0.0f);
+      }
   }
   float* sig = P.heads.data() + S::SIG_OFF;
   for (int h = 0; h < 2; ++h)
@@ -1192,10 +1220,10 @@ namespace {
 
 // default tile choice: one 32-sample tile per wave, 8 waves, two workgroups per CU
 void level_default_cfg(const loc_ctx* c, long n_rays, int& ntl, int& waves, int& blocks) {
-  ntl = 1;
-  waves = 8;
-  const long tiles = (n_rays + ntl * waves - 1) / (ntl * waves);
-  blocks = (int)std::max(1L, std::min(tiles, 2L * c->n_cu));
+  ntl = 2;
+  waves = 4;
+  const long batches = (n_rays + 7) / 8;   // rays set up per wave at once
+  blocks = (int)std::max(1L, std::min((batches + waves - 1) / waves, 2L * c->n_cu));
 }
 
 void level_cfg(const loc_ctx* c, int L, int& ntl, int& waves, int& blocks) {
@@ -1290,8 +1318,8 @@ loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool p
     fa.predict_next = last ? 0 : 1;
     fa.est = last ? q.est_out : nullptr;
     fa.flags = c->flags;
-    if ((s = run(K_LV_FINISH, 0, nr * 8.0 + lv.N * 120.0 + lv.n_out * 100.0,
-                 [&] { return launch_level_finish(fa, st); })))
+    if ((s = run(K_LV_SCORES, 0, nr * 8.0 + lv.N * 20.0, [&] { return launch_level_scores(fa, st); }))) return s;
+    if ((s = run(K_LV_FINISH, 0, lv.N * 120.0 + lv.n_out * 100.0, [&] { return launch_level_finish(fa, st); })))
       return s;
   }
   return LOC_OK;
@@ -1523,7 +1551,7 @@ loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera*
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!s && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     s = fail(c, LOC_E_HIP, "event creation failed");
-  static const int kCand[5][2] = {{1, 4}, {1, 8}, {1, 16}, {2, 4}, {2, 8}};
+  static const int kCand[3][2] = {{2, 2}, {2, 4}, {2, 8}};
   for (int L = 0; !s && L < n_levels; ++L) {
     auto& lv = c->lv[L];
     char key[160];
@@ -1545,7 +1573,7 @@ loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera*
     float best = 1e30f;
     int bn = 1, bw = 8, bb = 1;
     for (const auto& cd : kCand) {
-      const long tiles = (n_rays + (long)cd[0] * cd[1] - 1) / ((long)cd[0] * cd[1]);
+      const long tiles = ((n_rays + 7) / 8 + cd[1] - 1) / cd[1];   // workgroups with work
       int last_blocks = -1;
       for (int mult : {1, 2, 4, 8}) {
         const int blocks = (int)std::max(1L, std::min(tiles, (long)mult * c->n_cu));

@@ -136,7 +136,7 @@ def test_levels_match_oracle_lockstep(torch_dev):
     assert np.isfinite(r["pose"]).all() and np.isfinite(r["est"]).all()
 
 
-@pytest.mark.parametrize("ntl,waves,blocks", [(1, 4, 7), (1, 16, 300), (2, 4, 1), (2, 8, 64), (1, 8, 2048)])
+@pytest.mark.parametrize("ntl,waves,blocks", [(2, 2, 7), (2, 4, 300), (2, 8, 1), (2, 8, 64), (2, 2, 2048)])
 def test_levels_tile_configurations_bitwise(torch_dev, ntl, waves, blocks):
     torch = torch_dev
     s, p, cam, poses, img = _setup(73, 80)
