@@ -41,9 +41,9 @@ PEAK = {"fp32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s"), "fp8": (5000.0,
 # x1.0), together with a digest of the kernel sources they were taken on: the
 # figure is reported only while the sources are unchanged.
 TRAFFIC = {
-    "bf16": {"sources": ("mlp_bf16.hip", "mfma_util.h", "maplayout_bf16.h", "common.h"), "digest": "2c2d5588b35f41ed",
-             "bytes": {"headline": ((11.746e6 + 32.768e6) + (14.204e6 + 13.107e6)) / 2}},
-    "fp32": {"sources": ("mlp_f32.hip", "maplayout.h", "common.h"), "digest": "a40493ded30e7163",
+    "bf16": {"sources": ("mlp_bf16.hip", "mfma_util.h", "maplayout_bf16.h", "common.h"), "digest": "6ae9e6b0dac9a5a4",
+             "bytes": {"headline": ((11.668e6 + 32.768e6) + (14.126e6 + 13.107e6)) / 2}},
+    "fp32": {"sources": ("mlp_f32.hip", "maplayout.h", "common.h"), "digest": "6604d0af64e52fa1",
              "bytes": {"headline": ((26.498e6 + 32.768e6) + (39.600e6 + 52.429e6)) / 2}},
 }
 
