@@ -139,7 +139,7 @@ def time_path(ctx, img_d, cam, B, pose_a, steps, warmup, seed, torch):
 
 def summarize(spec, precision, N, B, steps, ms_total, kstats, counted=None):
     S = spec["n_coarse"] + spec["n_fine"]
-    mlp = [kstats[k] for k in ("mlp_coarse", "mlp_fine") if k in kstats]
+    mlp = [kstats[k] for k in ("mlp_coarse", "mlp_fine", "mlp_coarse_fine") if k in kstats]
     launches = sum(m["launches"] for m in mlp)
     mlp_ms = sum(m["ms"] for m in mlp)
     mlp_flop = sum(m["flop"] for m in mlp)

@@ -29,6 +29,14 @@ struct MlpArgs {
   // applied to layer l's output before it is rounded to E4M3
   int f8_sw[12], f8_sx[12];
   float f8_qout[12];
+  // optional second sample set evaluated by the same launch (BF16 and FP8
+  // kernels): samples n_samples .. n_samples + n_samples2 - 1 are sample
+  // s - n_samples of this set, laid out [ray][k] with spr2 per ray, depths
+  // from t_in2, outputs to out2
+  const float* t_in2;
+  float4* out2;
+  long n_samples2;
+  int spr2;
 };
 hipError_t launch_mlp(int map_kind, const MlpArgs& a, hipStream_t st);
 hipError_t launch_mlp_bf16(int map_kind, const MlpArgs& a, hipStream_t st);

@@ -16,11 +16,13 @@
 //
 // Weights are stored as "chunks", one per (layer, output m-tile) in execution
 // order; a chunk is kb 1 KB blocks, block k holding the 64 lanes' 16-byte A
-// operands of k-block k.  Biases stay float32.  Maps without a direction
-// layer evaluate both heads as one more MFMA tile after the trunk: rows 0
+// operands of k-block k.  Biases stay float32.  The heads are MFMA tiles too,
+// stored after the layers ("tail tiles") with 32 biases each after the
+// layers' biases: a map without direction layer has one tile, rows 0
 // (density, over the trunk output) and 1..3 (colour, over the trunk output
-// and gamma(d)), KBH + KBD blocks after the layers and 32 biases after the
-// layers' biases.  Maps with a direction layer keep float32 heads.
+// and gamma(d)), KBH + KBD blocks; a map with a direction layer has a density
+// tile (row 0 over the trunk output, KBH blocks) and a colour tile (rows 0..2
+// over the direction layer's output, DW / 16 blocks).
 #pragma once
 
 namespace fl {
@@ -53,11 +55,18 @@ struct ShapeB {
     for (int i = 0; i < l; ++i) o += 32L * layer_mt(i);
     return o;
   }
-  static constexpr int HEAD_KB = DW > 0 ? 0 : KBH + KBD;   // head tile (maps without direction layer)
-  static constexpr long HEAD_BLOCK = block_base(NL);
-  static constexpr long HEAD_BIAS = bias_base(NL);
-  static constexpr long BLOCKS = block_base(NL) + HEAD_KB;
-  static constexpr long BIASES = bias_base(NL) + (DW > 0 ? 0 : 32);
+  static constexpr int SIG_KB = DW > 0 ? KBH : KBH + KBD;   // first tail tile
+  static constexpr int RGB_KB = DW > 0 ? DW / 16 : 0;         // second tail tile (maps with a direction layer)
+  static constexpr long SIG_BLOCK = block_base(NL);
+  static constexpr long RGB_BLOCK = SIG_BLOCK + SIG_KB;
+  static constexpr long SIG_BIAS = bias_base(NL);
+  static constexpr long RGB_BIAS = SIG_BIAS + 32;
+  static constexpr long BLOCKS = RGB_BLOCK + RGB_KB;
+  static constexpr long BIASES = SIG_BIAS + (DW > 0 ? 64 : 32);
+  // the single head tile of a map without direction layer
+  static constexpr int HEAD_KB = DW > 0 ? 0 : SIG_KB;
+  static constexpr long HEAD_BLOCK = SIG_BLOCK;
+  static constexpr long HEAD_BIAS = SIG_BIAS;
   static constexpr int MAX_KB = (KBH + KBX) > (KBH + KBD) ? (KBH + KBX) : (KBH + KBD);
   static constexpr long SIG_OFF = 0;              // float offsets in the head buffer
   static constexpr long SIG_SIZE = 16L * KBH + 4;

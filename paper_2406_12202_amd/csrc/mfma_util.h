@@ -81,23 +81,33 @@ __device__ __forceinline__ void issue_blocks(const uint4* __restrict__ wb, const
 // stratified with jitter and written out), then gamma(x) and gamma(d) as bf16
 // operands into the wave's LDS blocks laid out [column tile][k-block][lane].
 // Each lane later reads back only its own entries, so no barrier is needed.
+// Samples past n_samples belong to the optional second set (t_in2, out2):
+// sidx is the index within the sample's set, seg2 tells which set.
 template <int LX, int LD, int KBX, int KBD, int NTL>
 __device__ __forceinline__ void stage_samples(const MlpArgs& a, const long tile, const int lane, uint4* gx_lds,
-                                              uint4* gd_lds, long (&sidx)[NTL], bool (&valid)[NTL]) {
+                                              uint4* gd_lds, long (&sidx)[NTL], bool (&valid)[NTL],
+                                              bool (&seg2)[NTL]) {
   const int n = lane & 31, h = lane >> 5;
+  const long n_tot = a.n_samples + a.n_samples2;
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt) {
     const long s = tile * (32 * NTL) + nt * 32 + n;
-    valid[nt] = s < a.n_samples;
-    sidx[nt] = s;
-    const long sc = valid[nt] ? s : a.n_samples - 1;
-    const int ray = (int)(sc / a.spr);
-    const int k = (int)(sc - (long)ray * a.spr);
+    valid[nt] = s < n_tot;
+    const long sc = valid[nt] ? s : n_tot - 1;
+    const bool second = sc >= a.n_samples;
+    seg2[nt] = second;
+    const long sl = second ? sc - a.n_samples : sc;
+    sidx[nt] = sl;
+    const int spr = second ? a.spr2 : a.spr;
+    const int ray = (int)(sl / spr);
+    const int k = (int)(sl - (long)ray * spr);
     const float4 o = a.ray_o[ray];
     const float4 d = a.ray_d[ray];
     float t;
-    if (a.t_in) {
-      t = a.t_in[sc];
+    if (second) {
+      t = a.t_in2[sl];
+    } else if (a.t_in) {
+      t = a.t_in[sl];
     } else {
       float xi = 0.0f;
       if (a.jitter) {
@@ -105,7 +115,7 @@ __device__ __forceinline__ void stage_samples(const MlpArgs& a, const long tile,
         xi = unit24(pick(draw(a.seed, a.iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
       }
       t = a.near_ + ((float)k + xi) * a.dt;
-      if (valid[nt] && h == 0) a.t_out[s] = t;
+      if (valid[nt] && h == 0) a.t_out[sl] = t;
     }
     bf16x8 gx[KBX], gd[KBD];
     posenc_b<LX>(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z), h, gx);

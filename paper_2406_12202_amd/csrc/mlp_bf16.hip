@@ -3,48 +3,72 @@
 //
 // A workgroup is WAVES waves; each wave evaluates NTL column tiles of 32
 // samples.  The packed weights are a sequence of chunks (one per layer and
-// 32-row output tile, see maplayout_bf16.h); the workgroup streams MPC
-// consecutive chunks at a time through two LDS slots with direct global->LDS
-// loads (global_load_lds_dwordx4), prefetching the next group while all waves
-// multiply the current one.  Each 16-byte weight fragment read from LDS feeds
-// NTL MFMAs.  The bias enters as the accumulator input of the first MFMA of a
-// tile, and ReLU runs on packed bf16 pairs after rounding, so the epilogue of a
-// tile is one conversion and one packed max per pair of outputs.
+// 32-row output tile, then the head tiles, see maplayout_bf16.h); the
+// workgroup streams up to MPC consecutive chunks of one item at a time (a
+// "group") through two LDS slots with direct global->LDS loads
+// (global_load_lds_dwordx4), prefetching the next group while all waves
+// multiply the current one; groups alternate between the slots by a running
+// count.  Each 16-byte weight fragment read from LDS feeds NTL MFMAs.  The
+// bias enters as the accumulator input of the first MFMA of a tile, and ReLU
+// runs on packed bf16 pairs after rounding, so the epilogue of a tile is one
+// conversion and one packed max per pair of outputs.  The density and colour
+// heads are tiles of the same stream, evaluated on MFMA like the layers.
 #include "mfma_util.h"
 #include "maplayout_bf16.h"
 
 namespace fl {
 
-// One MFMA layer: y = act(b + W [x1, x2]) for MTO output tiles of 32 rows.
-// Chunk groups of MPC m-tiles alternate between slot0 and slot1 (every layer
-// has an even number of groups, so the slot of a tile is static).  On entry
-// the loads of this layer's first group are in flight.  x1 is a register
-// array (chained activations) or, when X1_LDS, the wave's encoding block in
-// LDS; x2 (the encoding segment) comes from LDS, laid out
-// [column tile][k-block][lane].
+// chunk stream of one workgroup: weights, the two LDS slots, running group count
+struct ChunkStream {
+  const uint4* wb;
+  uint4* slot0;
+  uint4* slot1;
+  int g;
+  int wv, lane;
+};
+
+// first group of an item: (first block, 1 KB units)
+struct NextGroup {
+  long base;
+  int units;
+};
+
+// start of the next group: wait for its loads (issued when the previous group
+// started, or by the prologue), then issue the loads of the group after it
+// into the other slot
+template <int WAVES>
+__device__ __forceinline__ const uint4* group_begin(ChunkStream& st, const NextGroup nx) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  uint4* cur = (st.g & 1) ? st.slot1 : st.slot0;
+  uint4* nxt = (st.g & 1) ? st.slot0 : st.slot1;
+  if (nx.units > 0) issue_blocks<WAVES>(st.wb, nx.base, nx.units, nxt, st.wv, st.lane);
+  ++st.g;
+  return cur;
+}
+
+// One MFMA layer: y = act(b + W [x1, x2]) for MTO output tiles of 32 rows,
+// chunks of kb_tot blocks from `base`; `after` is the first group of the
+// item that follows.  x1 is a register array (chained activations) or, when
+// X1_LDS, the wave's encoding block in LDS; x2 (the encoding segment) comes
+// from LDS, laid out [column tile][k-block][lane].
 template <class S, int NTL, int WAVES, int MPC, int MTO, int KB1, int KB2, int NY, bool X1_LDS, int NX1>
-__device__ __forceinline__ void dense_b(const uint4* __restrict__ wb, const float* bias_lds, const int l,
-                                        const bool use2, const bool relu, uint4* slot0, uint4* slot1,
-                                        const bf16x8 (&x1)[NTL][NX1], const uint4* x1s, const uint4* x2s,
-                                        bf16x8 (&y)[NTL][NY], const int wv, const int lane) {
-  static_assert(MTO % (2 * MPC) == 0 && 2 * MTO <= NY && (X1_LDS || KB1 <= NX1), "layout");
-  const int h = lane >> 5;
+__device__ __forceinline__ void dense_b(ChunkStream& st, const long base, const float* bl, const bool use2,
+                                        const bool relu, const NextGroup after, const bf16x8 (&x1)[NTL][NX1],
+                                        const uint4* x1s, const uint4* x2s, bf16x8 (&y)[NTL][NY]) {
+  static_assert(2 * MTO <= NY && (X1_LDS || KB1 <= NX1), "layout");
+  const int lane = st.lane;
   const int kb_tot = KB1 + (use2 ? KB2 : 0);
-  const long base = S::block_base(l);
-  const float* bl = bias_lds + S::bias_base(l) + h * 16;
+  const uint4* grp = nullptr;
 #pragma unroll
   for (int mt = 0; mt < MTO; ++mt) {
-    uint4* grp = ((mt / MPC) & 1) ? slot1 : slot0;
     if (mt % MPC == 0) {
-      uint4* nxt = ((mt / MPC) & 1) ? slot0 : slot1;
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      if (mt + MPC < MTO)
-        issue_blocks<WAVES>(wb, base + (long)(mt + MPC) * kb_tot, MPC * kb_tot, nxt, wv, lane);
-      else if (l + 1 < S::NL)
-        issue_blocks<WAVES>(wb, S::block_base(l + 1), MPC * S::layer_kb(l + 1), nxt, wv, lane);
-      else if (S::HEAD_KB > 0)
-        issue_blocks<WAVES>(wb, S::HEAD_BLOCK, S::HEAD_KB, nxt, wv, lane);
+      NextGroup nx = after;
+      if (mt + MPC < MTO) {
+        nx.base = base + (long)(mt + MPC) * kb_tot;
+        nx.units = (MTO - mt - MPC < MPC ? MTO - mt - MPC : MPC) * kb_tot;
+      }
+      grp = group_begin<WAVES>(st, nx);
     }
     const uint4* cur = grp + (mt % MPC) * kb_tot * 64;
     // bias of this tile's 16 rows (lane half h), used as the accumulator input
@@ -60,15 +84,35 @@ __device__ __forceinline__ void dense_b(const uint4* __restrict__ wb, const floa
     f32x16 acc[NTL];
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+    {
+      // A fragments in pairs, the next pair read while this one multiplies
+      constexpr int G = 2;
+      constexpr int NG = (KB1 + G - 1) / G;
+      bf16x8 abuf[2][G];
 #pragma unroll
-    for (int kb = 0; kb < KB1; ++kb) {
-      const bf16x8 a = __builtin_bit_cast(bf16x8, cur[kb * 64 + lane]);
+      for (int kk = 0; kk < G; ++kk)
+        if (kk < KB1) abuf[0][kk] = __builtin_bit_cast(bf16x8, cur[kk * 64 + lane]);
 #pragma unroll
-      for (int nt = 0; nt < NTL; ++nt) {
-        bf16x8 bx;
-        if constexpr (X1_LDS) bx = __builtin_bit_cast(bf16x8, x1s[(nt * KB1 + kb) * 64 + lane]);
-        else bx = x1[nt][kb];
-        acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+      for (int gg = 0; gg < NG; ++gg) {
+        if (gg + 1 < NG) {
+#pragma unroll
+          for (int kk = 0; kk < G; ++kk)
+            if ((gg + 1) * G + kk < KB1)
+              abuf[(gg + 1) & 1][kk] = __builtin_bit_cast(bf16x8, cur[((gg + 1) * G + kk) * 64 + lane]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < G; ++kk) {
+          const int kb = gg * G + kk;
+          if (kb < KB1) {
+#pragma unroll
+            for (int nt = 0; nt < NTL; ++nt) {
+              bf16x8 bx;
+              if constexpr (X1_LDS) bx = __builtin_bit_cast(bf16x8, x1s[(nt * KB1 + kb) * 64 + lane]);
+              else bx = x1[nt][kb];
+              acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(abuf[gg & 1][kk], bx, acc[nt], 0, 0, 0);
+            }
+          }
+        }
       }
     }
     if (use2) {
@@ -87,12 +131,51 @@ __device__ __forceinline__ void dense_b(const uint4* __restrict__ wb, const floa
   }
 }
 
+// a head tile of the stream: acc = b + W [x, x2] (one 32-row tile, one group)
+template <int NTL, int WAVES, int KB1, int KB2, int NX>
+__device__ __forceinline__ void head_b(ChunkStream& st, const float* bl, const NextGroup after,
+                                       const bf16x8 (&x)[NTL][NX], const uint4* x2s, f32x16 (&acc)[NTL]) {
+  const uint4* cur = group_begin<WAVES>(st, after);
+  const int lane = st.lane;
+  f32x16 binit;
+  const float4* b4 = reinterpret_cast<const float4*>(bl);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 v = b4[i];
+    binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
+  }
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+#pragma unroll
+  for (int kb = 0; kb < KB1; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, cur[kb * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[nt][kb], acc[nt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int kb = 0; kb < KB2; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, cur[(KB1 + kb) * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) {
+      const bf16x8 bx = __builtin_bit_cast(bf16x8, x2s[(nt * KB2 + kb) * 64 + lane]);
+      acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+    }
+  }
+}
+
 template <class S, int NTL, int WAVES, int MPC>
 struct BCfg {
   static constexpr int SLOT_KB = MPC * S::MAX_KB;   // 1 KB blocks per LDS slot
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int SAMPLES = 32 * NTL * WAVES;  // per workgroup
 };
+
+// first group of layer l (execution order)
+template <class S, int MPC>
+__device__ __forceinline__ NextGroup first_group(const int l) {
+  const int mt = S::layer_mt(l) < MPC ? S::layer_mt(l) : MPC;
+  return NextGroup{S::block_base(l), mt * S::layer_kb(l)};
+}
 
 template <class S, int NTL, int WAVES, int MPC>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
@@ -104,86 +187,92 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
   __shared__ float4 s_bias[S::BIASES / 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int h = lane >> 5;
-  const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
+  ChunkStream st{reinterpret_cast<const uint4*>(a.wblocks), slot0, slot1, 0, wv, lane};
   // weights of layer 0's first chunk group start loading while the inputs
   // are encoded; biases go to LDS (visible after the first barrier)
-  issue_blocks<WAVES>(wb, 0, MPC * S::layer_kb(0), slot0, wv, lane);
+  {
+    const NextGroup g0 = first_group<S, MPC>(0);
+    issue_blocks<WAVES>(st.wb, g0.base, g0.units, slot0, wv, lane);
+  }
   for (int i = threadIdx.x; i < S::BIASES / 4; i += C::THREADS)
     s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
 
   const long tile = (long)blockIdx.x * WAVES + wv;
   long sidx[NTL];
-  bool valid[NTL];
-  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid);
+  bool valid[NTL], seg2[NTL];
+  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid, seg2);
 
   const float* bias = reinterpret_cast<const float*>(s_bias);
+  const NextGroup sig_group{S::SIG_BLOCK, S::SIG_KB};
   bf16x8 xa[NTL][S::KBH], xb[NTL][S::KBH];
-  dense_b<S, NTL, WAVES, MPC, S::MT, S::KBX, S::KBD, S::KBH, true>(wb, bias, 0, false, true, slot0, slot1, xb,
-                                                                  s_gx[wv], s_gd[wv], xa, wv, lane);
+  dense_b<S, NTL, WAVES, MPC, S::MT, S::KBX, S::KBD, S::KBH, true>(
+      st, S::block_base(0), bias + S::bias_base(0) + h * 16, false, true,
+      S::D > 1 ? first_group<S, MPC>(1) : sig_group, xb, s_gx[wv], s_gd[wv], xa);
+  // hidden layers 1 .. D-1, ping-ponging between xa and xb; the result ends
+  // in xa (a final copy when D - 1 is odd)
 #pragma unroll 1
-  for (int l = 1; l < S::D; ++l) {
-    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBX, S::KBH, false>(wb, bias, l, l == S::SKIP, true, slot0,
-                                                                     slot1, xa, nullptr, s_gx[wv], xb, wv, lane);
+  for (int l = 1; l < S::D; l += 2) {
+    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBX, S::KBH, false>(
+        st, S::block_base(l), bias + S::bias_base(l) + h * 16, l == S::SKIP, true,
+        l + 1 < S::D ? first_group<S, MPC>(l + 1) : sig_group, xa, nullptr, s_gx[wv], xb);
+    if (l + 1 < S::D)
+      dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBX, S::KBH, false>(
+          st, S::block_base(l + 1), bias + S::bias_base(l + 1) + h * 16, l + 1 == S::SKIP, true,
+          l + 2 < S::D ? first_group<S, MPC>(l + 2) : sig_group, xb, nullptr, s_gx[wv], xa);
+  }
+  if constexpr ((S::D - 1) % 2 == 1) {
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
       for (int i = 0; i < S::KBH; ++i) xa[nt][i] = xb[nt][i];
   }
+  // heads: rows of the head tiles in lanes of half 0 (density row 0; colour
+  // rows 1..3 of the single tile, or rows 0..2 of the colour tile)
   float sigma[NTL], rgb[NTL][3];
-  if constexpr (S::HEAD_KB > 0) {
-    // both heads as one MFMA tile (rows 0: density, 1..3: colour) from the
-    // chunk that follows the last layer's; it sits in slot0 (each layer has
-    // an even number of chunk groups)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    f32x16 acc[NTL];
-    head_tile<S, NTL>(slot0, bias + S::HEAD_BIAS + h * 16, xa, s_gd[wv], lane, acc);
+  f32x16 hacc[NTL];
+  if constexpr (S::DW == 0) {
+    head_b<NTL, WAVES, S::KBH, S::KBD>(st, bias + S::SIG_BIAS + h * 16, NextGroup{0, 0}, xa, s_gd[wv], hacc);
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt) {
-      sigma[nt] = softplus_b(acc[nt][0]);
+      sigma[nt] = softplus_b(hacc[nt][0]);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(acc[nt][1 + c]);
+      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][1 + c]);
     }
   } else {
-    const float* __restrict__ hs = a.heads + S::SIG_OFF;
+    head_b<NTL, WAVES, S::KBH, 0>(st, bias + S::SIG_BIAS + h * 16, first_group<S, MPC>(S::D), xa, nullptr, hacc);
 #pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) {
-      float z = dot_b<S::KBH>(hs + h * S::KBH * 8, xa[nt]);
-      z += __shfl_xor(z, 32, 64);
-      sigma[nt] = softplus_b(z + hs[16 * S::KBH]);
-    }
-    const float* __restrict__ hr = a.heads + S::RGB_OFF;
-    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D, false, false, slot0, slot1,
-                                                                     xa, nullptr, s_gd[wv], xb, wv, lane);
-    dense_b<S, NTL, WAVES, MPC, S::MTD, S::KBH, S::KBD, S::KBH, false>(wb, bias, S::D + 1, true, true, slot0,
-                                                                      slot1, xb, nullptr, s_gd[wv], xa, wv, lane);
+    for (int nt = 0; nt < NTL; ++nt) sigma[nt] = softplus_b(hacc[nt][0]);
+    dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBD, S::KBH, false>(
+        st, S::block_base(S::D), bias + S::bias_base(S::D) + h * 16, false, false, first_group<S, MPC>(S::D + 1),
+        xa, nullptr, s_gd[wv], xb);
+    dense_b<S, NTL, WAVES, MPC, S::MTD, S::KBH, S::KBD, S::KBH, false>(
+        st, S::block_base(S::D + 1), bias + S::bias_base(S::D + 1) + h * 16, true, true,
+        NextGroup{S::RGB_BLOCK, S::RGB_KB}, xb, nullptr, s_gd[wv], xa);
+    head_b<NTL, WAVES, S::RGB_KB, 0>(st, bias + S::RGB_BIAS + h * 16, NextGroup{0, 0}, xa, nullptr, hacc);
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float z = dot_b<S::KBG>(hr + (c * 2 + h) * S::KBG * 8, xa[nt]);
-        z += __shfl_xor(z, 32, 64);
-        rgb[nt][c] = sigmoid_b(z + hr[48 * S::KBG + c]);
-      }
+      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][c]);
   }
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt)
-    if (valid[nt] && h == 0) a.out[sidx[nt]] = make_float4(sigma[nt], rgb[nt][0], rgb[nt][1], rgb[nt][2]);
+    if (valid[nt] && h == 0)
+      (seg2[nt] ? a.out2 : a.out)[sidx[nt]] = make_float4(sigma[nt], rgb[nt][0], rgb[nt][1], rgb[nt][2]);
 }
 
 template <class S, int NTL, int WAVES, int MPC>
 hipError_t launch_mlp_bf16_t(const MlpArgs& a, hipStream_t st) {
   using C = BCfg<S, NTL, WAVES, MPC>;
-  const long blocks = (a.n_samples + C::SAMPLES - 1) / C::SAMPLES;
+  const long blocks = (a.n_samples + a.n_samples2 + C::SAMPLES - 1) / C::SAMPLES;
   hipLaunchKernelGGL((k_mlp_bf16<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(C::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
 // Tiling (measured on MI355X, 8x256 map): one 32-sample column tile per wave
-// and 8 waves per workgroup keep two waves on every SIMD (225 VGPRs), so one
-// wave's epilogue, LDS latency and barrier waits overlap the other's MFMAs;
-// streaming two m-tiles per chunk group halves the barriers.  1155 TFLOP/s,
-// against 922 for two column tiles per wave at one wave per SIMD.
+// and 8 waves per workgroup keep two waves on every SIMD, so one wave's
+// epilogue, LDS latency and barrier waits overlap the other's MFMAs;
+// streaming two m-tiles per chunk group halves the barriers.  Two column
+// tiles per wave (one wave per SIMD) and 4-wave workgroups were slower.
 #ifndef FL_BF16_NTL
 #define FL_BF16_NTL 1
 #endif
@@ -195,7 +284,7 @@ hipError_t launch_mlp_bf16_t(const MlpArgs& a, hipStream_t st) {
 #endif
 
 hipError_t launch_mlp_bf16(int map_kind, const MlpArgs& a, hipStream_t st) {
-  if (a.n_samples <= 0) return hipSuccess;
+  if (a.n_samples + a.n_samples2 <= 0) return hipSuccess;
   if (map_kind == kMapSmall) return launch_mlp_bf16_t<SmallMapB, FL_BF16_NTL, FL_BF16_WAVES, 1>(a, st);
   return launch_mlp_bf16_t<NerfMapB, FL_BF16_NTL, FL_BF16_WAVES, FL_BF16_MPC>(a, st);
 }

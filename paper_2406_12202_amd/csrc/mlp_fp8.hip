@@ -179,8 +179,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
 
   const long tile = (long)blockIdx.x * WAVES + wv;
   long sidx[NTL];
-  bool valid[NTL];
-  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid);
+  bool valid[NTL], seg2[NTL];
+  stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid, seg2);
 
   const float* bias = reinterpret_cast<const float*>(s_bias);
   const float* heads = reinterpret_cast<const float*>(s_heads);
@@ -227,14 +227,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
       z += __shfl_xor(z, 32, 64);
       rgb[c] = sigmoid_f(z + heads[S::RGB_OFF + 3 * S::DW + c]);
     }
-    if (valid[nt] && h == 0) a.out[sidx[nt]] = make_float4(sigma, rgb[0], rgb[1], rgb[2]);
+    if (valid[nt] && h == 0) (seg2[nt] ? a.out2 : a.out)[sidx[nt]] = make_float4(sigma, rgb[0], rgb[1], rgb[2]);
   }
 }
 
 template <class S, int NTL, int WAVES, int MPC>
 hipError_t launch_mlp_fp8_t(const MlpArgs& a, hipStream_t st) {
   constexpr int SAMPLES = 32 * NTL * WAVES;
-  const long blocks = (a.n_samples + SAMPLES - 1) / SAMPLES;
+  const long blocks = (a.n_samples + a.n_samples2 + SAMPLES - 1) / SAMPLES;
   hipLaunchKernelGGL((k_mlp_fp8<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, st, a);
   return hipGetLastError();
 }
@@ -250,7 +250,7 @@ hipError_t launch_mlp_fp8_t(const MlpArgs& a, hipStream_t st) {
 #endif
 
 hipError_t launch_mlp_fp8(int map_kind, const MlpArgs& a, hipStream_t st) {
-  if (a.n_samples <= 0) return hipSuccess;
+  if (a.n_samples + a.n_samples2 <= 0) return hipSuccess;
   if (map_kind != kMapNerf) return hipErrorInvalidValue;
   return launch_mlp_fp8_t<NerfMapF8, FL_FP8_NTL, FL_FP8_WAVES, FL_FP8_MPC>(a, st);
 }

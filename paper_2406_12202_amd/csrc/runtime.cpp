@@ -24,12 +24,12 @@ namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
                 K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
-                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_COUNT };
+                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
                                      "pose_estimate", "fp8_calibration", "level_key", "level_predict",
-                                     "level_rays", "level_scores", "level_finish"};
+                                     "level_rays", "level_scores", "level_finish", "mlp_coarse_fine"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -328,17 +328,20 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
         for (int v = 0; v < 16; ++v)
           P.bias[S::bias_base(l) + (mt * 2 + h) * 16 + v] = cn.b[ci][32 * mt + 8 * (v / 4) + 4 * h + v % 4];
   }
-  if constexpr (S::HEAD_KB > 0) {
-    // head tile: row 0 density (trunk output), rows 1..3 colour (trunk output, gamma(d))
-    const int ci = (int)cn.W.size() - 1;
-    for (int kb = 0; kb < S::HEAD_KB; ++kb)
+  {
+    // tail tiles (maplayout_bf16.h): row r of a tile, lane half h, slot q
+    const int ci = (int)cn.W.size() - 1;   // colour head
+    auto put = [&](long blk0, int kb, int lane, int q, float v) {
+      P.blocks[(size_t)((blk0 + kb) * 64 + lane) * 8 + q] = to_bf16(v);
+    };
+    for (int kb = 0; kb < S::SIG_KB; ++kb)
       for (int lane = 0; lane < 64; ++lane)
         for (int q = 0; q < 8; ++q) {
           const int row = lane % 32, h = lane / 32;
           float v = 0.0f;
           if (row == 0 && kb < S::KBH) {
             v = cn.W[S::D][chain_feature_b(kb, h, q)];
-          } else if (row >= 1 && row <= 3) {
+          } else if (S::DW == 0 && row >= 1 && row <= 3) {
             const int c = row - 1, nin = cn.nin[ci];
             int col;
             if (kb < S::KBH) col = chain_feature_b(kb, h, q);
@@ -348,12 +351,23 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
             }
             v = col >= 0 ? cn.W[ci][c * nin + col] : 0.0f;
           }
-          P.blocks[(size_t)((S::HEAD_BLOCK + kb) * 64 + lane) * 8 + q] = to_bf16(v);
+          put(S::SIG_BLOCK, kb, lane, q, v);
+        }
+    for (int kb = 0; kb < S::RGB_KB; ++kb)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int q = 0; q < 8; ++q) {
+          const int row = lane % 32, h = lane / 32;
+          const float v = row < 3 ? cn.W[ci][row * S::DW + chain_feature_b(kb, h, q)] : 0.0f;
+          put(S::RGB_BLOCK, kb, lane, q, v);
         }
     for (int h = 0; h < 2; ++h)
       for (int v = 0; v < 16; ++v) {
         const int row = 8 * (v / 4) + 4 * h + v % 4;
-        P.bias[S::HEAD_BIAS + h * 16 + v] = row == 0 ? cn.b[S::D][0] : (row <= 3 ? cn.b[ci][row - 1] : 0.0f);
+        float bs = 0.0f;
+        if (row == 0) bs = cn.b[S::D][0];
+        else if (S::DW == 0 && row <= 3) bs = cn.b[ci][row - 1];
+        P.bias[S::SIG_BIAS + h * 16 + v] = bs;
+        if (S::RGB_KB > 0) P.bias[S::RGB_BIAS + h * 16 + v] = row < 3 ? cn.b[ci][row] : 0.0f;
       }
   }
   float* sig = P.heads.data() + S::SIG_OFF;
@@ -382,6 +396,7 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
 }
 
 hipError_t mlp_launch(loc_ctx* c, const MlpArgs& a) {
+  if (a.n_samples2 > 0 && c->desc.precision == LOC_FP32) return hipErrorInvalidValue;   // one set per FP32 launch
   if (c->desc.precision == LOC_FP8_E4M3) {
     MlpArgs b = a;
     b.wblocks = c->wunits;
@@ -697,8 +712,11 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   ma.seed = seed;
   ma.iter = iter;
   const double fl_sample = 2.0 * (double)c->macs;
-  if ((s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
-                 [&] { return mlp_launch(c, ma); })))
+  // with proposal-placed fine samples (which do not depend on the coarse
+  // render) the MFMA paths evaluate coarse and fine samples in one launch
+  const bool merged = Sf > 0 && c->fine_mode == 1 && d.precision != LOC_FP32;
+  if (!merged && (s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
+                            [&] { return mlp_launch(c, ma); })))
     return s;
 
   if (Sf > 0 && c->fine_mode == 1) {
@@ -736,15 +754,27 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
     if (c->fine_mode == 0 &&
         (s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); })))
       return s;
-    MlpArgs mf = ma;
-    mf.t_in = c->t_f.p;
-    mf.t_out = nullptr;
-    mf.out = c->out_f.p;
-    mf.n_samples = nr * Sf;
-    mf.spr = Sf;
-    if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
-                   [&] { return mlp_launch(c, mf); })))
-      return s;
+    if (merged) {
+      MlpArgs mb = ma;
+      mb.t_in2 = c->t_f.p;
+      mb.out2 = c->out_f.p;
+      mb.n_samples2 = nr * Sf;
+      mb.spr2 = Sf;
+      const double n_all = (double)(ma.n_samples + mb.n_samples2);
+      if ((s = timed(c, K_MLP_BOTH, fl_sample * n_all, 20.0 * n_all + 4.0 * mb.n_samples2 + 32.0 * nr,
+                     [&] { return mlp_launch(c, mb); })))
+        return s;
+    } else {
+      MlpArgs mf = ma;
+      mf.t_in = c->t_f.p;
+      mf.t_out = nullptr;
+      mf.out = c->out_f.p;
+      mf.n_samples = nr * Sf;
+      mf.spr = Sf;
+      if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
+                     [&] { return mlp_launch(c, mf); })))
+        return s;
+    }
   }
 
   CompositeArgs ca{};

@@ -108,3 +108,19 @@ def test_bf16_deterministic(torch_dev):
     b = run_gpu(c, img, cam, 1, 16, poses, seed=4, it=4)
     for k in ("loglik", "weight", "C", "F"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_bf16_proposal_one_launch_for_coarse_and_fine(torch_dev):
+    """With proposal-placed fine samples the BF16 path evaluates coarse and
+    fine samples in one MFMA launch; ragged ray count so that the two sample
+    sets meet inside a workgroup."""
+    from paper_2406_12202_amd import synth
+    s, p, cam, poses, img = inputs("nerf", 27, N=5, n_fine=32)
+    theta = synth.proposal_params(27)
+    c = ctx(s, p, "bf16")
+    c.loc_set_proposal(theta)
+    c.loc_set_fine_mode(1)
+    kw = dict(seed=3, it=2)
+    g = run_gpu(c, img, cam, 1, 37, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 37, poses, proposal=theta, **kw)
+    _check(g, o)
