@@ -318,3 +318,51 @@ def update_levels(spec, params, image, cam, levels, poses, motion=None, sigma_t=
         est = se3.pose_estimate(o["pose"], w)
         X = o["pose"][idx]
     return dict(levels=recs, pose=X, estimate=est)
+
+
+# ----------------------------------------------------------------------------
+# localisation loop with variance-triggered refinement (Sec. III-C)
+
+def position_variance(poses, weight):
+    """Spread of the particle set: sum_i w_i |t_i - t_bar|^2 / sum_i w_i with
+    t_bar the weighted mean position (the trace of the weighted covariance of
+    the 3D positions; w <= 0 or non-finite counts as 0).  NaN if no weight."""
+    P = np.asarray(poses, dtype=np.float64).reshape(-1, 3, 4)
+    w = np.asarray(weight, dtype=np.float64)
+    w = np.where(np.isfinite(w) & (w > 0.0), w, 0.0)
+    W = w.sum()
+    if not W > 0.0:
+        return math.nan
+    t = P[:, :, 3]
+    tbar = (w[:, None] * t).sum(0) / W
+    return float((w * ((t - tbar) ** 2).sum(1)).sum() / W)
+
+
+def localize(spec, params, image, cam, stages, n_iters, poses, motion=None, sigma_t=0.0, sigma_r=0.0,
+             seed=0, proposal=None):
+    """The localisation loop: stages = [(inv_R, B, N, delta), ...].  At every
+    iteration t (counter t) the particle set is updated at the current stage's
+    scale and ray count (update_particles), the pose is read out and the
+    position variance of the weighted set measured; when the variance falls
+    below the stage's delta the next stage begins (the last stage's delta is
+    never used); then N particles of the (possibly new) stage are drawn
+    (counter t).  Returns per-iteration records and the final set."""
+    X = np.asarray(poses, dtype=np.float64).reshape(-1, 3, 4)
+    s = 0
+    recs = []
+    for t in range(n_iters):
+        inv_R, B, N, delta = stages[s]
+        o = update_particles(spec, params, image, cam, inv_R, B, X, motion, sigma_t, sigma_r, seed, t,
+                             proposal=proposal)
+        var = position_variance(o["pose"], o["weight"])
+        est = se3.pose_estimate(o["pose"], o["weight"]) if np.any(o["weight"] > 0) else None
+        rec = dict(iter=t, stage=s, var=var, est=est, loglik=o["loglik"], weight=o["weight"])
+        if s + 1 < len(stages) and var < delta:
+            s += 1
+        idx = resample(o["weight"], stages[s][2], seed, t)
+        rec["index"] = idx
+        recs.append(rec)
+        if idx is None:
+            return dict(steps=recs, pose=None)
+        X = o["pose"][idx]
+    return dict(steps=recs, pose=X)

@@ -588,3 +588,47 @@ def test_levels_rejected_particles_are_never_drawn():
     assert r["pose"].shape == (4, 3, 4)
     # level 1 starts from level 0's resampled set
     assert len(r["levels"][1]["out"]["index"]) == 9
+
+
+def test_position_variance_closed_form():
+    # two particles at +-a along x with equal weight: variance a^2
+    P = np.zeros((2, 3, 4))
+    P[:, :, :3] = np.eye(3)
+    P[0, 0, 3], P[1, 0, 3] = 0.3, -0.3
+    assert abs(mcl.position_variance(P, [1.0, 1.0]) - 0.09) < 1e-15
+    # weights 1:3 at x = 0 and x = 4: mean 3, variance (1*9 + 3*1)/4 = 3
+    P[0, 0, 3], P[1, 0, 3] = 0.0, 4.0
+    assert abs(mcl.position_variance(P, [1.0, 3.0]) - 3.0) < 1e-14
+    # trace over axes, invariance to a common shift, ignored bad weights
+    rng = np.random.default_rng(2)
+    Q = np.zeros((50, 3, 4))
+    Q[:, :, 3] = rng.normal(size=(50, 3)) * [1.0, 2.0, 3.0]
+    w = rng.random(50)
+    v = mcl.position_variance(Q, w)
+    Q2 = Q.copy()
+    Q2[:, :, 3] += [5.0, -7.0, 11.0]
+    assert abs(mcl.position_variance(Q2, w) - v) < 1e-10
+    wb = np.concatenate([w, [np.nan, -1.0]])
+    Qb = np.concatenate([Q, Q[:2]])
+    assert abs(mcl.position_variance(Qb, wb) - v) < 1e-15
+    assert np.isnan(mcl.position_variance(Q, np.zeros(50)))
+
+
+def test_localize_stage_switch_and_counts():
+    s = synth.spec("small")
+    p = synth.map_params(s, 8)
+    cam = synth.camera("small")
+    X = synth.particles("small", 8, N=20)
+    img = synth.observation("small", 8)
+    # a huge first threshold switches after iteration 0; a tiny one never
+    stages = [(2, 4, 20, 1e9), (1, 8, 10, 0.0)]
+    r = mcl.localize(s, p, img, cam, stages, 3, X, seed=1)
+    assert [st["stage"] for st in r["steps"]] == [0, 1, 1]
+    assert [len(st["index"]) for st in r["steps"]] == [10, 10, 10]
+    assert r["pose"].shape == (10, 3, 4)
+    r2 = mcl.localize(s, p, img, cam, [(2, 4, 20, 0.0), (1, 8, 10, 0.0)], 2, X, seed=1)
+    assert [st["stage"] for st in r2["steps"]] == [0, 0]
+    # the first iteration equals one update at the first stage
+    o = mcl.update_particles(s, p, img, cam, 2, 4, X, seed=1, it=0)
+    assert np.array_equal(r["steps"][0]["weight"], o["weight"])
+    assert r["steps"][0]["var"] == mcl.position_variance(o["pose"], o["weight"])
