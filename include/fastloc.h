@@ -267,6 +267,80 @@ loc_status loc_gather_poses(loc_ctx* ctx, const double* pose_in, int n_in, const
  * LOC_FLAG_SINGULAR_ROTATION. */
 loc_status loc_pose_estimate(loc_ctx* ctx, const double* pose, const double* weight, int N, double* est);
 
+/* Spread of a weighted particle set, the quantity whose fall below a
+ * threshold triggers the next refinement stage (Sec. III-C): var (DEVICE 1
+ * float64) = sum_i w_i |t_i - t_bar|^2 / sum_i w_i, t_bar the weighted mean
+ * position (the trace of the weighted covariance of the 3D positions; the
+ * paper names the variance of the positions without fixing the estimator).
+ * pose DEVICE N x 12 float64, weight DEVICE N float64 (w <= 0 or non-finite
+ * counts as 0).  NaN if no particle has weight.  N in [1, 2^24]. */
+loc_status loc_position_variance(loc_ctx* ctx, const double* pose, const double* weight, int N, double* var);
+
+/* Render the map from one pose at every pixel of the level-1/inv_R image
+ * (Eq. 1 with the context's samples: stratified coarse plus hierarchical or
+ * proposal-placed fine, as the update's rays; pixel centres and intrinsics as
+ * loc_update_particles; sample streams keyed (particle 0, ray p) with p the
+ * row-major pixel index).  pose DEVICE 12 float64; rgb DEVICE (H/inv_R) x
+ * (W/inv_R) x 3 float32 (C, row-major); opacity DEVICE (H/inv_R) x (W/inv_R)
+ * float32 (1 - T(far)) or NULL.  At most 2^22 pixels.  Enqueued. */
+loc_status loc_render_image(loc_ctx* ctx, const loc_camera* cam, int inv_R, const double* pose, uint64_t seed,
+                            uint64_t iter, float* rgb, float* opacity);
+
+/* ------------------------------------------------------------ localisation
+ * The localisation loop with variance-triggered refinement (Sec. III-C): the
+ * set moves through stages of growing resolution and rays per particle and
+ * shrinking particle counts; stage k weights the set at scale 1/inv_R with B
+ * rays per particle and the set drawn while in stage k has N particles.  At
+ * iteration t (counter iter + t): the set is predicted and weighted
+ * (loc_update_particles at the current stage), its position variance
+ * (loc_position_variance) and pose read-out (loc_pose_estimate) are taken;
+ * if the variance is below the current stage's delta the next stage begins
+ * (the last stage's delta is not used; NaN never switches); then the new
+ * current stage's N particles are drawn (loc_resample, counter iter + t) and
+ * gathered.  One stream synchronisation per iteration (the variance decides
+ * the next launch sizes on the host). */
+typedef struct {
+  int inv_R;      /* level scale 1/inv_R, inv_R in {1, 2, 4, 8} */
+  int B;          /* rays per particle, [1, 1024] */
+  int N;          /* particles drawn while in this stage, [1, 2^24] */
+  double delta;   /* variance threshold that ends the stage */
+} loc_stage;
+
+typedef struct {
+  long long iter; /* counter of the iteration */
+  int stage;      /* stage that weighted the set */
+  int n;          /* particles weighted */
+  int n_next;     /* particles drawn (0: the set had no weight, the loop ended) */
+  double var;     /* position variance of the weighted set */
+  double est[12]; /* pose read-out of the weighted set */
+  double ms;      /* host wall time of the iteration, milliseconds */
+} loc_step_info;
+
+/* Optional per-iteration record of the loop in DEVICE buffers, appended
+ * iteration by iteration: pose (12 x capacity float64) the predicted poses
+ * and weight (capacity float64) the normalised weights of the n particles
+ * weighted, idx (capacity int32) the n_next drawn indices.  The loop fails
+ * with LOC_E_ARG once capacity particles would be exceeded. */
+typedef struct {
+  double* pose;
+  double* weight;
+  int32_t* idx;
+  long capacity;
+} loc_trace;
+
+/* image DEVICE H x W x 3 float32; stages HOST n_stages (1..8); pose_in
+ * DEVICE n_in x 12 float64, the initial set (n_in in [1, 2^24]); motion,
+ * sigma_t, sigma_r, seed as loc_update_particles; pose_out DEVICE (max N over
+ * the stages) x 12 float64 receives the final set and *n_out its size (0 if
+ * the loop ended on a set without weight); info HOST n_iters records or NULL;
+ * *n_done (may be NULL) the iterations run; trace NULL or as above.
+ * Synchronous. */
+loc_status loc_localize(loc_ctx* ctx, const float* image, const loc_camera* cam, int n_stages,
+                        const loc_stage* stages, int n_iters, int n_in, const double* pose_in,
+                        const double* motion, double sigma_t, double sigma_r, uint64_t seed, uint64_t iter,
+                        double* pose_out, int* n_out, loc_step_info* info, int* n_done,
+                        const loc_trace* trace);
+
 /* Per-ray results of the last loc_update_particles on this context, copied
  * into DEVICE arrays of N*B entries (ray (i, j) at i*B + j); any pointer may be
  * NULL.  rgb: 3 floats per ray (C), opacity: A = 1 - T(far), F: uncertainty,

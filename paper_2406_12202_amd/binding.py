@@ -22,7 +22,8 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outp
            "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal",
            "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
            "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
-           "loc_autotune_levels", "loc_set_level_tiles"]
+           "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
+           "loc_localize"]
 PROPOSAL_PARAMS = 11296
 
 
@@ -52,6 +53,20 @@ class TrainCfg(ctypes.Structure):
 
 class Level(ctypes.Structure):
     _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("n_out", ctypes.c_int)]
+
+
+class Stage(ctypes.Structure):
+    _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("N", ctypes.c_int), ("delta", ctypes.c_double)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_longlong), ("stage", ctypes.c_int), ("n", ctypes.c_int), ("n_next", ctypes.c_int),
+                ("var", ctypes.c_double), ("est", ctypes.c_double * 12), ("ms", ctypes.c_double)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("pose", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("idx", ctypes.c_void_p),
+                ("capacity", ctypes.c_long)]
 
 
 class LocError(RuntimeError):
@@ -106,12 +121,18 @@ def load(path=LIB_PATH):
     lib.loc_autotune_levels.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Level), c_int, vp,
                                         c_int, ctypes.c_char_p, vp]
     lib.loc_set_level_tiles.argtypes = [vp, c_int, c_int, c_int, c_int]
+    lib.loc_position_variance.argtypes = [vp, vp, vp, c_int, vp]
+    lib.loc_render_image.argtypes = [vp, ctypes.POINTER(Camera), c_int, vp, c_u64, c_u64, vp, vp]
+    lib.loc_localize.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Stage), c_int, c_int, vp, vp,
+                                 c_dbl, c_dbl, c_u64, c_u64, vp, ctypes.POINTER(c_int), ctypes.POINTER(StepInfo),
+                                 ctypes.POINTER(c_int), ctypes.POINTER(Trace)]
     for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
               "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
               "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
               "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
               "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
-              "loc_autotune_levels", "loc_set_level_tiles"):
+              "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
+              "loc_localize"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -443,3 +464,73 @@ class Context:
     def loc_set_level_tiles(self, level, ntl, waves, blocks):
         self._check(self.lib.loc_set_level_tiles(self.h, int(level), int(ntl), int(waves), int(blocks)),
                     "loc_set_level_tiles")
+
+    # ------------------------------------------------------------ localisation
+
+    def loc_position_variance(self, pose, weight, var=None):
+        import torch
+        N = pose.shape[0]
+        if var is None:
+            var = torch.empty(1, dtype=torch.float64, device=pose.device)
+        self._check(self.lib.loc_position_variance(self.h, _ptr(pose, torch.float64, N * 12, "pose"),
+                                                   _ptr(weight, torch.float64, N, "weight"), int(N),
+                                                   _ptr(var, torch.float64, 1, "var")), "loc_position_variance")
+        return var
+
+    def loc_render_image(self, cam, inv_R, pose, seed=0, iter=0, opacity=False):
+        """Render the map from pose (device 3x4 float64) at every level pixel;
+        returns rgb (H/inv_R, W/inv_R, 3) and, if asked, the opacity."""
+        import torch
+        W, H = int(cam[0]) // int(inv_R), int(cam[1]) // int(inv_R)
+        dev = pose.device
+        rgb = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        op = torch.empty((H, W), dtype=torch.float32, device=dev) if opacity else None
+        c = self._cam(cam)
+        self._check(self.lib.loc_render_image(self.h, ctypes.byref(c), int(inv_R), _ptr(pose, torch.float64, 12, "pose"),
+                                              int(seed), int(iter), rgb.data_ptr(),
+                                              op.data_ptr() if op is not None else None), "loc_render_image")
+        return (rgb, op) if opacity else rgb
+
+    def loc_localize(self, image, cam, stages, n_iters, pose_in, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0,
+                     iter=0, trace_capacity=0):
+        """The localisation loop; stages = [(inv_R, B, N, delta), ...].  Returns
+        a dict: pose (final set, n_out x 3 x 4), steps (per-iteration records)
+        and, with trace_capacity > 0, the appended trace tensors."""
+        import numpy as np
+        import torch
+        W, H = int(cam[0]), int(cam[1])
+        n_in = pose_in.shape[0]
+        dev = pose_in.device
+        st = (Stage * len(stages))()
+        for k, (r, b, n, dl) in enumerate(stages):
+            st[k] = Stage(int(r), int(b), int(n), float(dl))
+        n_max = max(int(g[2]) for g in stages)
+        pose_out = torch.empty((max(n_max, 1), 3, 4), dtype=torch.float64, device=dev)
+        info = (StepInfo * int(n_iters))()
+        n_out, n_done = ctypes.c_int(0), ctypes.c_int(0)
+        tr = None
+        trace = None
+        if trace_capacity > 0:
+            trace = dict(pose=torch.empty((trace_capacity, 3, 4), dtype=torch.float64, device=dev),
+                         weight=torch.empty(trace_capacity, dtype=torch.float64, device=dev),
+                         idx=torch.empty(trace_capacity, dtype=torch.int32, device=dev))
+            tr = Trace(trace["pose"].data_ptr(), trace["weight"].data_ptr(), trace["idx"].data_ptr(),
+                       int(trace_capacity))
+        mo = None
+        if motion is not None:
+            self._mo = np.ascontiguousarray(np.asarray(motion, dtype=np.float64).reshape(12))
+            mo = ctypes.c_void_p(self._mo.ctypes.data)
+        c = self._cam(cam)
+        rc = self.lib.loc_localize(self.h, _ptr(image, torch.float32, H * W * 3, "image"), ctypes.byref(c), len(stages),
+                                   st, int(n_iters), int(n_in), _ptr(pose_in, torch.float64, n_in * 12, "pose_in"), mo,
+                                   float(sigma_t), float(sigma_r), int(seed), int(iter), pose_out.data_ptr(),
+                                   ctypes.byref(n_out), info, ctypes.byref(n_done),
+                                   ctypes.byref(tr) if tr is not None else None)
+        self._check(rc, "loc_localize")
+        steps = [dict(iter=int(r.iter), stage=int(r.stage), n=int(r.n), n_next=int(r.n_next), var=float(r.var),
+                      est=np.array(r.est[:], dtype=np.float64).reshape(3, 4), ms=float(r.ms))
+                 for r in info[:n_done.value]]
+        out = dict(pose=pose_out[:n_out.value] if n_out.value > 0 else None, steps=steps)
+        if trace is not None:
+            out["trace"] = trace
+        return out

@@ -69,4 +69,15 @@ hipError_t launch_pose_estimate(const double* pose, const double* w, int N, doub
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kEstThreads) void k_position_variance(const double* pose, const double* w, int N,
+                                                                   double* var) {
+  __shared__ double s[kEstThreads][4];
+  position_variance_block(pose, w, N, var, s);
+}
+
+hipError_t launch_position_variance(const double* pose, const double* w, int N, double* var, hipStream_t st) {
+  hipLaunchKernelGGL(k_position_variance, dim3(1), dim3(kEstThreads), 0, st, pose, w, N, var);
+  return hipGetLastError();
+}
+
 }  // namespace fl

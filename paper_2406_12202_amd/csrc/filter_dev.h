@@ -327,4 +327,52 @@ __device__ inline void pose_estimate_block(const double* pose, const double* w, 
   __syncthreads();
 }
 
+// spread of a weighted particle set: sum_i w_i |t_i - t_bar|^2 / sum_i w_i
+// (trace of the weighted covariance of the positions; w <= 0 or non-finite
+// counts as 0; NaN without weight); two fixed-order passes over kEstThreads
+// threads; s: kEstThreads x 4 doubles
+__device__ inline void position_variance_block(const double* pose, const double* w, int N, double* var,
+                                               double (*s)[4]) {
+  const int tid = threadIdx.x;
+  if (tid < kEstThreads) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = tid; i < N; i += kEstThreads) {
+      const double wi = (isfinite(w[i]) && w[i] > 0.0) ? w[i] : 0.0;
+      for (int r = 0; r < 3; ++r) acc[r] += wi * pose[(long)i * 12 + 4 * r + 3];
+      acc[3] += wi;
+    }
+    for (int q = 0; q < 4; ++q) s[tid][q] = acc[q];
+  }
+  __syncthreads();
+  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int q = 0; q < 4; ++q) s[tid][q] += s[tid + o][q];
+    __syncthreads();
+  }
+  const double W = s[0][3];
+  const double tb[3] = {s[0][0] / W, s[0][1] / W, s[0][2] / W};
+  __syncthreads();
+  if (tid < kEstThreads) {
+    double v = 0.0;
+    for (int i = tid; i < N; i += kEstThreads) {
+      const double wi = (isfinite(w[i]) && w[i] > 0.0) ? w[i] : 0.0;
+      double d2 = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        const double d = pose[(long)i * 12 + 4 * r + 3] - tb[r];
+        d2 += d * d;
+      }
+      v += wi * d2;
+    }
+    s[tid][0] = v;
+  }
+  __syncthreads();
+  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) s[tid][0] += s[tid + o][0];
+    __syncthreads();
+  }
+  if (tid == 0) *var = W > 0.0 ? s[0][0] / W : NAN;
+  __threadfence_block();
+  __syncthreads();
+}
+
 }  // namespace fl

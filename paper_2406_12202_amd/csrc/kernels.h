@@ -78,6 +78,7 @@ struct RaygenArgs {
   float4* ray_o;
   float4* ray_d;
   float4* obs;           // I^R(p_j) per ray (rgb, pad)
+  int all_pixels;        // 1: ray j goes through level pixel j (row-major) instead of a drawn pixel
 };
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st);
 
@@ -154,6 +155,7 @@ hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t s
 hipError_t launch_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out,
                                hipStream_t st);
 hipError_t launch_pose_estimate(const double* pose, const double* w, int N, double* est, int* flags, hipStream_t st);
+hipError_t launch_position_variance(const double* pose, const double* w, int N, double* var, hipStream_t st);
 
 hipError_t launch_split_ray_outputs(const float4* rgba, const float2* fe, int n, float* rgb,
                                     float* opacity, float* F, float* E, hipStream_t st);

@@ -14,9 +14,9 @@ __global__ __launch_bounds__(256) void k_raygen(const RaygenArgs a) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.N * a.B) return;
   const int i = r / a.B, j = r - (r / a.B) * a.B;
-  const uint32_t w = draw(a.seed, a.iter, kStreamPix, (uint32_t)j, 0, 0).x;
   const uint64_t npix = (uint64_t)a.Wl * (uint64_t)a.Hl;
-  const uint64_t p = ((uint64_t)w * npix) >> 32;
+  const uint64_t p = a.all_pixels ? (uint64_t)j
+                                  : (((uint64_t)draw(a.seed, a.iter, kStreamPix, (uint32_t)j, 0, 0).x * npix) >> 32);
   const int u = (int)(p % (uint64_t)a.Wl), v = (int)(p / (uint64_t)a.Wl);
   float o[3], d[3];
   camera_ray(a.pose + (long)i * 12, u, v, a.fx, a.fy, a.cx, a.cy, o, d);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -24,12 +25,13 @@ namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
                 K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
-                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_COUNT };
+                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_VARIANCE, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
                                      "pose_estimate", "fp8_calibration", "level_key", "level_predict",
-                                     "level_rays", "level_scores", "level_finish", "mlp_coarse_fine"};
+                                     "level_rays", "level_scores", "level_finish", "mlp_coarse_fine",
+                                     "position_variance"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -92,6 +94,11 @@ struct loc_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<double> graph_sig;
+  // localisation loop: particle sets (ping-pong), predicted set, scores,
+  // drawn indices, device and pinned host copies of (var, est)
+  DevBuf<double> lz_x[2], lz_pred, lz_ll, lz_w, lz_ve;
+  DevBuf<int32_t> lz_idx;
+  double* lz_host = nullptr;
   int* flags = nullptr;
   int last_N = 0, last_B = 0;
   // profiling
@@ -520,6 +527,105 @@ bool same_shape(const loc_map_desc& d, int W, int D, int skip, int lx, int ld, i
 
 }  // namespace
 
+namespace {
+
+// Samples of nr rays (ray r = particle r / B, pixel r % B; rays in
+// c->ray_o / c->ray_d): stratified coarse samples, fine placement
+// (hierarchical or proposal) and the map at every sample, into c->t_c / c->out_c
+// and c->t_f / c->out_f.
+loc_status map_samples(loc_ctx* c, long nr, int B, uint64_t seed, uint64_t iter) {
+  const loc_map_desc& d = c->desc;
+  const int Sc = d.n_coarse, Sf = d.n_fine;
+  loc_status s;
+  MlpArgs ma{};
+  ma.ray_o = c->ray_o.p;
+  ma.ray_d = c->ray_d.p;
+  ma.t_in = nullptr;
+  ma.t_out = c->t_c.p;
+  ma.out = c->out_c.p;
+  ma.weights = c->weights;
+  ma.wblocks = c->wblocks;
+  ma.bias = c->bias_b;
+  ma.heads = c->heads_b;
+  ma.n_samples = nr * Sc;
+  ma.spr = Sc;
+  ma.B = B;
+  ma.near_ = d.near_;
+  ma.dt = (d.far_ - d.near_) / (float)Sc;
+  ma.jitter = d.jitter;
+  ma.seed = seed;
+  ma.iter = iter;
+  const double fl_sample = 2.0 * (double)c->macs;
+  // with proposal-placed fine samples (which do not depend on the coarse
+  // render) the MFMA paths evaluate coarse and fine samples in one launch
+  const bool merged = Sf > 0 && c->fine_mode == 1 && d.precision != LOC_FP32;
+  if (!merged && (s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
+                            [&] { return mlp_launch(c, ma); })))
+    return s;
+
+  if (Sf > 0 && c->fine_mode == 1) {
+    ProposalArgs pa2{};
+    pa2.ray_o = c->ray_o.p;
+    pa2.ray_d = c->ray_d.p;
+    pa2.params = c->prop;
+    pa2.hist = nullptr;
+    pa2.t_fine = c->t_f.p;
+    pa2.n_rays = (int)nr;
+    pa2.Sf = Sf;
+    pa2.B = B;
+    pa2.near_ = d.near_;
+    pa2.far_ = d.far_;
+    pa2.jitter = d.jitter;
+    pa2.seed = seed;
+    pa2.iter = iter;
+    if ((s = timed(c, K_PROPOSAL, 2.0 * 11136.0 * nr, 40.0 * nr + 4.0 * nr * Sf,
+                   [&] { return launch_proposal_fine(pa2, c->stream); })))
+      return s;
+  }
+  if (Sf > 0) {
+    FineArgs fa{};
+    fa.t_coarse = c->t_c.p;
+    fa.out_coarse = c->out_c.p;
+    fa.t_fine = c->t_f.p;
+    fa.n_rays = (int)nr;
+    fa.Sc = Sc;
+    fa.Sf = Sf;
+    fa.B = B;
+    fa.far_ = d.far_;
+    fa.jitter = d.jitter;
+    fa.seed = seed;
+    fa.iter = iter;
+    if (c->fine_mode == 0 &&
+        (s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); })))
+      return s;
+    if (merged) {
+      MlpArgs mb = ma;
+      mb.t_in2 = c->t_f.p;
+      mb.out2 = c->out_f.p;
+      mb.n_samples2 = nr * Sf;
+      mb.spr2 = Sf;
+      const double n_all = (double)(ma.n_samples + mb.n_samples2);
+      if ((s = timed(c, K_MLP_BOTH, fl_sample * n_all, 20.0 * n_all + 4.0 * mb.n_samples2 + 32.0 * nr,
+                     [&] { return mlp_launch(c, mb); })))
+        return s;
+    } else {
+      MlpArgs mf = ma;
+      mf.t_in = c->t_f.p;
+      mf.t_out = nullptr;
+      mf.out = c->out_f.p;
+      mf.n_samples = nr * Sf;
+      mf.spr = Sf;
+      if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
+                     [&] { return mlp_launch(c, mf); })))
+        return s;
+    }
+  }
+
+  return LOC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* loc_status_str(loc_status s) {
@@ -614,6 +720,9 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
   hipFree(c->prop); hipFree(c->prop_m); hipFree(c->prop_v); hipFree(c->prop_partial.p); hipFree(c->prop_loss.p);
   hipFree(c->tr_o.p); hipFree(c->tr_d.p);
+  for (auto& b : c->lz_x) hipFree(b.p);
+  hipFree(c->lz_pred.p); hipFree(c->lz_ll.p); hipFree(c->lz_w.p); hipFree(c->lz_ve.p); hipFree(c->lz_idx.p);
+  if (c->lz_host) hipHostFree(c->lz_host);
   for (auto& L : c->lv) {
     hipFree(L.pose.p); hipFree(L.loglik.p); hipFree(L.weight.p); hipFree(L.uncert.p); hipFree(L.idx.p);
     hipFree(L.rgba.p); hipFree(L.fe.p);
@@ -693,89 +802,7 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
                  [&] { return launch_raygen(ra, c->stream); })))
     return s;
 
-  MlpArgs ma{};
-  ma.ray_o = c->ray_o.p;
-  ma.ray_d = c->ray_d.p;
-  ma.t_in = nullptr;
-  ma.t_out = c->t_c.p;
-  ma.out = c->out_c.p;
-  ma.weights = c->weights;
-  ma.wblocks = c->wblocks;
-  ma.bias = c->bias_b;
-  ma.heads = c->heads_b;
-  ma.n_samples = nr * Sc;
-  ma.spr = Sc;
-  ma.B = B;
-  ma.near_ = d.near_;
-  ma.dt = (d.far_ - d.near_) / (float)Sc;
-  ma.jitter = d.jitter;
-  ma.seed = seed;
-  ma.iter = iter;
-  const double fl_sample = 2.0 * (double)c->macs;
-  // with proposal-placed fine samples (which do not depend on the coarse
-  // render) the MFMA paths evaluate coarse and fine samples in one launch
-  const bool merged = Sf > 0 && c->fine_mode == 1 && d.precision != LOC_FP32;
-  if (!merged && (s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
-                            [&] { return mlp_launch(c, ma); })))
-    return s;
-
-  if (Sf > 0 && c->fine_mode == 1) {
-    ProposalArgs pa2{};
-    pa2.ray_o = c->ray_o.p;
-    pa2.ray_d = c->ray_d.p;
-    pa2.params = c->prop;
-    pa2.hist = nullptr;
-    pa2.t_fine = c->t_f.p;
-    pa2.n_rays = (int)nr;
-    pa2.Sf = Sf;
-    pa2.B = B;
-    pa2.near_ = d.near_;
-    pa2.far_ = d.far_;
-    pa2.jitter = d.jitter;
-    pa2.seed = seed;
-    pa2.iter = iter;
-    if ((s = timed(c, K_PROPOSAL, 2.0 * 11136.0 * nr, 40.0 * nr + 4.0 * nr * Sf,
-                   [&] { return launch_proposal_fine(pa2, c->stream); })))
-      return s;
-  }
-  if (Sf > 0) {
-    FineArgs fa{};
-    fa.t_coarse = c->t_c.p;
-    fa.out_coarse = c->out_c.p;
-    fa.t_fine = c->t_f.p;
-    fa.n_rays = (int)nr;
-    fa.Sc = Sc;
-    fa.Sf = Sf;
-    fa.B = B;
-    fa.far_ = d.far_;
-    fa.jitter = d.jitter;
-    fa.seed = seed;
-    fa.iter = iter;
-    if (c->fine_mode == 0 &&
-        (s = timed(c, K_FINE, 0, nr * (8.0 * Sc + 4.0 * Sf), [&] { return launch_fine(fa, c->stream); })))
-      return s;
-    if (merged) {
-      MlpArgs mb = ma;
-      mb.t_in2 = c->t_f.p;
-      mb.out2 = c->out_f.p;
-      mb.n_samples2 = nr * Sf;
-      mb.spr2 = Sf;
-      const double n_all = (double)(ma.n_samples + mb.n_samples2);
-      if ((s = timed(c, K_MLP_BOTH, fl_sample * n_all, 20.0 * n_all + 4.0 * mb.n_samples2 + 32.0 * nr,
-                     [&] { return mlp_launch(c, mb); })))
-        return s;
-    } else {
-      MlpArgs mf = ma;
-      mf.t_in = c->t_f.p;
-      mf.t_out = nullptr;
-      mf.out = c->out_f.p;
-      mf.n_samples = nr * Sf;
-      mf.spr = Sf;
-      if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
-                     [&] { return mlp_launch(c, mf); })))
-        return s;
-    }
-  }
+  if ((s = map_samples(c, nr, B, seed, iter))) return s;
 
   CompositeArgs ca{};
   ca.t_coarse = c->t_c.p;
@@ -1657,6 +1684,183 @@ loc_status loc_set_level_tiles(loc_ctx* c, int level, int ntl, int waves, int bl
   c->lv[level].ntl = ntl;
   c->lv[level].waves = waves;
   c->lv[level].blocks = blocks;
+  return LOC_OK;
+}
+
+
+loc_status loc_position_variance(loc_ctx* c, const double* pose, const double* weight, int N, double* var) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!pose || !weight || !var) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (N < 1 || N > (1 << 24)) return fail(c, LOC_E_ARG, "N must be in [1, 2^24]");
+  return timed(c, K_VARIANCE, 0, 2.0 * 32.0 * N, [&] { return launch_position_variance(pose, weight, N, var, c->stream); });
+}
+
+loc_status loc_render_image(loc_ctx* c, const loc_camera* cam, int inv_R, const double* pose, uint64_t seed,
+                            uint64_t iter, float* rgb, float* opacity) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!cam || !pose || !rgb) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (inv_R != 1 && inv_R != 2 && inv_R != 4 && inv_R != 8) return fail(c, LOC_E_ARG, "inv_R must be 1, 2, 4 or 8");
+  if (cam->W <= 0 || cam->H <= 0 || cam->W % inv_R || cam->H % inv_R || !(cam->fx > 0 && cam->fy > 0) ||
+      !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(c, LOC_E_ARG, "invalid camera for level factor %d", inv_R);
+  if (c->fine_mode == 1 && !c->prop) return fail(c, LOC_E_STATE, "proposal mode without proposal parameters");
+  if (c->desc.precision == LOC_FP8_E4M3 && !c->f8_ready)
+    return fail(c, LOC_E_STATE, "FP8 map used before loc_calibrate_fp8");
+  const int Wl = cam->W / inv_R, Hl = cam->H / inv_R;
+  const long n = (long)Wl * Hl;
+  if (n > (1L << 30) / 256) return fail(c, LOC_E_ARG, "image of %ld pixels exceeds 2^22", n);
+  const loc_map_desc& d = c->desc;
+  const int Sc = d.n_coarse, Sf = d.n_fine;
+  loc_status s;
+  if ((s = ensure(c, c->ray_o, n)) || (s = ensure(c, c->ray_d, n)) || (s = ensure(c, c->rgba, n)) ||
+      (s = ensure(c, c->fe, n)) || (s = ensure(c, c->t_c, n * Sc)) || (s = ensure(c, c->out_c, n * Sc)))
+    return s;
+  if (Sf > 0 && ((s = ensure(c, c->t_f, n * Sf)) || (s = ensure(c, c->out_f, n * Sf)))) return s;
+  RaygenArgs ra{};
+  ra.pose = pose;
+  ra.image = nullptr;
+  ra.W_full = cam->W;
+  ra.s = inv_R;
+  ra.Wl = Wl;
+  ra.Hl = Hl;
+  ra.fx = cam->fx / inv_R;
+  ra.fy = cam->fy / inv_R;
+  ra.cx = cam->cx / inv_R;
+  ra.cy = cam->cy / inv_R;
+  ra.N = 1;
+  ra.B = (int)n;
+  ra.seed = seed;
+  ra.iter = iter;
+  ra.ray_o = c->ray_o.p;
+  ra.ray_d = c->ray_d.p;
+  ra.obs = nullptr;
+  ra.all_pixels = 1;
+  if ((s = timed(c, K_RAYGEN, 0, 32.0 * n + 96.0, [&] { return launch_raygen(ra, c->stream); }))) return s;
+  if ((s = map_samples(c, n, (int)n, seed, iter))) return s;
+  CompositeArgs ca{};
+  ca.t_coarse = c->t_c.p;
+  ca.out_coarse = c->out_c.p;
+  ca.t_fine = Sf > 0 ? c->t_f.p : nullptr;
+  ca.out_fine = Sf > 0 ? c->out_f.p : nullptr;
+  ca.obs = nullptr;
+  ca.N = (int)((n + 3) / 4);     // no scores: particle grouping is immaterial
+  ca.B = 4;
+  ca.Sc = Sc;
+  ca.Sf = Sf;
+  ca.far_ = d.far_;
+  ca.log_trans = (float)std::log1p(-(double)d.alpha);
+  ca.log_opq = (float)std::log((double)d.alpha);
+  ca.tau = d.tau;
+  ca.ray_rgba = c->rgba.p;
+  ca.ray_fe = c->fe.p;
+  ca.loglik = nullptr;
+  ca.uncert = nullptr;
+  ca.hist = nullptr;
+  ca.n_rays = (int)n;
+  ca.near_ = d.near_;
+  if ((s = timed(c, K_COMPOSITE, 0, n * (20.0 * (Sc + Sf) + 24.0), [&] { return launch_composite(ca, c->stream); })))
+    return s;
+  return timed(c, K_SPLIT, 0, 28.0 * n, [&] {
+    return launch_split_ray_outputs(c->rgba.p, c->fe.p, (int)n, rgb, opacity, nullptr, nullptr, c->stream);
+  });
+}
+
+loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, int n_stages, const loc_stage* stages,
+                        int n_iters, int n_in, const double* pose_in, const double* motion, double sigma_t,
+                        double sigma_r, uint64_t seed, uint64_t iter, double* pose_out, int* n_out,
+                        loc_step_info* info, int* n_done, const loc_trace* trace) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!image || !cam || !stages || !pose_in || !pose_out || !n_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n_stages < 1 || n_stages > 8) return fail(c, LOC_E_ARG, "n_stages must be in [1, 8]");
+  if (n_iters < 1) return fail(c, LOC_E_ARG, "n_iters must be >= 1");
+  int n_max = n_in;
+  for (int k = 0; k < n_stages; ++k) {
+    const loc_stage& g = stages[k];
+    if (g.inv_R != 1 && g.inv_R != 2 && g.inv_R != 4 && g.inv_R != 8)
+      return fail(c, LOC_E_ARG, "stage %d: inv_R must be 1, 2, 4 or 8", k);
+    if (g.B < 1 || g.B > 1024 || g.N < 1 || g.N > (1 << 24))
+      return fail(c, LOC_E_ARG, "stage %d: B or N out of range", k);
+    if (k + 1 < n_stages && std::isnan(g.delta)) return fail(c, LOC_E_ARG, "stage %d: delta is NaN", k);
+    n_max = std::max(n_max, g.N);
+  }
+  if (n_in < 1 || n_in > (1 << 24)) return fail(c, LOC_E_ARG, "n_in must be in [1, 2^24]");
+  if (trace && trace->capacity > 0 && (!trace->pose || !trace->weight || !trace->idx))
+    return fail(c, LOC_E_ARG, "trace buffers missing");
+  loc_status s;
+  if ((s = ensure(c, c->lz_x[0], 12L * n_max)) || (s = ensure(c, c->lz_x[1], 12L * n_max)) ||
+      (s = ensure(c, c->lz_pred, 12L * n_max)) || (s = ensure(c, c->lz_ll, n_max)) ||
+      (s = ensure(c, c->lz_w, n_max)) || (s = ensure(c, c->lz_ve, 13)) || (s = ensure(c, c->lz_idx, n_max)))
+    return s;
+  if (!c->lz_host && hipHostMalloc((void**)&c->lz_host, 13 * sizeof(double), 0) != hipSuccess) {
+    (void)hipGetLastError();
+    c->lz_host = nullptr;
+    return fail(c, LOC_E_OOM, "pinned host allocation failed");
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->lz_x[0].p, pose_in, 96L * n_in, hipMemcpyDeviceToDevice, c->stream));
+  int cur = 0, n = n_in, st = 0, done = 0;
+  bool lost = false;
+  long toff = 0, ioff = 0;
+  for (int t = 0; t < n_iters; ++t) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const loc_stage& g = stages[st];
+    const uint64_t it = iter + (uint64_t)t;
+    if ((s = loc_update_particles(c, image, cam, g.inv_R, g.B, n, c->lz_x[cur].p, motion, sigma_t, sigma_r, seed, it,
+                                  c->lz_pred.p, c->lz_ll.p, c->lz_w.p, nullptr)))
+      return s;
+    if ((s = loc_position_variance(c, c->lz_pred.p, c->lz_w.p, n, c->lz_ve.p)) ||
+        (s = loc_pose_estimate(c, c->lz_pred.p, c->lz_w.p, n, c->lz_ve.p + 1)))
+      return s;
+    HIP_TRY(c, hipMemcpyAsync(c->lz_host, c->lz_ve.p, 13 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double var = c->lz_host[0];
+    const int st_w = st;
+    if (st + 1 < n_stages && var < stages[st].delta) ++st;   // NaN never switches
+    const int n_next = std::isnan(var) ? 0 : stages[st].N;
+    if (n_next > 0) {
+      if ((s = loc_resample(c, c->lz_w.p, n, n_next, seed, it, c->lz_idx.p)) ||
+          (s = loc_gather_poses(c, c->lz_pred.p, n, c->lz_idx.p, n_next, c->lz_x[cur ^ 1].p)))
+        return s;
+    }
+    if (trace && trace->capacity > 0) {
+      if (toff + n > trace->capacity || ioff + n_next > trace->capacity)
+        return fail(c, LOC_E_ARG, "trace capacity %ld exceeded at iteration %d", trace->capacity, t);
+      HIP_TRY(c, hipMemcpyAsync(trace->pose + 12 * toff, c->lz_pred.p, 96L * n, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(trace->weight + toff, c->lz_w.p, 8L * n, hipMemcpyDeviceToDevice, c->stream));
+      if (n_next > 0)
+        HIP_TRY(c, hipMemcpyAsync(trace->idx + ioff, c->lz_idx.p, 4L * n_next, hipMemcpyDeviceToDevice, c->stream));
+      toff += n;
+      ioff += n_next;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (info) {
+      loc_step_info& r = info[t];
+      r.iter = (long long)it;
+      r.stage = st_w;
+      r.n = n;
+      r.n_next = n_next;
+      r.var = var;
+      for (int q = 0; q < 12; ++q) r.est[q] = c->lz_host[1 + q];
+      r.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    ++done;
+    if (n_next == 0) {
+      lost = true;
+      break;
+    }
+    cur ^= 1;
+    n = n_next;
+  }
+  if (n_done) *n_done = done;
+  if (lost) {
+    *n_out = 0;
+    return LOC_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(pose_out, c->lz_x[cur].p, 96L * n, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *n_out = n;
   return LOC_OK;
 }
 
