@@ -10,6 +10,9 @@ namespace fl {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -39,7 +42,8 @@ __device__ __forceinline__ void posenc_both(const float p0, const float p1, cons
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
+    for (int kb = 0; kb < KB; ++kb) {
+      f32x8 v;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int p = 8 * kb + 4 * hh + j;
@@ -52,9 +56,11 @@ __device__ __forceinline__ void posenc_both(const float p0, const float p1, cons
         } else if (p == 3 * L + 1) {
           a = p2;
         }
-        out[hh][kb][2 * j] = (__bf16)a;
-        out[hh][kb][2 * j + 1] = (__bf16)b;
+        v[2 * j] = a;
+        v[2 * j + 1] = b;
       }
+      out[hh][kb] = __builtin_convertvector(v, bf16x8);   // round to nearest even, two values per instruction
+    }
 }
 
 // the operands of lane half h
@@ -127,10 +133,21 @@ __device__ __forceinline__ void stage_samples(const MlpArgs& a, const long tile,
   }
 }
 
+// two float32 values rounded to bf16 (nearest even) as one packed word, one
+// conversion instruction; with relu, max with 0 on the packed int16 halves (a
+// non-negative bf16 is a non-negative int16, a negative one a negative int16)
+__device__ __forceinline__ uint32_t pack_bf16(const float a, const float b, const bool relu) {
+  const f32x2 f = {a, b};
+  s16x2 w = __builtin_bit_cast(s16x2, __builtin_convertvector(f, bf16x2));
+  if (relu) {
+    const s16x2 z = {0, 0};
+    w = __builtin_elementwise_max(w, z);
+  }
+  return __builtin_bit_cast(uint32_t, w);
+}
+
 // rounded bf16 operands of the next layer from one finished output tile; the
-// bias is already in the accumulators; ReLU acts on the packed bf16 pairs
-// (a non-negative bf16 is a non-negative int16, a negative one a negative
-// int16, so max with 0 as int16 is ReLU)
+// bias is already in the accumulators
 template <int NTL, int NY>
 __device__ __forceinline__ void epilogue_b(const f32x16 (&acc)[NTL], const bool relu, const int mt,
                                            bf16x8 (&y)[NTL][NY]) {
@@ -138,18 +155,12 @@ __device__ __forceinline__ void epilogue_b(const f32x16 (&acc)[NTL], const bool 
   for (int nt = 0; nt < NTL; ++nt) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      bf16x8 v;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = (__bf16)acc[nt][8 * c + q];
-      if (relu) {
-        s16x2 w[4];
-        __builtin_memcpy(w, &v, 16);
-        const s16x2 z = {0, 0};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = __builtin_elementwise_max(w[i], z);
-        __builtin_memcpy(&v, w, 16);
-      }
-      y[nt][2 * mt + c] = v;
+      uint4 u;
+      u.x = pack_bf16(acc[nt][8 * c + 0], acc[nt][8 * c + 1], relu);
+      u.y = pack_bf16(acc[nt][8 * c + 2], acc[nt][8 * c + 3], relu);
+      u.z = pack_bf16(acc[nt][8 * c + 4], acc[nt][8 * c + 5], relu);
+      u.w = pack_bf16(acc[nt][8 * c + 6], acc[nt][8 * c + 7], relu);
+      y[nt][2 * mt + c] = __builtin_bit_cast(bf16x8, u);
     }
   }
 }
