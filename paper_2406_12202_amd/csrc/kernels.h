@@ -28,7 +28,6 @@ struct MlpArgs {
   // (2^-ew_l) and activation (2^-ea_l) operands, and the factor 2^ea_{l+1}
   // applied to layer l's output before it is rounded to E4M3
   int f8_sw[12], f8_sx[12];
-  float f8_qout[12];
   // optional second sample set evaluated by the same launch (BF16 and FP8
   // kernels): samples n_samples .. n_samples + n_samples2 - 1 are sample
   // s - n_samples of this set, laid out [ray][k] with spr2 per ray, depths

@@ -8,12 +8,14 @@
 // direct global->LDS loads, and each wave evaluates NTL column tiles of 32
 // samples.  E4M3 activations take half the registers of bf16 ones, so two
 // column tiles fit per wave at two waves per SIMD, and every 32-byte weight
-// fragment read from LDS feeds two MFMAs.  The output of a tile is scaled by
-// 2^ea of the next layer, clamped to the E4M3 range (the conversion returns
-// NaN above it) and rounded to E4M3 in place of the bf16 epilogue.  The
-// density and colour heads act on the float32 accumulators of the last trunk
-// layer and of the direction layer in the epilogues, so they see unrounded
-// activations.  Calibration of the activation ranges (a float32 evaluation
+// fragment read from LDS feeds two MFMAs.  Each layer's accumulators come out
+// already multiplied by 2^ea of the next layer (the factor rides on the MFMA's
+// weight scale, and is packed into the layer's bias and bf16 encoding
+// weights), so the epilogue only clamps to the E4M3 range (the conversion
+// returns NaN above it) and rounds.  The density and colour heads act on the
+// float32 accumulators of the last trunk layer (head weights divided by that
+// layer's factor) and of the direction layer in the epilogues, so they see
+// unrounded activations.  Calibration of the activation ranges (a float32 evaluation
 // with per-layer maxima) sits at the end of this file.
 #include "mfma_util.h"
 #include "maplayout_fp8.h"
@@ -23,21 +25,19 @@ namespace fl {
 enum : int { kEpiRelu = 0, kEpiReluSigma = 1, kEpiLinear = 2, kEpiRgb = 3 };
 
 // E4M3 operands of the next layer from one finished output tile (bytes
-// 16 (mt % 2) .. + 15 of k-block mt / 2)
+// 16 (mt % 2) .. + 15 of k-block mt / 2).  The accumulators already carry the
+// next layer's input scale 2^ea (folded into the MFMA's weight scale, the
+// bias and the encoding weights), so the epilogue is a clamp to [0, 448]
+// (ReLU) or [-448, 448] (the E4M3 range; the conversion returns NaN above it)
+// and the rounding, four values per two conversions.
 template <int NTL, int K8, bool RELU>
-__device__ __forceinline__ void quantize_f8(const f32x16 (&acc)[NTL], const float q, const int mt,
-                                            i32x8 (&y)[NTL][K8]) {
+__device__ __forceinline__ void quantize_f8(const f32x16 (&acc)[NTL], const int mt, i32x8 (&y)[NTL][K8]) {
+  constexpr float lo = RELU ? 0.0f : -448.0f;
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt) {
     float v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      float t = acc[nt][i];
-      if (RELU) t = fmaxf(t, 0.0f);
-      t = fminf(t * q, 448.0f);
-      if (!RELU) t = fmaxf(t, -448.0f);
-      v[i] = t;
-    }
+    for (int i = 0; i < 16; ++i) v[i] = __builtin_amdgcn_fmed3f(acc[nt][i], lo, 448.0f);
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       int d = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w], v[4 * w + 1], 0, false);
@@ -79,8 +79,8 @@ template <class S, int NTL, int WAVES, int MPC, int MTO, int KBE, int EPI, bool 
 __device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const float* bias_lds, const float* head_lds,
                                          const int l, const bool use_enc, uint4* slot0, uint4* slot1,
                                          const i32x8 (&x)[NTL][S::K8], const uint4* xe, i32x8 (&y)[NTL][S::K8],
-                                         float (&hp)[NTL][3], const int sw, const int sx, const float q,
-                                         const int wv, const int lane) {
+                                         float (&hp)[NTL][3], const int sw, const int sx, const int wv,
+                                         const int lane) {
   static_assert(MTO % (2 * MPC) == 0, "layout");
   const int h = lane >> 5;
   constexpr int U8 = FIRST ? 0 : 2 * S::K8;
@@ -152,7 +152,7 @@ __device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const flo
 #pragma unroll
         for (int nt = 0; nt < NTL; ++nt) hp[nt][0] = p[nt];
       }
-      quantize_f8<NTL, S::K8, EPI != kEpiLinear>(acc, q, mt, y);
+      quantize_f8<NTL, S::K8, EPI != kEpiLinear>(acc, mt, y);
     }
   }
 }
@@ -192,12 +192,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
     for (int c = 0; c < 3; ++c) sp[nt][c] = rp[nt][c] = 0.0f;
   // input layer: bf16 products with gamma(x)
   dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, true>(wb, bias, heads, 0, true, slot0, slot1, xb, s_gx[wv],
-                                                               xa, sp, 0, 0, a.f8_qout[0], wv, lane);
+                                                               xa, sp, 0, 0, wv, lane);
 #pragma unroll 1
   for (int l = 1; l < S::D - 1; ++l) {
     dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, false>(wb, bias, heads, l, l == S::SKIP, slot0, slot1, xa,
-                                                                  s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l],
-                                                                  a.f8_qout[l], wv, lane);
+                                                                  s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l], wv,
+                                                                  lane);
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
@@ -206,15 +206,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   // last trunk layer: density head on its float32 outputs
   dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiReluSigma, false>(
       wb, bias, heads + S::SIG_OFF, S::D - 1, S::D - 1 == S::SKIP, slot0, slot1, xa, s_gx[wv], xb, sp,
-      a.f8_sw[S::D - 1], a.f8_sx[S::D - 1], a.f8_qout[S::D - 1], wv, lane);
+      a.f8_sw[S::D - 1], a.f8_sx[S::D - 1], wv, lane);
   // feature layer (no activation)
   dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiLinear, false>(wb, bias, heads, S::D, false, slot0, slot1, xb,
-                                                                  nullptr, xa, sp, a.f8_sw[S::D], a.f8_sx[S::D],
-                                                                  a.f8_qout[S::D], wv, lane);
+                                                                  nullptr, xa, sp, a.f8_sw[S::D], a.f8_sx[S::D], wv,
+                                                                  lane);
   // direction layer with gamma(d); colour head on its float32 outputs
   dense_f8<S, NTL, WAVES, MPC, S::MTD, S::KBD, kEpiRgb, false>(wb, bias, heads + S::RGB_OFF, S::D + 1, true, slot0,
                                                                 slot1, xa, s_gd[wv], xb, rp, a.f8_sw[S::D + 1],
-                                                                a.f8_sx[S::D + 1], 1.0f, wv, lane);
+                                                                a.f8_sx[S::D + 1], wv, lane);
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt) {
     float zs = sp[nt][0];

@@ -408,10 +408,11 @@ hipError_t mlp_launch(loc_ctx* c, const MlpArgs& a) {
     MlpArgs b = a;
     b.wblocks = c->wunits;
     b.heads = c->heads_f8;
+    // weight scale 2^-ew[l] times the next layer's input scale 2^ea[l+1]:
+    // the accumulators come out in the next layer's E4M3 units
     for (int l = 0; l < 12; ++l) {
-      b.f8_sw[l] = 127 - c->f8_ew[l];
+      b.f8_sw[l] = 127 - c->f8_ew[l] + (l + 1 < 12 ? c->f8_ea[l + 1] : 0);
       b.f8_sx[l] = 127 - c->f8_ea[l];
-      b.f8_qout[l] = (l + 1 < 12) ? std::ldexp(1.0f, c->f8_ea[l + 1]) : 1.0f;
     }
     return launch_mlp_fp8(c->kind, b, c->stream);
   }
@@ -444,9 +445,10 @@ int fp8_exponent(double amax) {
 }
 
 // E4M3 hidden-weight units and BF16 encoding units (maplayout_fp8.h);
-// fills ew[l] for l = 1..NL-1
+// fills ew[l] for l = 1..NL-1.  The encoding weights of layer l carry the
+// next layer's input scale 2^ea[l+1] (exact: a power of two)
 template <class S>
-std::vector<uint8_t> pack_map_fp8(const loc_map_desc& d, int* ew) {
+std::vector<uint8_t> pack_map_fp8(const loc_map_desc& d, int* ew, const int* ea) {
   Canon cn;
   canon_split(d, cn);
   std::vector<uint8_t> U((size_t)S::UNITS * 1024, 0);
@@ -478,7 +480,7 @@ std::vector<uint8_t> pack_map_fp8(const loc_map_desc& d, int* ew) {
         for (int kb = 0; kb < ue; ++kb)
           for (int q = 0; q < 8; ++q) {
             const int f = posenc_feature_b(L, kb, h, q);
-            const uint16_t v = f >= 0 ? to_bf16(W[(long)row * nin + n_h + f]) : 0;
+            const uint16_t v = f >= 0 ? to_bf16((float)std::ldexp((double)W[(long)row * nin + n_h + f], ea[l + 1])) : 0;
             const long unit = ub + u8 + kb;
             std::memcpy(&U[(size_t)(unit * 64 + lane) * 16 + 2 * q], &v, 2);
           }
@@ -488,13 +490,15 @@ std::vector<uint8_t> pack_map_fp8(const loc_map_desc& d, int* ew) {
   return U;
 }
 
-// natural-order heads of the FP8 path: density (W + bias), colour (3 x DW + 3)
+// natural-order heads of the FP8 path: density (W + bias), colour (3 x DW + 3);
+// the density weights divided by 2^e_sig, the factor the last trunk layer's
+// accumulators carry
 template <class S>
-std::vector<float> pack_heads_fp8(const loc_map_desc& d) {
+std::vector<float> pack_heads_fp8(const loc_map_desc& d, const int e_sig) {
   Canon cn;
   canon_split(d, cn);
   std::vector<float> H((size_t)S::HEADS, 0.0f);
-  for (int k = 0; k < S::W; ++k) H[S::SIG_OFF + k] = cn.W[S::D][k];
+  for (int k = 0; k < S::W; ++k) H[S::SIG_OFF + k] = std::ldexp(cn.W[S::D][k], -e_sig);
   H[S::SIG_OFF + S::W] = cn.b[S::D][0];
   const int ci = (int)cn.W.size() - 1;
   for (int c = 0; c < 3; ++c)
@@ -680,7 +684,7 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
   } else if (d->precision == LOC_FP8_E4M3) {
     // biases as in the BF16 layout; weights are packed by loc_calibrate_fp8
     PackedB P = pack_map_bf16<NerfMapB>(*d);
-    std::vector<float> H = pack_heads_fp8<NerfMapF8>(*d);
+    std::vector<float> H = pack_heads_fp8<NerfMapF8>(*d, 0);
     c->params_host.assign(d->params, d->params + d->n_params);
     ok = hipMalloc(&c->bias_b, P.bias.size() * 4) == hipSuccess &&
          hipMalloc(&c->heads_f8, H.size() * 4) == hipSuccess &&
@@ -1246,8 +1250,17 @@ loc_status loc_calibrate_fp8(loc_ctx* c, const float* o, const float* d, int n_r
     c->f8_amax[l] = v;
     c->f8_ea[l + 1] = fp8_exponent(v);
   }
-  std::vector<uint8_t> U = pack_map_fp8<S>(pd, c->f8_ew);
+  std::vector<uint8_t> U = pack_map_fp8<S>(pd, c->f8_ew, c->f8_ea);
+  // biases of layer l times 2^ea[l+1] (the layer's output scale), density head
+  // weights over the last trunk layer's factor
+  PackedB P = pack_map_bf16<NerfMapB>(pd);
+  for (int l = 0; l < S::NL; ++l)
+    for (long i = NerfMapB::bias_base(l); i < NerfMapB::bias_base(l) + 32L * NerfMapB::layer_mt(l); ++i)
+      P.bias[i] = std::ldexp(P.bias[i], c->f8_ea[l + 1]);
+  std::vector<float> H = pack_heads_fp8<S>(pd, c->f8_ea[S::D]);
   e = hipMemcpyAsync(c->wunits, U.data(), U.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->bias_b, P.bias.data(), P.bias.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->heads_f8, H.data(), H.size() * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(c, LOC_E_HIP, "FP8 weight upload: %s", hipGetErrorString(e));
   c->f8_ready = true;
