@@ -632,3 +632,89 @@ def test_localize_stage_switch_and_counts():
     o = mcl.update_particles(s, p, img, cam, 2, 4, X, seed=1, it=0)
     assert np.array_equal(r["steps"][0]["weight"], o["weight"])
     assert r["steps"][0]["var"] == mcl.position_variance(o["pose"], o["weight"])
+
+
+# ------------------------------------------------------------------ map training (Eq. 2)
+
+def _train_case(seed, S=8, jitter=1, R=3):
+    from oracle import train  # noqa: F401
+    s = synth.spec("small", n_coarse=S, jitter=jitter)
+    # no built-in solid: its pass-through units have pre-activations exactly
+    # at the ReLU kink, where the loss has no derivative
+    p = synth.map_params(s, seed, solid=False).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    O = rng.uniform(-0.5, 0.5, (R, 3))
+    D = rng.standard_normal((R, 3))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    tgt = rng.uniform(0.0, 1.0, (R, 3))
+    return s, p, O, D, tgt
+
+
+def test_photometric_gradient_matches_finite_differences():
+    from oracle import train
+    s, p, O, D, tgt = _train_case(31)
+    L, g = train.photometric_loss_grad(s, p, O, D, tgt, 5, 2)
+    assert np.isfinite(L) and g.shape == p.shape
+    rng = np.random.default_rng(1)
+    n = p.size
+    idx = np.unique(np.concatenate([rng.choice(n, 160, replace=False), np.arange(n - 243, n)]))
+    h = 1e-6
+    for k in idx:
+        e = np.zeros(n)
+        e[k] = h
+        fd = (train.photometric_loss(s, p + e, O, D, tgt, 5, 2) - train.photometric_loss(s, p - e, O, D, tgt, 5, 2)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (k, fd, g[k])
+
+
+def test_photometric_gradient_closed_form_for_a_constant_map():
+    # all weights zero: sigma = softplus(b_s), c = sigmoid(b_c) everywhere, so
+    # C_hat = A c with A = 1 - exp(-sigma (far - near)) (deterministic samples)
+    from oracle import train
+    from oracle import render as rd
+    s, p, O, D, tgt = _train_case(32, S=16, jitter=0, R=4)
+    p[:] = 0.0
+    shapes = rd.layer_shapes(s)
+    pos = {}
+    off = 0
+    for name, o, i in shapes:
+        pos[name] = (off, off + o * i, off + o * i + o)
+        off += o * i + o
+    bs, bc = 0.4, np.array([0.3, -0.7, 1.1])
+    p[pos["sigma"][1]] = bs
+    p[pos["rgb"][1]:pos["rgb"][2]] = bc
+    sig = np.log1p(np.exp(bs))
+    c = 1.0 / (1.0 + np.exp(-bc))
+    span = s["far"] - s["near"]
+    A = 1.0 - np.exp(-sig * span)
+    Chat = A * c
+    gC = 2.0 * (Chat[None, :] - tgt) / tgt.shape[0]
+    L, g = train.photometric_loss_grad(s, p, O, D, tgt, 0, 0)
+    assert abs(L - ((Chat[None, :] - tgt) ** 2).sum() / tgt.shape[0]) < 1e-14
+    g_bc = (gC * A * c * (1 - c)).sum(0)
+    assert np.allclose(g[pos["rgb"][1]:pos["rgb"][2]], g_bc, atol=1e-14, rtol=1e-12)
+    g_bs = ((gC * c).sum(1) * span * np.exp(-sig * span) / (1.0 + np.exp(-bs))).sum()
+    assert abs(g[pos["sigma"][1]] - g_bs) < 1e-14
+    # direction columns of the colour head: sum over rays of gC c (1 - c) A gamma(d)
+    gd = rd.posenc(D, s["L_dir"])
+    Wd = s["width"]
+    G = g[pos["rgb"][0]:pos["rgb"][1]].reshape(3, Wd + gd.shape[1])
+    assert np.allclose(G[:, Wd:], (gC * c * (1 - c) * A).T @ gd, atol=1e-14, rtol=1e-12)
+    # everything that multiplies a zero activation vanishes
+    assert np.all(G[:, :Wd] == 0.0)
+    assert np.all(g[:pos["sigma"][1]] == 0.0)
+
+
+def test_photometric_gradient_is_a_descent_direction():
+    from oracle import train
+    s, p, O, D, tgt = _train_case(33, R=6)
+    L, g = train.photometric_loss_grad(s, p, O, D, tgt, 1, 4)
+    L2 = train.photometric_loss(s, p - 1e-3 * g / np.linalg.norm(g), O, D, tgt, 1, 4)
+    assert L2 < L
+
+
+def test_map_adam_first_step_closed_form():
+    from oracle import train
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    th, m, v = train.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
