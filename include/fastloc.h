@@ -426,6 +426,34 @@ typedef struct { int batch, steps; float lr, beta1, beta2, eps; } loc_train_cfg;
 loc_status loc_train_proposal(loc_ctx* ctx, const float* ray_o, const float* ray_d, const float* target, int n,
                               const loc_train_cfg* cfg, float* loss_out);
 
+/* --------------------------------------------------------- map training
+ * Training of the 4x64 map (no skip input, no direction branch; n_coarse <=
+ * 64, n_fine = 0; FP32 or BF16 context) with the photometric loss of Eq. 2,
+ * read for a minibatch as the mean over the batch's rays of |C_hat(r) -
+ * C(r)|^2, C_hat the coarse render of Eq. 1 as the update computes it
+ * (stratified samples of ray r keyed (r, 0) at the call's counter).  The
+ * context keeps float32 master weights in the canonical order of
+ * loc_map_desc.params and Adam moments; the first training call starts them
+ * from the map the context was created with.
+ *
+ * loc_map_grad: gradient at the current master weights for n rays
+ *   ray_o, ray_d DEVICE n x 3 float32 (unit directions), target DEVICE n x 3
+ *   float32 colours; grad_out DEVICE 15345 float32 (canonical order);
+ *   loss_out DEVICE 1 float32 or NULL.  Per-wave partials summed in a fixed
+ *   order (deterministic).  1 <= n <= 2^20.
+ * loc_train_map: `steps` Adam steps; step k uses the cfg->batch rays from
+ *   (k * batch) mod n (cyclic) at counter (the context's step count, from 0);
+ *   loss_out DEVICE `steps` floats (mean batch loss before each step) or
+ *   NULL.  Synchronous; afterwards the context renders and localises with the
+ *   trained map (repacked for its precision).
+ * loc_get_map: the current map (HOST n_params floats, canonical order).
+ * LOC_E_UNSUPPORTED for other maps or samplings. */
+loc_status loc_map_grad(loc_ctx* ctx, const float* ray_o, const float* ray_d, const float* target, int n,
+                        uint64_t seed, uint64_t iter, float* grad_out, float* loss_out);
+loc_status loc_train_map(loc_ctx* ctx, const float* ray_o, const float* ray_d, const float* target, int n,
+                         const loc_train_cfg* cfg, uint64_t seed, float* loss_out);
+loc_status loc_get_map(loc_ctx* ctx, float* params, size_t n);
+
 void loc_destroy(loc_ctx* ctx);
 const char* loc_status_str(loc_status s);     /* static text, never NULL */
 const char* loc_last_error(const loc_ctx* ctx);/* detail of the last failure; "" if none */

@@ -23,7 +23,8 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outp
            "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
            "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
            "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-           "loc_localize"]
+           "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map"]
+SMALL_MAP_PARAMS = 15345
 PROPOSAL_PARAMS = 11296
 
 
@@ -122,6 +123,9 @@ def load(path=LIB_PATH):
                                         c_int, ctypes.c_char_p, vp]
     lib.loc_set_level_tiles.argtypes = [vp, c_int, c_int, c_int, c_int]
     lib.loc_position_variance.argtypes = [vp, vp, vp, c_int, vp]
+    lib.loc_map_grad.argtypes = [vp, vp, vp, vp, c_int, c_u64, c_u64, vp, vp]
+    lib.loc_train_map.argtypes = [vp, vp, vp, vp, c_int, ctypes.POINTER(TrainCfg), c_u64, vp]
+    lib.loc_get_map.argtypes = [vp, vp, ctypes.c_size_t]
     lib.loc_render_image.argtypes = [vp, ctypes.POINTER(Camera), c_int, vp, c_u64, c_u64, vp, vp]
     lib.loc_localize.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Stage), c_int, c_int, vp, vp,
                                  c_dbl, c_dbl, c_u64, c_u64, vp, ctypes.POINTER(c_int), ctypes.POINTER(StepInfo),
@@ -132,7 +136,7 @@ def load(path=LIB_PATH):
               "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
               "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
               "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-              "loc_localize"):
+              "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -534,3 +538,36 @@ class Context:
         if trace is not None:
             out["trace"] = trace
         return out
+
+    # ------------------------------------------------------------ map training
+
+    def loc_map_grad(self, ray_o, ray_d, target, seed=0, iter=0):
+        """Gradient of the photometric loss at the current map; returns
+        (grad (15345,), loss (1,)) device tensors."""
+        import torch
+        n = ray_o.shape[0]
+        dev = ray_o.device
+        grad = torch.empty(SMALL_MAP_PARAMS, dtype=torch.float32, device=dev)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self._check(self.lib.loc_map_grad(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                          _ptr(ray_d, torch.float32, n * 3, "ray_d"),
+                                          _ptr(target, torch.float32, n * 3, "target"), int(n), int(seed), int(iter),
+                                          grad.data_ptr(), loss.data_ptr()), "loc_map_grad")
+        return grad, loss
+
+    def loc_train_map(self, ray_o, ray_d, target, batch, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        import torch
+        n = ray_o.shape[0]
+        losses = torch.empty(max(int(steps), 1), dtype=torch.float32, device=ray_o.device)
+        cfg = TrainCfg(int(batch), int(steps), float(lr), float(beta1), float(beta2), float(eps))
+        self._check(self.lib.loc_train_map(self.h, _ptr(ray_o, torch.float32, n * 3, "ray_o"),
+                                           _ptr(ray_d, torch.float32, n * 3, "ray_d"),
+                                           _ptr(target, torch.float32, n * 3, "target"), int(n), ctypes.byref(cfg),
+                                           int(seed), losses.data_ptr()), "loc_train_map")
+        return losses[:steps]
+
+    def loc_get_map(self):
+        import numpy as np
+        p = np.empty(self._p.size, dtype=np.float32)
+        self._check(self.lib.loc_get_map(self.h, ctypes.c_void_p(p.ctypes.data), p.size), "loc_get_map")
+        return p

@@ -143,6 +143,29 @@ struct TrainArgs {
   float lr, beta1, beta2, eps;
 };
 hipError_t launch_prop_grad(const TrainArgs& a, hipStream_t st);
+// training of the 4x64 map with the photometric loss (Eq. 2)
+constexpr int kSmallMapParams = 15345;
+struct MapTrainArgs {
+  const float4* ray_o;
+  const float4* ray_d;
+  const float* target;     // per ray 3 (rgb)
+  const float* params;     // canonical order, read by the gradient kernel
+  float* params_rw;        // Adam update target (same buffer), or NULL
+  float* m;
+  float* v;
+  float* partial;          // n_waves x kSmallMapParams
+  float* loss_partial;     // n_waves
+  float* loss_out;         // mean loss per call at loss_index, or NULL
+  float* grad_out;         // summed gradient, or NULL
+  int loss_index;
+  int n_rays, first, batch, rays_per_wave, n_waves;
+  int adam, step;
+  float lr, beta1, beta2, eps;
+  int S, jitter;           // coarse samples per ray (<= 64), stratified jitter
+  uint64_t seed, iter;     // sample streams keyed (ray, 0) at counter iter
+  float near_, far_, dt;
+};
+hipError_t launch_map_grad(const MapTrainArgs& a, hipStream_t st);
 hipError_t launch_rays_to_f4(const float* o3, const float* d3, int n, float4* o4, float4* d4, hipStream_t st);
 hipError_t launch_rays_from_f4(const float4* o4, const float4* d4, int n, float* o3, float* d3, hipStream_t st);
 

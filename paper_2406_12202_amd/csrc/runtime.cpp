@@ -25,13 +25,13 @@ namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
                 K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
-                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_VARIANCE, K_COUNT };
+                K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_VARIANCE, K_MAP_TRAIN, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
                                      "pose_estimate", "fp8_calibration", "level_key", "level_predict",
                                      "level_rays", "level_scores", "level_finish", "mlp_coarse_fine",
-                                     "position_variance"};
+                                     "position_variance", "map_train"};
 
 struct Pending { int kid; hipEvent_t a, b; double flop, bytes; };
 
@@ -94,6 +94,11 @@ struct loc_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<double> graph_sig;
+  // map training (4x64 map): float32 master weights in canonical order,
+  // Adam moments, per-wave partial gradients and losses
+  DevBuf<float> tm_params, tm_m, tm_v, tm_partial, tm_lpart;
+  int tm_step = 0;
+  bool tm_ready = false;
   // localisation loop: particle sets (ping-pong), predicted set, scores,
   // drawn indices, device and pinned host copies of (var, est)
   DevBuf<double> lz_x[2], lz_pred, lz_ll, lz_w, lz_ve;
@@ -676,6 +681,7 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
     loc_destroy(c);
     return LOC_E_OOM;
   }
+  c->params_host.assign(d->params, d->params + d->n_params);
   bool ok = true;
   if (d->precision == LOC_FP32) {
     std::vector<float> P = kind == kMapSmall ? pack_map<SmallMap>(*d) : pack_map<NerfMap>(*d);
@@ -685,7 +691,6 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
     // biases as in the BF16 layout; weights are packed by loc_calibrate_fp8
     PackedB P = pack_map_bf16<NerfMapB>(*d);
     std::vector<float> H = pack_heads_fp8<NerfMapF8>(*d, 0);
-    c->params_host.assign(d->params, d->params + d->n_params);
     ok = hipMalloc(&c->bias_b, P.bias.size() * 4) == hipSuccess &&
          hipMalloc(&c->heads_f8, H.size() * 4) == hipSuccess &&
          hipMalloc(&c->wunits, (size_t)NerfMapF8::UNITS * 1024) == hipSuccess &&
@@ -725,6 +730,7 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->prop); hipFree(c->prop_m); hipFree(c->prop_v); hipFree(c->prop_partial.p); hipFree(c->prop_loss.p);
   hipFree(c->tr_o.p); hipFree(c->tr_d.p);
   for (auto& b : c->lz_x) hipFree(b.p);
+  hipFree(c->tm_params.p); hipFree(c->tm_m.p); hipFree(c->tm_v.p); hipFree(c->tm_partial.p); hipFree(c->tm_lpart.p);
   hipFree(c->lz_pred.p); hipFree(c->lz_ll.p); hipFree(c->lz_w.p); hipFree(c->lz_ve.p); hipFree(c->lz_idx.p);
   if (c->lz_host) hipHostFree(c->lz_host);
   for (auto& L : c->lv) {
@@ -1874,6 +1880,148 @@ loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, i
   HIP_TRY(c, hipMemcpyAsync(pose_out, c->lz_x[cur].p, 96L * n, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   *n_out = n;
+  return LOC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- map training
+namespace {
+
+constexpr int kMapWavesMax = 1024;   // partial-gradient rows per call, at most
+
+loc_status tm_prepare(loc_ctx* c, const float* ray_o, const float* ray_d, int n, int batch, MapTrainArgs& ta) {
+  const loc_map_desc& d = c->desc;
+  if (c->kind != kMapSmall || d.n_fine != 0 || d.n_coarse > 64 || c->desc.precision == LOC_FP8_E4M3)
+    return fail(c, LOC_E_UNSUPPORTED, "map training covers the 4x64 map with at most 64 coarse and no fine samples");
+  const int rpw = (batch + kMapWavesMax - 1) / kMapWavesMax;
+  const int n_waves = (batch + rpw - 1) / rpw;
+  loc_status s;
+  if ((s = ensure(c, c->tr_o, n)) || (s = ensure(c, c->tr_d, n)) || (s = ensure(c, c->tm_params, kSmallMapParams)) ||
+      (s = ensure(c, c->tm_m, kSmallMapParams)) || (s = ensure(c, c->tm_v, kSmallMapParams)) ||
+      (s = ensure(c, c->tm_partial, (size_t)n_waves * kSmallMapParams)) || (s = ensure(c, c->tm_lpart, n_waves)))
+    return s;
+  if (!c->tm_ready) {
+    if (c->params_host.size() != (size_t)kSmallMapParams) return fail(c, LOC_E_STATE, "map parameters missing");
+    HIP_TRY(c, hipMemcpyAsync(c->tm_params.p, c->params_host.data(), 4L * kSmallMapParams, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->tm_m.p, 0, 4L * kSmallMapParams, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->tm_v.p, 0, 4L * kSmallMapParams, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->tm_step = 0;
+    c->tm_ready = true;
+  }
+  if ((s = timed(c, K_RAYS, 0, 56.0 * n,
+                 [&] { return launch_rays_to_f4(ray_o, ray_d, n, c->tr_o.p, c->tr_d.p, c->stream); })))
+    return s;
+  ta = MapTrainArgs{};
+  ta.ray_o = c->tr_o.p;
+  ta.ray_d = c->tr_d.p;
+  ta.params = c->tm_params.p;
+  ta.partial = c->tm_partial.p;
+  ta.loss_partial = c->tm_lpart.p;
+  ta.n_rays = n;
+  ta.batch = batch;
+  ta.rays_per_wave = rpw;
+  ta.n_waves = n_waves;
+  ta.S = d.n_coarse;
+  ta.jitter = d.jitter;
+  ta.near_ = d.near_;
+  ta.far_ = d.far_;
+  ta.dt = (d.far_ - d.near_) / (float)d.n_coarse;
+  return LOC_OK;
+}
+
+// the map packed again for the context's precision from params_host
+loc_status tm_repack(loc_ctx* c) {
+  loc_map_desc d = c->desc;
+  d.params = c->params_host.data();
+  d.n_params = c->params_host.size();
+  if (d.precision == LOC_FP32) {
+    std::vector<float> P = pack_map<SmallMap>(d);
+    HIP_TRY(c, hipMemcpyAsync(c->weights, P.data(), 4 * P.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  } else {
+    PackedB P = pack_map_bf16<SmallMapB>(d);
+    HIP_TRY(c, hipMemcpyAsync(c->wblocks, P.blocks.data(), P.blocks.size() * 2, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->bias_b, P.bias.data(), P.bias.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->heads_b, P.heads.data(), P.heads.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  drop_graph(c);
+  return LOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+loc_status loc_map_grad(loc_ctx* c, const float* ray_o, const float* ray_d, const float* target, int n, uint64_t seed,
+                        uint64_t iter, float* grad_out, float* loss_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !target || !grad_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 20)) return fail(c, LOC_E_ARG, "n must be in [1, 2^20]");
+  MapTrainArgs ta;
+  loc_status s;
+  if ((s = tm_prepare(c, ray_o, ray_d, n, n, ta))) return s;
+  ta.target = target;
+  ta.first = 0;
+  ta.seed = seed;
+  ta.iter = iter;
+  ta.loss_out = loss_out;
+  ta.loss_index = 0;
+  ta.grad_out = grad_out;
+  ta.adam = 0;
+  return timed(c, K_MAP_TRAIN, 2.0 * 4.0 * SmallMap::macs() * n * ta.S, 0.0,
+               [&] { return launch_map_grad(ta, c->stream); });
+}
+
+loc_status loc_train_map(loc_ctx* c, const float* ray_o, const float* ray_d, const float* target, int n,
+                         const loc_train_cfg* cfg, uint64_t seed, float* loss_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!ray_o || !ray_d || !target || !cfg) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n < 1 || n > (1 << 24)) return fail(c, LOC_E_ARG, "n out of range");
+  if (cfg->batch < 1 || cfg->batch > (1 << 20) || cfg->steps < 0) return fail(c, LOC_E_ARG, "batch or steps out of range");
+  if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f))
+    return fail(c, LOC_E_ARG, "invalid Adam hyperparameters");
+  MapTrainArgs ta;
+  loc_status s;
+  if ((s = tm_prepare(c, ray_o, ray_d, n, cfg->batch, ta))) return s;
+  ta.target = target;
+  ta.params_rw = c->tm_params.p;
+  ta.m = c->tm_m.p;
+  ta.v = c->tm_v.p;
+  ta.loss_out = loss_out;
+  ta.adam = 1;
+  ta.lr = cfg->lr;
+  ta.beta1 = cfg->beta1;
+  ta.beta2 = cfg->beta2;
+  ta.eps = cfg->eps;
+  ta.seed = seed;
+  for (int k = 0; k < cfg->steps; ++k) {
+    ta.first = (int)(((long)k * cfg->batch) % n);
+    ta.loss_index = k;
+    ta.iter = (uint64_t)c->tm_step;
+    ta.step = ++c->tm_step;
+    if ((s = timed(c, K_MAP_TRAIN, 2.0 * 4.0 * SmallMap::macs() * cfg->batch * ta.S, 0.0,
+                   [&] { return launch_map_grad(ta, c->stream); })))
+      return s;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->params_host.data(), c->tm_params.p, 4L * kSmallMapParams, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return tm_repack(c);
+}
+
+loc_status loc_get_map(loc_ctx* c, float* params, size_t n) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!params || n != c->params_host.size()) return fail(c, LOC_E_ARG, "expected %zu floats", c->params_host.size());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(params, c->params_host.data(), 4 * n);
   return LOC_OK;
 }
 

@@ -263,3 +263,127 @@ def random_histograms(seed, n, bins=32):
     rng = np.random.default_rng([seed, 6])
     h = rng.random((n, bins)) ** 4
     return (h / h.sum(1, keepdims=True)).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Structured scene: a closed room (axis-aligned box) with a procedural texture
+# on each of its six faces, seen from inside.  Training rays are rendered
+# exactly (first face hit along the ray); a map trained on them has a valid
+# region (inside the room) and an untrained one beyond its walls.
+
+ROOM = dict(half=(3.5, 3.5, 2.5),            # room extent: |x| <= 3.5, |y| <= 3.5, |z| <= 2.5
+            views=(0.75, 0.75, 0.25),        # training cameras: |x| <= 0.75, |y| <= 0.75, |z| <= 0.25
+            pitch_deg=15.0,
+            W=160, H=120, f=140.0)           # camera of the room workload
+_FACE_BASE = np.array([[0.85, 0.35, 0.30], [0.30, 0.70, 0.40], [0.30, 0.40, 0.85],
+                       [0.85, 0.75, 0.30], [0.60, 0.35, 0.75], [0.35, 0.75, 0.80]])
+
+
+def room_camera():
+    r = ROOM
+    return (r["W"], r["H"], r["f"], r["f"], r["W"] / 2.0, r["H"] / 2.0)
+
+
+def room_colour(p, face):
+    """Texture of face `face` (0/1: x = -/+, 2/3: y = -/+, 4/5: z = -/+) at
+    points p (n, 3): the face colour modulated by two crossed sinusoids and a
+    coarse checker, values in [0.05, 0.95]."""
+    p = np.asarray(p, dtype=np.float64)
+    out = np.zeros((p.shape[0], 3))
+    for fc in range(6):
+        m = face == fc
+        if not np.any(m):
+            continue
+        ax = fc // 2
+        u, v = [p[m, a] for a in range(3) if a != ax]
+        f1, f2 = 0.9 + 0.25 * fc, 1.4 - 0.15 * fc
+        pat = 0.5 + 0.25 * np.sin(2 * math.pi * f1 * u) * np.cos(2 * math.pi * f2 * v + fc)
+        chk = ((np.floor(u / 1.2) + np.floor(v / 1.2)) % 2) * 0.3 - 0.15
+        val = np.clip(pat + chk, 0.0, 1.0)
+        base = _FACE_BASE[fc]
+        out[m] = np.clip(0.05 + 0.9 * (val[:, None] * base + (1 - val[:, None]) * (1 - base) * 0.5), 0.05, 0.95)
+    return out
+
+
+def room_render(O, D, far=None):
+    """Colour of the first room face hit by rays from inside (black beyond
+    `far`, when given)."""
+    O = np.asarray(O, dtype=np.float64).reshape(-1, 3)
+    D = np.asarray(D, dtype=np.float64).reshape(-1, 3)
+    half = np.array(ROOM["half"])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tp = np.where(D > 0, (half - O) / D, np.inf)
+        tn = np.where(D < 0, (-half - O) / D, np.inf)
+    t_ax = np.minimum(tp, tn)
+    ax = np.argmin(t_ax, axis=1)
+    t = t_ax[np.arange(O.shape[0]), ax]
+    face = 2 * ax + (tp[np.arange(O.shape[0]), ax] <= tn[np.arange(O.shape[0]), ax]).astype(int)
+    P = O + t[:, None] * D
+    C = room_colour(P, face)
+    if far is not None:
+        C[t > far] = 0.0
+    return C
+
+
+def room_pose(rng):
+    """A camera inside the view box looking horizontally (random yaw, pitch
+    within +-ROOM['pitch_deg'])."""
+    r = ROOM
+    eye = rng.uniform(-1.0, 1.0, 3) * np.array(r["views"])
+    yaw = rng.uniform(-math.pi, math.pi)
+    pitch = math.radians(rng.uniform(-r["pitch_deg"], r["pitch_deg"]))
+    fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+    return lookat(eye, eye + fwd)
+
+
+def room_rays(seed, n_views, rays_per_view, far=6.0):
+    """Training rays of the room: n_views random cameras, rays_per_view random
+    pixels each; returns O, D (float32, n x 3, unit D) and the exact colours
+    (float32), shuffled."""
+    rng = np.random.default_rng([seed, 11])
+    W, H, fx, fy, cx, cy = room_camera()
+    O, D = [], []
+    for _ in range(n_views):
+        P = room_pose(rng)
+        u = rng.integers(0, W, rays_per_view) + 0.5
+        v = rng.integers(0, H, rays_per_view) + 0.5
+        dc = np.stack([(u - cx) / fx, -(v - cy) / fy, -np.ones(rays_per_view)], 1)
+        d = dc @ P[:, :3].T
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        O.append(np.repeat(P[None, :, 3], rays_per_view, 0))
+        D.append(d)
+    O, D = np.concatenate(O), np.concatenate(D)
+    C = room_render(O, D, far)
+    perm = rng.permutation(O.shape[0])
+    return O[perm].astype(np.float32), D[perm].astype(np.float32), C[perm].astype(np.float32)
+
+
+def room_image(pose, far=6.0):
+    """Exact H x W x 3 image of the room from `pose` (pixel centres as the
+    update's rays)."""
+    W, H, fx, fy, cx, cy = room_camera()
+    P = np.asarray(pose, dtype=np.float64).reshape(3, 4)
+    v, u = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    dc = np.stack([(u - cx) / fx, -(v - cy) / fy, -np.ones_like(u)], -1).reshape(-1, 3)
+    d = dc @ P[:, :3].T
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    C = room_render(np.repeat(P[None, :, 3], d.shape[0], 0), d, far)
+    return C.reshape(H, W, 3).astype(np.float32)
+
+
+def room_particles(seed, N, gt, spread_m, spread_deg):
+    """N poses around gt: position offsets uniform in +-spread_m per axis (half
+    that vertically), rotation vector uniform in +-spread_deg per axis."""
+    rng = np.random.default_rng([seed, 12])
+    out = np.zeros((N, 3, 4))
+    for i in range(N):
+        phi = np.radians(rng.uniform(-spread_deg, spread_deg, 3))
+        out[i, :, :3] = gt[:, :3] @ _rot_exp(phi)
+        out[i, :, 3] = gt[:, 3] + rng.uniform(-1.0, 1.0, 3) * np.array([spread_m, spread_m, 0.5 * spread_m])
+    return out
+
+
+def room_map_init(seed):
+    """Initial parameters of the 4x64 map for training on the room (He-scaled
+    weights, zero biases; no built-in solid)."""
+    return map_params(spec("small"), seed, solid=False)
