@@ -68,11 +68,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize", "room"],
                     help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision); "
                          "copy: a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "levels: the coarse-to-fine workload (eager and graph); large: the FP8 workload; "
-                         "localize: the localisation loop with variance-triggered stages and its module ablation")
+                         "localize: the localisation loop with variance-triggered stages and its module ablation; "
+                         "room: a map trained on the room scene, then tau and initial-particle sweeps and the ablation")
     ap.add_argument("--trials", type=int, default=3, help="localize: starting sets per variant")
     ap.add_argument("--iters", type=int, default=40, help="localize: iterations per run")
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
@@ -400,6 +401,99 @@ def bench_localize(args, torch):
     return 0
 
 
+# room workload: the paper's schedule at the room camera's 160 x 120 pixels,
+# thresholds 0.05 m^2 and 0.01 m^2 for a +-1 m start (variance 0.75 m^2) and
+# the prediction noise (0.05 m, 2 deg) scaled by 1, 0.4 and 0.1 per stage; the
+# single-stage ablation keeps the middle factor
+ROOM_STAGES = [(4, 8, 9600, 0.05, 1.0), (2, 16, 600, 0.01, 0.4), (1, 32, 100, 0.0, 0.1)]
+ROOM_SINGLE = [(1, 32, 2400, 0.0, 0.4)]
+
+
+def bench_room(args, torch):
+    """The 4x64 map trained on the room scene (Eq. 2, 3000 Adam steps on 262 k
+    exact rays from 512 views; untimed), then localisation from starts within
+    +-1 m (+-0.5 m vertically) and +-15 deg of the true pose, where particles
+    near a pillar or a wall see through it into the map's untrained region:
+      * tau sweep of the rejection weighting (the paper's Fig. 5 analogue),
+      * initial particle count sweep (Fig. 6 analogue),
+      * module ablation (Table 3 analogue), as the localize mode.
+    The observation is the exact room image (160 x 120) plus 0.01 noise; the
+    map runs in bf16 with 32 samples per ray."""
+    from paper_2406_12202_amd import binding, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    spec = synth.spec("small", n_coarse=32)
+    O, D, C = synth.room_rays(args.seed, 512, 512)
+    tr = binding.Context(spec, synth.room_map_init(args.seed), precision="fp32", stream=stream)
+    losses = tr.loc_train_map(*[torch.as_tensor(x, device=dev) for x in (O, D, C)], batch=2048, steps=3000,
+                              lr=2e-3, seed=args.seed).cpu().numpy()
+    params = tr.loc_get_map()
+    tr.close()
+    train_s = time.perf_counter() - t0
+    cam = synth.room_camera()
+    sigma_t, sigma_r = 0.05, math.radians(2.0)
+    rng = np.random.default_rng([args.seed, 21])
+    gts = [synth.room_pose(rng) for _ in range(args.trials)]
+    imgs = [torch.as_tensor(synth.add_noise(synth.room_image(g), args.seed + k), device=dev)
+            for k, g in enumerate(gts)]
+    ctxs = {}
+
+    def ctx_for(tau):
+        if tau not in ctxs:
+            ctxs[tau] = binding.Context(dict(spec, tau=tau), params, precision="bf16", stream=stream)
+        return ctxs[tau]
+
+    def run(tau, stages, n0=None):
+        c = ctx_for(tau)
+        stages = [tuple(g) for g in stages]
+        if n0 is not None:
+            stages[0] = (stages[0][0], stages[0][1], n0, stages[0][3])
+        res = []
+        for k, gt in enumerate(gts):
+            p0 = torch.as_tensor(synth.room_particles(args.seed + k, stages[0][2], gt, 1.0, 15.0), device=dev)
+            w0 = time.perf_counter()
+            out = c.loc_localize(imgs[k], cam, stages, args.iters, p0.contiguous(), sigma_t=sigma_t, sigma_r=sigma_r,
+                                 seed=args.seed + k)
+            wall = time.perf_counter() - w0
+            st = out["steps"]
+            ok = st and np.all(np.isfinite(st[-1]["est"]))
+            pe, re = _pose_errors(st[-1]["est"], gt) if ok else (math.inf, math.inf)
+            res.append((pe, re, 1e3 * wall / max(len(st), 1)))
+        pos = np.array([r[0] for r in res])
+        rot = np.array([r[1] for r in res])
+        return {"pos_err_cm_median": float(100 * np.median(pos)), "pos_err_cm_mean": float(100 * pos.mean()),
+                "rot_err_deg_median": float(np.median(rot)), "accuracy_5cm_5deg": float(np.mean((pos < 0.05) & (rot < 5.0))),
+                "accuracy_25cm_5deg": float(np.mean((pos < 0.25) & (rot < 5.0))),
+                "ms_per_step": float(np.mean([r[2] for r in res]))}
+
+    far_near = spec["far"] - spec["near"]
+    run(0.1, ROOM_STAGES)    # untimed: workspace allocation
+    taus = [0.02, 0.05, 0.1, 0.2, 0.4, far_near]
+    tau_sweep = {("%g" % t): run(t, ROOM_STAGES) for t in taus}
+    print("# tau sweep: %s" % json.dumps(tau_sweep), flush=True)
+    n_sweep = {str(n): run(0.1, ROOM_STAGES, n0=n) for n in (600, 2400, 9600, 38400)}
+    print("# initial particles: %s" % json.dumps(n_sweep), flush=True)
+    ablation = {"full": tau_sweep["0.1"], "wo_rejection": tau_sweep["%g" % far_near],
+                "wo_c2f": run(0.1, ROOM_SINGLE), "wo_both": run(far_near, ROOM_SINGLE)}
+    print("# ablation: %s" % json.dumps(ablation), flush=True)
+    out = {"metric": "localisation on a trained room map: time per update step (with accuracy sweeps)",
+           "value": ablation["full"]["ms_per_step"], "unit": "ms/step", "n_gpus": 1, "steps": args.iters,
+           "warmup": 1, "ms_per_step": ablation["full"]["ms_per_step"], "higher_is_better": False,
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "room: 4x64 map trained on an analytic textured room (Eq. 2), bf16, 32 samples; "
+                                  "160x120 views; start within +-1 m / +-15 deg; stages 1/4, 1/2, 1 with 8/16/32 rays "
+                                  "and 9600/600/100 particles; %d iterations, %d true poses" % (args.iters, args.trials)},
+           "training": {"steps": 3000, "batch": 2048, "rays": int(O.shape[0]), "seconds": train_s,
+                        "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
+           "tau_sweep": tau_sweep, "initial_particles": n_sweep, "ablation": ablation}
+    print(json.dumps(out), flush=True)
+    for c in ctxs.values():
+        c.close()
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -415,6 +509,8 @@ def main():
         return bench_large(args, torch)
     if args.mode == "localize":
         return bench_localize(args, torch)
+    if args.mode == "room":
+        return bench_room(args, torch)
     from paper_2406_12202_amd import binding, synth
 
     wl = args.workload if args.mode == "single" else "nerf"

@@ -304,6 +304,8 @@ typedef struct {
   int B;          /* rays per particle, [1, 1024] */
   int N;          /* particles drawn while in this stage, [1, 2^24] */
   double delta;   /* variance threshold that ends the stage */
+  double noise;   /* factor (>= 0) on sigma_t and sigma_r for the iterations
+                     this stage weights (the paper fixes no noise schedule) */
 } loc_stage;
 
 typedef struct {

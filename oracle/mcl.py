@@ -340,19 +340,22 @@ def position_variance(poses, weight):
 
 def localize(spec, params, image, cam, stages, n_iters, poses, motion=None, sigma_t=0.0, sigma_r=0.0,
              seed=0, proposal=None):
-    """The localisation loop: stages = [(inv_R, B, N, delta), ...].  At every
-    iteration t (counter t) the particle set is updated at the current stage's
-    scale and ray count (update_particles), the pose is read out and the
-    position variance of the weighted set measured; when the variance falls
-    below the stage's delta the next stage begins (the last stage's delta is
-    never used); then N particles of the (possibly new) stage are drawn
-    (counter t).  Returns per-iteration records and the final set."""
+    """The localisation loop: stages = [(inv_R, B, N, delta[, noise]), ...].
+    At every iteration t (counter t) the particle set is updated at the
+    current stage's scale and ray count (update_particles) with prediction
+    noise (noise sigma_t, noise sigma_r) (noise = 1 when not given), the pose
+    is read out and the position variance of the weighted set measured; when
+    the variance falls below the stage's delta the next stage begins (the
+    last stage's delta is never used); then N particles of the (possibly new)
+    stage are drawn (counter t).  Returns per-iteration records and the final
+    set."""
     X = np.asarray(poses, dtype=np.float64).reshape(-1, 3, 4)
     s = 0
     recs = []
     for t in range(n_iters):
-        inv_R, B, N, delta = stages[s]
-        o = update_particles(spec, params, image, cam, inv_R, B, X, motion, sigma_t, sigma_r, seed, t,
+        inv_R, B, N, delta = stages[s][:4]
+        k = stages[s][4] if len(stages[s]) > 4 else 1.0
+        o = update_particles(spec, params, image, cam, inv_R, B, X, motion, k * sigma_t, k * sigma_r, seed, t,
                              proposal=proposal)
         var = position_variance(o["pose"], o["weight"])
         est = se3.pose_estimate(o["pose"], o["weight"]) if np.any(o["weight"] > 0) else None

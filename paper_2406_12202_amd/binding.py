@@ -57,7 +57,8 @@ class Level(ctypes.Structure):
 
 
 class Stage(ctypes.Structure):
-    _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("N", ctypes.c_int), ("delta", ctypes.c_double)]
+    _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("N", ctypes.c_int), ("delta", ctypes.c_double),
+                ("noise", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -497,7 +498,7 @@ class Context:
 
     def loc_localize(self, image, cam, stages, n_iters, pose_in, motion=None, sigma_t=0.0, sigma_r=0.0, seed=0,
                      iter=0, trace_capacity=0):
-        """The localisation loop; stages = [(inv_R, B, N, delta), ...].  Returns
+        """The localisation loop; stages = [(inv_R, B, N, delta[, noise]), ...].  Returns
         a dict: pose (final set, n_out x 3 x 4), steps (per-iteration records)
         and, with trace_capacity > 0, the appended trace tensors."""
         import numpy as np
@@ -506,8 +507,8 @@ class Context:
         n_in = pose_in.shape[0]
         dev = pose_in.device
         st = (Stage * len(stages))()
-        for k, (r, b, n, dl) in enumerate(stages):
-            st[k] = Stage(int(r), int(b), int(n), float(dl))
+        for k, g in enumerate(stages):
+            st[k] = Stage(int(g[0]), int(g[1]), int(g[2]), float(g[3]), float(g[4]) if len(g) > 4 else 1.0)
         n_max = max(int(g[2]) for g in stages)
         pose_out = torch.empty((max(n_max, 1), 3, 4), dtype=torch.float64, device=dev)
         info = (StepInfo * int(n_iters))()

@@ -1803,6 +1803,7 @@ loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, i
     if (g.B < 1 || g.B > 1024 || g.N < 1 || g.N > (1 << 24))
       return fail(c, LOC_E_ARG, "stage %d: B or N out of range", k);
     if (k + 1 < n_stages && std::isnan(g.delta)) return fail(c, LOC_E_ARG, "stage %d: delta is NaN", k);
+    if (!(g.noise >= 0.0) || !std::isfinite(g.noise)) return fail(c, LOC_E_ARG, "stage %d: noise factor", k);
     n_max = std::max(n_max, g.N);
   }
   if (n_in < 1 || n_in > (1 << 24)) return fail(c, LOC_E_ARG, "n_in must be in [1, 2^24]");
@@ -1826,8 +1827,8 @@ loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, i
     const auto t0 = std::chrono::steady_clock::now();
     const loc_stage& g = stages[st];
     const uint64_t it = iter + (uint64_t)t;
-    if ((s = loc_update_particles(c, image, cam, g.inv_R, g.B, n, c->lz_x[cur].p, motion, sigma_t, sigma_r, seed, it,
-                                  c->lz_pred.p, c->lz_ll.p, c->lz_w.p, nullptr)))
+    if ((s = loc_update_particles(c, image, cam, g.inv_R, g.B, n, c->lz_x[cur].p, motion, g.noise * sigma_t,
+                                  g.noise * sigma_r, seed, it, c->lz_pred.p, c->lz_ll.p, c->lz_w.p, nullptr)))
       return s;
     if ((s = loc_position_variance(c, c->lz_pred.p, c->lz_w.p, n, c->lz_ve.p)) ||
         (s = loc_pose_estimate(c, c->lz_pred.p, c->lz_w.p, n, c->lz_ve.p + 1)))

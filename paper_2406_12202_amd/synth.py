@@ -267,11 +267,15 @@ def random_histograms(seed, n, bins=32):
 
 # ---------------------------------------------------------------------------
 # Structured scene: a closed room (axis-aligned box) with a procedural texture
-# on each of its six faces, seen from inside.  Training rays are rendered
+# on each of its six faces and eight textured pillars standing in front of the
+# walls, seen from inside.  Training rays are rendered
 # exactly (first face hit along the ray); a map trained on them has a valid
 # region (inside the room) and an untrained one beyond its walls.
 
 ROOM = dict(half=(3.5, 3.5, 2.5),            # room extent: |x| <= 3.5, |y| <= 3.5, |z| <= 2.5
+            # floor-to-ceiling pillars (centre x, y, half width): depth steps in front of the walls
+            pillars=((2.7, 2.7, 0.35), (-2.7, 2.7, 0.35), (2.7, -2.7, 0.35), (-2.7, -2.7, 0.35),
+                     (3.1, 0.0, 0.25), (-3.1, 0.0, 0.25), (0.0, 3.1, 0.25), (0.0, -3.1, 0.25)),
             views=(0.75, 0.75, 0.25),        # training cameras: |x| <= 0.75, |y| <= 0.75, |z| <= 0.25
             pitch_deg=15.0,
             W=160, H=120, f=140.0)           # camera of the room workload
@@ -286,8 +290,9 @@ def room_camera():
 
 def room_colour(p, face):
     """Texture of face `face` (0/1: x = -/+, 2/3: y = -/+, 4/5: z = -/+) at
-    points p (n, 3): the face colour modulated by two crossed sinusoids and a
-    coarse checker, values in [0.05, 0.95]."""
+    points p (n, 3): the face colour modulated by two crossed sinusoids of
+    periods 2.5 to 5 units and a checker of 2-unit squares, values in
+    [0.05, 0.95]."""
     p = np.asarray(p, dtype=np.float64)
     out = np.zeros((p.shape[0], 3))
     for fc in range(6):
@@ -296,9 +301,9 @@ def room_colour(p, face):
             continue
         ax = fc // 2
         u, v = [p[m, a] for a in range(3) if a != ax]
-        f1, f2 = 0.9 + 0.25 * fc, 1.4 - 0.15 * fc
-        pat = 0.5 + 0.25 * np.sin(2 * math.pi * f1 * u) * np.cos(2 * math.pi * f2 * v + fc)
-        chk = ((np.floor(u / 1.2) + np.floor(v / 1.2)) % 2) * 0.3 - 0.15
+        f1, f2 = 0.25 + 0.05 * fc, 0.35 - 0.03 * fc
+        pat = 0.5 + 0.3 * np.sin(2 * math.pi * f1 * u + 0.7 * fc) * np.cos(2 * math.pi * f2 * v + fc)
+        chk = ((np.floor(u / 2.0) + np.floor(v / 2.0)) % 2) * 0.3 - 0.15
         val = np.clip(pat + chk, 0.0, 1.0)
         base = _FACE_BASE[fc]
         out[m] = np.clip(0.05 + 0.9 * (val[:, None] * base + (1 - val[:, None]) * (1 - base) * 0.5), 0.05, 0.95)
@@ -320,6 +325,25 @@ def room_render(O, D, far=None):
     face = 2 * ax + (tp[np.arange(O.shape[0]), ax] <= tn[np.arange(O.shape[0]), ax]).astype(int)
     P = O + t[:, None] * D
     C = room_colour(P, face)
+    # pillars: slab test in x and y (they span the full height)
+    for q, (px, py, hw) in enumerate(ROOM["pillars"]):
+        lo = np.array([px - hw, py - hw])
+        hi = np.array([px + hw, py + hw])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1 = (lo - O[:, :2]) / D[:, :2]
+            t2 = (hi - O[:, :2]) / D[:, :2]
+        tmin = np.nanmax(np.minimum(t1, t2), axis=1)
+        tmax = np.nanmin(np.maximum(t1, t2), axis=1)
+        hit = (tmin <= tmax) & (tmin > 0) & (tmin < t)
+        if np.any(hit):
+            t = np.where(hit, tmin, t)
+            Ph = O[hit] + tmin[hit, None] * D[hit]
+            u = Ph[:, 0] + Ph[:, 1]
+            v = Ph[:, 2]
+            stripe = 0.5 + 0.4 * np.sign(np.sin(2 * math.pi * (0.8 * v + 0.3 * q)))
+            base = _FACE_BASE[(q + 2) % 6]
+            C[hit] = np.clip(0.1 + 0.8 * (stripe[:, None] * (1 - base) + (1 - stripe[:, None]) * base * 0.7)
+                             + 0.05 * np.sin(2 * math.pi * 0.5 * u)[:, None], 0.05, 0.95)
     if far is not None:
         C[t > far] = 0.0
     return C

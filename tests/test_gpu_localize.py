@@ -156,10 +156,11 @@ def _check_lockstep(spec, params, img, cam, stages, poses0, out, seed, sigma_t, 
     s = 0
     toff = ioff = 0
     for t, rec in enumerate(steps):
-        inv_R, B, _, _ = stages[s]
+        inv_R, B = stages[s][:2]
+        kn = stages[s][4] if len(stages[s]) > 4 else 1.0
         assert rec["iter"] == t and rec["stage"] == s and rec["n"] == X.shape[0]
         n = rec["n"]
-        o = mcl.update_particles(spec, params, img, cam, inv_R, B, X, motion, sigma_t, sigma_r, seed, t)
+        o = mcl.update_particles(spec, params, img, cam, inv_R, B, X, motion, kn * sigma_t, kn * sigma_r, seed, t)
         pred, w = tp[toff:toff + n], tw[toff:toff + n]
         assert np.allclose(pred.reshape(n, 12), o["pose"].reshape(n, 12), atol=1e-12, rtol=0)
         big = o["weight"] > 1e-6
@@ -232,7 +233,7 @@ def test_localize_three_stages_with_motion(torch_dev):
     dev = torch.device("cuda", 0)
     motion = se3.exp_se3(np.array([0.02, 0.0, -0.01]), np.array([0.01, -0.02, 0.015]))
     ctx = _ctx(spec, params)
-    stages = [(4, 4, 64, math.inf), (2, 8, 32, math.inf), (1, 16, 16, 0.0)]
+    stages = [(4, 4, 64, math.inf, 2.0), (2, 8, 32, math.inf), (1, 16, 16, 0.0, 0.5)]
     out = ctx.loc_localize(torch.as_tensor(img, device=dev), cam, stages, 4,
                            torch.as_tensor(poses, device=dev).contiguous(), motion=motion, sigma_t=0.02,
                            sigma_r=0.01, seed=seed, iter=0, trace_capacity=4 * 64)
@@ -271,7 +272,8 @@ def test_localize_rejects_bad_stage(torch_dev):
     ctx = _ctx(spec, params)
     img_d = torch.as_tensor(img, device=dev)
     pose_d = torch.as_tensor(poses, device=dev).contiguous()
-    for bad in ([(3, 8, 16, 0.0)], [(1, 0, 16, 0.0)], [(1, 8, 0, 0.0)], [(1, 8, 16, math.nan), (1, 8, 8, 0.0)]):
+    for bad in ([(3, 8, 16, 0.0)], [(1, 0, 16, 0.0)], [(1, 8, 0, 0.0)], [(1, 8, 16, math.nan), (1, 8, 8, 0.0)],
+                [(1, 8, 16, 0.0, -1.0)]):
         with pytest.raises(LocError):
             ctx.loc_localize(img_d, cam, bad, 2, pose_d)
     with pytest.raises(LocError):

@@ -718,3 +718,19 @@ def test_map_adam_first_step_closed_form():
     th, m, v = train.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_localize_stage_noise_factor():
+    # a stage's noise factor scales both prediction noises: factor 0 is the
+    # noiseless update, factor 2 equals doubling sigma_t and sigma_r
+    s = synth.spec("small")
+    p = synth.map_params(s, 9)
+    cam = synth.camera("small")
+    X = synth.particles("small", 9, N=6)
+    img = synth.observation("small", 9)
+    r0 = mcl.localize(s, p, img, cam, [(2, 4, 6, 0.0, 0.0)], 1, X, sigma_t=0.3, sigma_r=0.2, seed=3)
+    o0 = mcl.update_particles(s, p, img, cam, 2, 4, X, None, 0.0, 0.0, 3, 0)
+    assert np.array_equal(r0["steps"][0]["weight"], o0["weight"])
+    r2 = mcl.localize(s, p, img, cam, [(2, 4, 6, 0.0, 2.0)], 1, X, sigma_t=0.3, sigma_r=0.2, seed=3)
+    o2 = mcl.update_particles(s, p, img, cam, 2, 4, X, None, 0.6, 0.4, 3, 0)
+    assert np.array_equal(r2["steps"][0]["weight"], o2["weight"])
