@@ -16,6 +16,7 @@ log-likelihood is l_i = 4 (ln B - ln S_i), so w_i is proportional to
 import math
 import numpy as np
 
+from . import grid as gr
 from . import philox as px
 from . import proposal as pr
 from . import render as rd
@@ -84,6 +85,22 @@ def predict(pose, motion, sigma_t, sigma_r, seed, it, i):
 # ----------------------------------------------------------------------------
 # rendering of one particle's query rays
 
+def unpack_map(spec, params):
+    """Map parameters as the map type needs them: the NeRF MLP's flat vector,
+    or, for a grid map (spec["map_type"] == "grid", Sec. IV-B), the pair
+    (tables, mlp) of oracle.grid."""
+    if spec.get("map_type") == "grid":
+        return gr.unpack(spec, params[0], params[1])
+    return rd.unpack(spec, params)
+
+
+def map_eval(spec, P, x, d):
+    """sigma and rgb of the map at points x seen along d."""
+    if spec.get("map_type") == "grid":
+        return gr.mlp(spec, P, x, d)
+    return rd.mlp(spec, P, x, d)
+
+
 def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False):
     """Render rays [(o, d)] whose random streams are keyed by (i, j) = keys[r].
     Fine samples (n_fine > 0) come from hierarchical sampling on the coarse
@@ -95,7 +112,7 @@ def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False
     # coarse map queries for all rays in one batch
     X = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tc)])
     Dd = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tc)])
-    sig_c, rgb_c = rd.mlp(spec, P, X, Dd)
+    sig_c, rgb_c = map_eval(spec, P, X, Dd)
     Sc = spec["n_coarse"]
     far = spec["far"]
     ts, sigs, rgbs = [], [], []
@@ -116,7 +133,7 @@ def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False
                 tf.append(rd.sample_pdf(tc[r], mass, far, fine_u(spec, seed, it, i, j)))
         Xf = np.concatenate([o[None, :] + t[:, None] * d[None, :] for (o, d), t in zip(rays, tf)])
         Df = np.concatenate([np.repeat(d[None, :], t.size, 0) for (o, d), t in zip(rays, tf)])
-        sig_f, rgb_f = rd.mlp(spec, P, Xf, Df)
+        sig_f, rgb_f = map_eval(spec, P, Xf, Df)
         Sf = spec["n_fine"]
         for r in range(B):
             sc, sf = slice(r * Sc, (r + 1) * Sc), slice(r * Sf, (r + 1) * Sf)
@@ -154,7 +171,7 @@ def particle_rays(pose, pix, Wl, cam_l):
 def teacher_histograms(spec, params, O, D, seed, it):
     """Proposal training targets for rays (O[r], D[r]) from a full render of
     the map (streams keyed by (r, 0))."""
-    P = rd.unpack(spec, params)
+    P = unpack_map(spec, params)
     rays = [(np.asarray(o, dtype=np.float64), np.asarray(d, dtype=np.float64)) for o, d in zip(O, D)]
     r = render_rays(spec, P, rays, [(k, 0) for k in range(len(rays))], seed, it, keep_samples=True)
     return np.array([pr.teacher_histogram(t, w, spec["near"], spec["far"], A)
@@ -197,7 +214,7 @@ def update_particles(spec, params, image, cam, inv_R, B, poses, motion=None,
            histogram instead of hierarchical sampling
     Returns per-particle predicted poses, log-likelihoods, normalised weights
     (over the subset), mean uncertainty, and per-ray renders."""
-    P = rd.unpack(spec, params)
+    P = unpack_map(spec, params)
     Wf, Hf, fx, fy, cx, cy = cam
     s = int(inv_R)
     img_l = rd.downscale(image, s)

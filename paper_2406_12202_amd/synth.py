@@ -411,3 +411,37 @@ def room_map_init(seed):
     """Initial parameters of the 4x64 map for training on the room (He-scaled
     weights, zero biases; no built-in solid)."""
     return map_params(spec("small"), seed, solid=False)
+
+
+# ---------------------------------------------------------------------------
+# Multi-resolution grid map (16 levels of 2^19 two-feature entries, resolutions
+# 16 .. 2048 over [-4, 4]^3, 64-wide tiny MLP), the second map type.
+
+GRID_MAP = dict(map_type="grid", levels=16, log2_table=19, n_min=16, n_max=2048, bound=4.0, L_dir=2)
+
+
+def grid_spec(n_coarse=64, n_fine=128, **over):
+    s = dict(GRID_MAP)
+    s.update(RENDER)
+    s.update(n_coarse=n_coarse, n_fine=n_fine)
+    s.update(over)
+    return s
+
+
+def grid_params(s, seed, feature_scale=0.5):
+    """Seeded grid tables (L x T x 2 float32, N(0, feature_scale^2)) and tiny-MLP
+    parameters (He-scaled weights, zero biases; the density output's weights
+    x3 and bias -1 so that sigma spans empty and opaque stretches)."""
+    rng = np.random.default_rng([seed, 31])
+    T = 1 << s["log2_table"]
+    tables = (feature_scale * rng.standard_normal((s["levels"], T, 2))).astype(np.float32)
+    in_d = 3 + 6 * s["L_dir"]
+    parts = []
+    for name, o, i in (("W1", 64, 2 * s["levels"]), ("W2", 16, 64), ("W3", 64, 16 + in_d), ("W4", 3, 64)):
+        W = rng.standard_normal((o, i)) * math.sqrt(2.0 / i)
+        b = np.zeros(o)
+        if name == "W2":
+            W[0] *= 3.0
+            b[0] = -1.0
+        parts += [W.ravel(), b]
+    return tables.ravel(), np.concatenate(parts).astype(np.float32)

@@ -734,3 +734,126 @@ def test_localize_stage_noise_factor():
     r2 = mcl.localize(s, p, img, cam, [(2, 4, 6, 0.0, 2.0)], 1, X, sigma_t=0.3, sigma_r=0.2, seed=3)
     o2 = mcl.update_particles(s, p, img, cam, 2, 4, X, None, 0.6, 0.4, 3, 0)
     assert np.array_equal(r2["steps"][0]["weight"], o2["weight"])
+
+
+# ------------------------------------------------------------------ grid map (Sec. IV-B)
+
+def _grid_small(levels=3, log2_table=12, n_min=4, n_max=32, L_dir=1):
+    return dict(map_type="grid", levels=levels, log2_table=log2_table, n_min=n_min, n_max=n_max, bound=2.0,
+                L_dir=L_dir, near=2.0, far=6.0, alpha=0.05, tau=0.1, jitter=0, n_coarse=8, n_fine=0)
+
+
+def test_grid_resolutions_span_min_to_max():
+    from oracle import grid
+    s = synth.grid_spec()
+    N = grid.resolutions(s)
+    assert N[0] == 16 and N[-1] == 2048 and len(N) == 16
+    assert all(b > a for a, b in zip(N, N[1:]))
+    assert grid.resolutions(_grid_small(levels=1)) == [4]
+
+
+def test_grid_dense_vertex_returns_the_table_entry():
+    from oracle import grid
+    s = _grid_small(levels=1, n_min=4)
+    T = 1 << s["log2_table"]
+    rng = np.random.default_rng(4)
+    tables = rng.standard_normal((1, T, 2)).astype(np.float32)
+    P = grid.unpack(s, tables, np.zeros(grid.n_mlp_params(s), np.float32))
+    c = np.array([[1, 2, 3], [0, 0, 0], [4, 4, 4], [4, 0, 2]])
+    x = c / 4.0 * 4.0 - 2.0                      # u = c / N, x = 2 bound u - bound
+    f, inside = grid.encode(s, P, x)
+    assert np.all(inside)
+    idx = c[:, 0] + 5 * c[:, 1] + 25 * c[:, 2]
+    assert np.array_equal(f, tables[0][idx].astype(np.float64))
+
+
+def test_grid_trilinear_reproduces_a_linear_field():
+    from oracle import grid
+    s = _grid_small(levels=1, n_min=6)
+    T = 1 << s["log2_table"]
+    N = 6
+    # feature k = c . a[:, k] + b[k]; dyadic coefficients keep the table exact in float32
+    a = np.array([[0.375, -1.25], [0.75, 0.5], [-0.5, 0.25]])
+    b0 = np.array([0.125, -0.25])
+    tab = np.zeros((1, T, 2))
+    for i in range(N + 1):
+        for j in range(N + 1):
+            for k in range(N + 1):
+                tab[0, i + j * (N + 1) + k * (N + 1) ** 2] = np.array([i, j, k]) @ a + b0
+    P = grid.unpack(s, tab.astype(np.float32), np.zeros(grid.n_mlp_params(s), np.float32))
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-2.0, 2.0, (50, 3))
+    f, _ = grid.encode(s, P, x)
+    p = (x + 2.0) / 4.0 * N
+    assert np.allclose(f, p @ a + b0, atol=1e-12)
+
+
+def test_grid_hash_along_first_axis_and_range():
+    from oracle import grid
+    T = 1 << 12
+    c = np.array([[5, 0, 0], [4095, 0, 0], [4096, 0, 0], [10000, 0, 0]])
+    # prime 1 on the first axis: the index is c_0 mod T
+    assert np.array_equal(grid.vertex_index(c, 100, T), c[:, 0] % T)
+    rng = np.random.default_rng(6)
+    idx = grid.vertex_index(rng.integers(0, 2049, (200000, 3)), 2048, T)
+    assert idx.min() >= 0 and idx.max() < T
+    counts = np.bincount(idx, minlength=T)
+    # spread over the table like independent uniform draws (Poisson counts)
+    assert counts.std() < 1.2 * np.sqrt(counts.mean())
+
+
+def test_grid_outside_box_is_empty_and_mlp_wiring():
+    from oracle import grid
+    s = _grid_small(levels=2, L_dir=1)
+    T = 1 << s["log2_table"]
+    tables = np.zeros((2, T, 2), np.float32)
+    shapes = grid.mlp_shapes(s)
+    flat = np.zeros(grid.n_mlp_params(s), np.float32)
+    pos = {}
+    off = 0
+    for name, o, i in shapes:
+        pos[name] = (off, o, i)
+        off += o * i + o
+    # zero features: h1 = relu(b1); z = W2 h1 + b2; rgb from [z, gamma(d)]
+    o1, n1, _ = pos["W1"]
+    flat[o1 + n1 * (2 * 2):o1 + n1 * (2 * 2) + n1] = np.linspace(-1.0, 1.0, n1)      # b1
+    o2, n2, i2 = pos["W2"]
+    W2 = np.zeros((n2, i2))
+    W2[0, :] = 0.05
+    flat[o2:o2 + n2 * i2] = W2.ravel()
+    flat[o2 + n2 * i2] = 0.3                                                      # b2[0]
+    o4, n4, i4 = pos["W4"]
+    flat[o4 + n4 * i4:o4 + n4 * i4 + 3] = [0.5, -0.5, 0.0]                        # b4
+    P = grid.unpack(s, tables, flat)
+    sig, rgb = grid.mlp(s, P, np.array([[0.5, -0.5, 1.0], [3.0, 0.0, 0.0]]), np.array([[0, 0, 1.0], [0, 0, 1.0]]))
+    h1 = np.maximum(np.linspace(-1.0, 1.0, n1).astype(np.float32).astype(np.float64), 0.0)
+    z0 = np.float64(np.float32(0.05)) * h1.sum() + np.float64(np.float32(0.3))
+    assert abs(sig[0] - np.log1p(np.exp(z0))) < 1e-14
+    assert np.allclose(rgb[0], 1.0 / (1.0 + np.exp(-np.array([0.5, -0.5, 0.0]))), atol=1e-15)
+    assert sig[1] == 0.0 and np.all(rgb[1] == 0.0)
+
+
+def test_grid_map_through_the_renderer_constant_field():
+    # zero tables and hidden weights: sigma = softplus(b2[0]) and c = sigmoid(b4)
+    # everywhere inside the box, so Eq. 1 gives C = (1 - exp(-sigma (far - near))) c
+    from oracle import grid
+    s = _grid_small(levels=2)
+    s["bound"] = 10.0
+    T = 1 << s["log2_table"]
+    flat = np.zeros(grid.n_mlp_params(s), np.float32)
+    off = 0
+    for name, o, i in grid.mlp_shapes(s):
+        if name == "W2":
+            flat[off + o * i] = 0.7
+        if name == "W4":
+            flat[off + o * i:off + o * i + 3] = [0.2, -0.4, 1.0]
+        off += o * i + o
+    params = (np.zeros(2 * T * 2, np.float32), flat)
+    P = mcl.unpack_map(s, params)
+    rays = [(np.array([0.0, 0.0, 0.0]), np.array([0.0, 0.6, 0.8]))]
+    r = mcl.render_rays(s, P, rays, [(0, 0)], 0, 0)
+    sig = np.log1p(np.exp(np.float64(np.float32(0.7))))
+    c = 1.0 / (1.0 + np.exp(-np.array([0.2, -0.4, 1.0], np.float32).astype(np.float64)))
+    A = 1.0 - np.exp(-sig * (s["far"] - s["near"]))
+    assert np.allclose(r["C"][0], A * c, atol=1e-13)
+    assert abs(r["A"][0] - A) < 1e-13
