@@ -68,12 +68,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize", "room"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize", "room", "grid"],
                     help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision); "
                          "copy: a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "levels: the coarse-to-fine workload (eager and graph); large: the FP8 workload; "
                          "localize: the localisation loop with variance-triggered stages and its module ablation; "
-                         "room: a map trained on the room scene, then tau and initial-particle sweeps and the ablation")
+                         "room: a map trained on the room scene, then tau and initial-particle sweeps and the ablation; "
+                         "grid: the multi-resolution grid map on the NeRF-sized workload")
     ap.add_argument("--trials", type=int, default=3, help="localize: starting sets per variant")
     ap.add_argument("--iters", type=int, default=40, help="localize: iterations per run")
     ap.add_argument("--workload", default="nerf", choices=["nerf", "small"])
@@ -494,6 +495,51 @@ def bench_room(args, torch):
     return 0
 
 
+def bench_grid(args, torch):
+    """The multi-resolution grid map (16 levels of 2^19 entries of two
+    half-precision features, resolutions 16..2048 over [-4, 4]^3, 64-wide tiny
+    MLP) on the NeRF-sized workload: 400 particles x 64 rays x (64 + 128
+    hierarchical) samples, K steps of update, read-out, resampling and
+    gather.  The map kernel's roofline is the gather: 8 corners x one 4-byte
+    entry per level (512 B per sample) plus the 20 B sample output, against
+    HBM's 8 TB/s."""
+    from paper_2406_12202_amd import binding, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    spec = synth.grid_spec()
+    params = synth.grid_params(spec, args.seed)
+    W = synth.WORKLOADS["nerf"]
+    N, B = W["N"], W["B"]
+    cam = synth.camera("nerf")
+    img_d = torch.as_tensor(synth.observation("nerf", args.seed), device=dev)
+    pose_a = torch.as_tensor(synth.particles("nerf", args.seed), device=dev).contiguous()
+    ctx = binding.Context(spec, params, stream=stream)
+    ms, ks, flags = time_path(ctx, img_d, cam, B, pose_a, args.steps, args.warmup, args.seed, torch)
+    S = spec["n_coarse"] + spec["n_fine"]
+    maps = [ks[k] for k in ("mlp_coarse", "mlp_fine") if k in ks]
+    m_ms = sum(m["ms"] for m in maps)
+    m_bytes = sum(m["bytes"] for m in maps)
+    m_launch = sum(m["launches"] for m in maps)
+    achieved = m_bytes / (m_ms * 1e-3) / 1e9
+    total_k = sum(x["ms"] for x in ks.values())
+    kernels = {k: {"launches": v["launches"], "avg_ms": v["ms"] / max(v["launches"], 1), "share": v["ms"] / total_k}
+               for k, v in ks.items()}
+    out = {"metric": "MLP samples/s (multi-resolution grid map)", "value": N * B * S * args.steps / (ms * 1e-3),
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "grid: %d particles x %d rays x (64 + 128) samples, 16-level hash grid (2^19 entries "
+                                  "of two fp16 features per level) + 64-wide tiny MLP, 400x400 view" % (N, B)},
+           "particle_updates_per_s": N * args.steps / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_grid_map (16 levels)",
+                        "bytes_per_launch": m_bytes / m_launch, "avg_launch_ms": m_ms / m_launch},
+           "kernels": kernels, "flags": flags}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -511,6 +557,8 @@ def main():
         return bench_localize(args, torch)
     if args.mode == "room":
         return bench_room(args, torch)
+    if args.mode == "grid":
+        return bench_grid(args, torch)
     from paper_2406_12202_amd import binding, synth
 
     wl = args.workload if args.mode == "single" else "nerf"

@@ -123,6 +123,41 @@ typedef struct {
  * s = 1/R the intrinsics are R K = (fx/s, fy/s, cx/s, cy/s). */
 typedef struct { int W, H; double fx, fy, cx, cy; } loc_camera;
 
+/* Multi-resolution grid map (the map type of Sec. IV-B, read as a
+ * multiresolution hash encoding with a tiny MLP; no anti-aliased
+ * multisampling).  The map covers [-bound, bound]^3 (u = (x + bound) /
+ * (2 bound); points outside are empty); level l = 0..levels-1 has resolution
+ * N_l = floor(n_min b^l + 1e-6), b = exp((ln n_max - ln n_min) / (levels - 1));
+ * a point's level feature is the trilinear blend (weights prod (1 - |p - c|),
+ * p = u N_l) of the two-feature entries of its cell's 8 corners c, indexed
+ * densely (c_0 + c_1 (N_l + 1) + c_2 (N_l + 1)^2) while (N_l + 1)^3 <= T and
+ * by the hash (c_0 xor 2654435761 c_1 xor 805459861 c_2) mod 2^32 mod T
+ * otherwise.  Network: z = W2 relu(W1 f + b1) + b2 (64 hidden, 16 outputs),
+ * sigma = softplus(z_0), rgb = sigmoid(W4 relu(W3 [z, gamma(d)] + b3) + b4)
+ * (64 hidden).  Rendering settings as loc_map_desc; the map runs in float32.
+ *   tables  HOST levels x T x 2 float32 (T = 2^log2_table, level-major);
+ *           stored on the device in half precision (rounded to nearest even
+ *           on upload; values representable in half precision are exact)
+ *   mlp     HOST n_mlp float32: W1 (64 x 2 levels), b1, W2 (16 x 64), b2,
+ *           W3 (64 x (16 + 3 + 6 L_dir)), b3, W4 (3 x 64), b4 (row-major)
+ * levels in {4, 8, 16}, L_dir in {2, 4} (LOC_E_UNSUPPORTED otherwise),
+ * log2_table in [10, 24], 2 <= n_min <= n_max <= 2^16.  Every update,
+ * render and localisation call accepts the context; the coarse-to-fine level
+ * path, FP8 calibration and map training return LOC_E_UNSUPPORTED. */
+typedef struct {
+  int levels, log2_table, n_min, n_max;
+  float bound;
+  int L_dir;
+  const float* tables;
+  const float* mlp;
+  size_t n_mlp;
+  float near_, far_;
+  int n_coarse, n_fine;
+  float alpha, tau;
+  int jitter;
+} loc_grid_desc;
+loc_status loc_init_grid_map(const loc_grid_desc* map, void* hip_stream, loc_ctx** out);
+
 /* Create a context for map `map` bound to `hip_stream` (a hipStream_t, or
  * NULL for the null stream) on the current HIP device.  *out receives the
  * context; on failure *out is NULL. */

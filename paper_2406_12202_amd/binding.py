@@ -23,7 +23,7 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outp
            "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
            "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
            "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-           "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map"]
+           "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map"]
 SMALL_MAP_PARAMS = 15345
 PROPOSAL_PARAMS = 11296
 
@@ -54,6 +54,15 @@ class TrainCfg(ctypes.Structure):
 
 class Level(ctypes.Structure):
     _fields_ = [("inv_R", ctypes.c_int), ("B", ctypes.c_int), ("n_out", ctypes.c_int)]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("log2_table", ctypes.c_int), ("n_min", ctypes.c_int),
+                ("n_max", ctypes.c_int), ("bound", ctypes.c_float), ("L_dir", ctypes.c_int),
+                ("tables", ctypes.POINTER(ctypes.c_float)), ("mlp", ctypes.POINTER(ctypes.c_float)),
+                ("n_mlp", ctypes.c_size_t), ("near_", ctypes.c_float), ("far_", ctypes.c_float),
+                ("n_coarse", ctypes.c_int), ("n_fine", ctypes.c_int), ("alpha", ctypes.c_float),
+                ("tau", ctypes.c_float), ("jitter", ctypes.c_int)]
 
 
 class Stage(ctypes.Structure):
@@ -125,6 +134,7 @@ def load(path=LIB_PATH):
     lib.loc_set_level_tiles.argtypes = [vp, c_int, c_int, c_int, c_int]
     lib.loc_position_variance.argtypes = [vp, vp, vp, c_int, vp]
     lib.loc_map_grad.argtypes = [vp, vp, vp, vp, c_int, c_u64, c_u64, vp, vp]
+    lib.loc_init_grid_map.argtypes = [ctypes.POINTER(GridDesc), vp, ctypes.POINTER(vp)]
     lib.loc_train_map.argtypes = [vp, vp, vp, vp, c_int, ctypes.POINTER(TrainCfg), c_u64, vp]
     lib.loc_get_map.argtypes = [vp, vp, ctypes.c_size_t]
     lib.loc_render_image.argtypes = [vp, ctypes.POINTER(Camera), c_int, vp, c_u64, c_u64, vp, vp]
@@ -137,7 +147,7 @@ def load(path=LIB_PATH):
               "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
               "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
               "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-              "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map"):
+              "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -176,9 +186,26 @@ class Context:
         self.lib = load()
         self.spec = dict(spec)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        d, self._p = map_desc(spec, params, precision)
         h = ctypes.c_void_p()
-        st = self.lib.loc_init_map(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if spec.get("map_type") == "grid":
+            # params = (tables, mlp) of a multi-resolution grid map (float32 only)
+            import numpy as np
+            if precision != "fp32":
+                raise ValueError("the grid map runs in fp32")
+            tab = np.ascontiguousarray(params[0], dtype=np.float32).ravel()
+            mlp = np.ascontiguousarray(params[1], dtype=np.float32).ravel()
+            self._p = (tab, mlp)
+            d = GridDesc(levels=int(spec["levels"]), log2_table=int(spec["log2_table"]), n_min=int(spec["n_min"]),
+                         n_max=int(spec["n_max"]), bound=float(spec["bound"]), L_dir=int(spec["L_dir"]),
+                         tables=tab.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                         mlp=mlp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_mlp=mlp.size,
+                         near_=float(spec["near"]), far_=float(spec["far"]), n_coarse=int(spec["n_coarse"]),
+                         n_fine=int(spec["n_fine"]), alpha=float(spec["alpha"]), tau=float(spec["tau"]),
+                         jitter=int(spec["jitter"]))
+            st = self.lib.loc_init_grid_map(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        else:
+            d, self._p = map_desc(spec, params, precision)
+            st = self.lib.loc_init_map(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != LOC_OK:
             raise LocError(st, "loc_init_map: %s" % self.lib.loc_status_str(st).decode())
         self.h = h

@@ -15,7 +15,7 @@ OUT = os.path.join(PKG, "libfastloc.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["runtime.cpp", "mlp_f32.hip", "mlp_bf16.hip", "mlp_fp8.hip", "render.hip", "filter.hip", "proposal.hip", "levels.hip",
-           "train_map.hip"]
+           "train_map.hip", "grid_map.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # no packed FP32 instructions in device code

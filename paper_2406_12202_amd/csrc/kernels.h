@@ -5,7 +5,7 @@
 
 namespace fl {
 
-enum MapKind { kMapSmall = 0, kMapNerf = 1 };
+enum MapKind { kMapSmall = 0, kMapNerf = 1, kMapGrid = 2 };
 
 // map evaluation over n_samples = n_rays * spr samples laid out [ray][k]
 struct MlpArgs {
@@ -143,6 +143,20 @@ struct TrainArgs {
   float lr, beta1, beta2, eps;
 };
 hipError_t launch_prop_grad(const TrainArgs& a, hipStream_t st);
+// multi-resolution grid map (levels 4, 8 or 16; direction bands <= 4)
+constexpr int kGridMaxLevels = 16;
+constexpr int kGridMaxDirBands = 4;
+struct GridDev {
+  const uint32_t* tables;  // levels x 2^log2_table entries: two half-precision features (low, high)
+  const float* mlp;        // tiny MLP, flat canonical order
+  int n_mlp;
+  int levels, log2_table, in_d;
+  uint32_t dense_mask;     // bit l: level l indexes its vertices densely
+  int res[kGridMaxLevels];
+  float bound;
+};
+hipError_t launch_grid_map(const GridDev& g, const MlpArgs& a, hipStream_t st);
+
 // training of the 4x64 map with the photometric loss (Eq. 2)
 constexpr int kSmallMapParams = 15345;
 struct MapTrainArgs {

@@ -58,6 +58,11 @@ struct loc_ctx {
   std::vector<float> params_host;
   void* wunits = nullptr;
   float* heads_f8 = nullptr;
+  // multi-resolution grid map: tables and tiny MLP on the device
+  GridDev grid{};
+  double bytes_per_sample = 20.0;   // algorithmic bytes of one map evaluation (grid: its table reads)
+  uint32_t* grid_tab = nullptr;
+  float* grid_mlp = nullptr;
   bool f8_ready = false;
   int f8_ew[12] = {}, f8_ea[12] = {};
   float f8_amax[12] = {};
@@ -408,6 +413,7 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
 }
 
 hipError_t mlp_launch(loc_ctx* c, const MlpArgs& a) {
+  if (c->kind == kMapGrid) return launch_grid_map(c->grid, a, c->stream);
   if (a.n_samples2 > 0 && c->desc.precision == LOC_FP32) return hipErrorInvalidValue;   // one set per FP32 launch
   if (c->desc.precision == LOC_FP8_E4M3) {
     MlpArgs b = a;
@@ -568,7 +574,7 @@ loc_status map_samples(loc_ctx* c, long nr, int B, uint64_t seed, uint64_t iter)
   // with proposal-placed fine samples (which do not depend on the coarse
   // render) the MFMA paths evaluate coarse and fine samples in one launch
   const bool merged = Sf > 0 && c->fine_mode == 1 && d.precision != LOC_FP32;
-  if (!merged && (s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, 20.0 * ma.n_samples + 32.0 * nr,
+  if (!merged && (s = timed(c, K_MLP_COARSE, fl_sample * ma.n_samples, c->bytes_per_sample * ma.n_samples + 32.0 * nr,
                             [&] { return mlp_launch(c, ma); })))
     return s;
 
@@ -614,7 +620,7 @@ loc_status map_samples(loc_ctx* c, long nr, int B, uint64_t seed, uint64_t iter)
       mb.n_samples2 = nr * Sf;
       mb.spr2 = Sf;
       const double n_all = (double)(ma.n_samples + mb.n_samples2);
-      if ((s = timed(c, K_MLP_BOTH, fl_sample * n_all, 20.0 * n_all + 4.0 * mb.n_samples2 + 32.0 * nr,
+      if ((s = timed(c, K_MLP_BOTH, fl_sample * n_all, c->bytes_per_sample * n_all + 4.0 * mb.n_samples2 + 32.0 * nr,
                      [&] { return mlp_launch(c, mb); })))
         return s;
     } else {
@@ -624,7 +630,7 @@ loc_status map_samples(loc_ctx* c, long nr, int B, uint64_t seed, uint64_t iter)
       mf.out = c->out_f.p;
       mf.n_samples = nr * Sf;
       mf.spr = Sf;
-      if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, 20.0 * mf.n_samples + 32.0 * nr,
+      if ((s = timed(c, K_MLP_FINE, fl_sample * mf.n_samples, c->bytes_per_sample * mf.n_samples + 32.0 * nr,
                      [&] { return mlp_launch(c, mf); })))
         return s;
     }
@@ -724,6 +730,8 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->heads_b);
   hipFree(c->wunits);
   hipFree(c->heads_f8);
+  hipFree(c->grid_tab);
+  hipFree(c->grid_mlp);
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
@@ -2023,6 +2031,83 @@ loc_status loc_get_map(loc_ctx* c, float* params, size_t n) {
   if (!params || n != c->params_host.size()) return fail(c, LOC_E_ARG, "expected %zu floats", c->params_host.size());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   std::memcpy(params, c->params_host.data(), 4 * n);
+  return LOC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx** out) {
+  if (!out) return LOC_E_ARG;
+  *out = nullptr;
+  if (!g || !g->tables || !g->mlp) return LOC_E_ARG;
+  if (g->levels != 4 && g->levels != 8 && g->levels != 16) return LOC_E_UNSUPPORTED;
+  if (g->L_dir != 2 && g->L_dir != 4) return LOC_E_UNSUPPORTED;
+  if (g->log2_table < 10 || g->log2_table > 24 || g->n_min < 2 || g->n_max < g->n_min || g->n_max > (1 << 16) ||
+      !(g->bound > 0.0f))
+    return LOC_E_ARG;
+  if (!(g->near_ >= 0.0f && g->far_ > g->near_)) return LOC_E_ARG;
+  if (g->n_coarse < 1 || g->n_coarse > 256 || g->n_fine < 0 || g->n_fine > 256) return LOC_E_ARG;
+  if (!(g->alpha > 0.0f && g->alpha < 0.5f) || !(g->tau > 0.0f)) return LOC_E_ARG;
+  const int L = g->levels, in_d = 3 + 6 * g->L_dir;
+  const long n_mlp = 64L * 2 * L + 64 + 16L * 64 + 16 + 64L * (16 + in_d) + 64 + 3L * 64 + 3;
+  if ((long)g->n_mlp != n_mlp) return LOC_E_ARG;
+  loc_ctx* c = new (std::nothrow) loc_ctx();
+  if (!c) return LOC_E_OOM;
+  c->desc = loc_map_desc{};
+  c->desc.precision = LOC_FP32;
+  c->desc.near_ = g->near_;
+  c->desc.far_ = g->far_;
+  c->desc.n_coarse = g->n_coarse;
+  c->desc.n_fine = g->n_fine;
+  c->desc.alpha = g->alpha;
+  c->desc.tau = g->tau;
+  c->desc.jitter = g->jitter;
+  c->kind = kMapGrid;
+  c->macs = n_mlp - (64 + 16 + 64 + 3);
+  c->bytes_per_sample = 8.0 * 4.0 * L + 20.0;   // 8 corners x one word (two half features) per level, sample out
+  c->stream = (hipStream_t)hip_stream;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&c->device) == hipSuccess && hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+      c->n_cu = prop.multiProcessorCount;
+  }
+  // resolutions N_l = floor(N_min b^l + 1e-6), b = exp((ln N_max - ln N_min) / (L - 1))
+  GridDev& d = c->grid;
+  d.levels = L;
+  d.log2_table = g->log2_table;
+  d.in_d = in_d;
+  d.n_mlp = (int)n_mlp;
+  d.bound = g->bound;
+  d.dense_mask = 0;
+  const double b = L > 1 ? std::exp((std::log((double)g->n_max) - std::log((double)g->n_min)) / (L - 1)) : 1.0;
+  for (int l = 0; l < L; ++l) {
+    const long N = (long)std::floor((double)g->n_min * std::pow(b, l) + 1e-6);
+    d.res[l] = (int)N;
+    if ((N + 1) * (N + 1) * (N + 1) <= (1L << g->log2_table)) d.dense_mask |= 1u << l;
+  }
+  // tables rounded to half precision (nearest even), one 32-bit word per entry
+  const size_t n_tab = (size_t)L << g->log2_table;
+  std::vector<uint32_t> H(n_tab);
+  for (size_t i = 0; i < n_tab; ++i) {
+    const _Float16 a = (_Float16)g->tables[2 * i], b = (_Float16)g->tables[2 * i + 1];
+    H[i] = (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+  bool ok = hipMalloc(&c->flags, sizeof(int)) == hipSuccess && hipMalloc(&c->grid_tab, n_tab * 4) == hipSuccess &&
+            hipMalloc(&c->grid_mlp, n_mlp * 4) == hipSuccess &&
+            hipMemcpy(c->grid_tab, H.data(), n_tab * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->grid_mlp, g->mlp, n_mlp * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) == hipSuccess &&
+            hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    loc_destroy(c);
+    return LOC_E_HIP;
+  }
+  d.tables = c->grid_tab;
+  d.mlp = c->grid_mlp;
+  *out = c;
   return LOC_OK;
 }
 

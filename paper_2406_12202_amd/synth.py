@@ -429,12 +429,13 @@ def grid_spec(n_coarse=64, n_fine=128, **over):
 
 
 def grid_params(s, seed, feature_scale=0.5):
-    """Seeded grid tables (L x T x 2 float32, N(0, feature_scale^2)) and tiny-MLP
+    """Seeded grid tables (L x T x 2 float32, N(0, feature_scale^2) rounded to
+    half-precision values, which the grid map stores exactly) and tiny-MLP
     parameters (He-scaled weights, zero biases; the density output's weights
     x3 and bias -1 so that sigma spans empty and opaque stretches)."""
     rng = np.random.default_rng([seed, 31])
     T = 1 << s["log2_table"]
-    tables = (feature_scale * rng.standard_normal((s["levels"], T, 2))).astype(np.float32)
+    tables = (feature_scale * rng.standard_normal((s["levels"], T, 2))).astype(np.float16).astype(np.float32)
     in_d = 3 + 6 * s["L_dir"]
     parts = []
     for name, o, i in (("W1", 64, 2 * s["levels"]), ("W2", 16, 64), ("W3", 64, 16 + in_d), ("W4", 3, 64)):
