@@ -82,7 +82,6 @@ def test_grid_map_small_tables_dense_hash_and_box_edge(torch_dev, levels, L_dir,
     spec = synth.grid_spec(n_coarse=32, n_fine=0, levels=levels, L_dir=L_dir, log2_table=log2_table, n_min=4,
                            n_max=96, bound=3.0)
     params = synth.grid_params(spec, 2)
-    s_small = synth.spec("small")
     cam = synth.camera("small")
     poses = synth.particles("small", 2, N=12)
     img = synth.observation("small", 2)
@@ -91,7 +90,6 @@ def test_grid_map_small_tables_dense_hash_and_box_edge(torch_dev, levels, L_dir,
     o = mcl.update_particles(spec, params, img, cam, 2, 16, poses, None, 0.0, 0.0, 7, 1)
     _compare(g, o, list(range(12)))
     assert np.all(g["A"] >= 0.0) and np.all(g["A"] <= 1.0)
-    del s_small
     ctx.close()
 
 
@@ -124,3 +122,65 @@ def test_grid_map_rejects_unsupported(torch_dev):
     spec = synth.grid_spec(L_dir=3)
     with pytest.raises(LocError):
         _ctx(spec, synth.grid_params(spec, 4))
+
+
+def test_grid_map_with_proposal_placement(torch_dev):
+    """Proposal-placed fine samples (a seeded, untrained proposal network) on
+    the grid map; all particles of a small workload checked."""
+    torch = torch_dev
+    spec = synth.grid_spec(n_coarse=32, n_fine=16, levels=8, log2_table=14, n_min=8, n_max=256)
+    params = synth.grid_params(spec, 5)
+    prop = synth.proposal_params(5)
+    cam = synth.camera("small")
+    poses = synth.particles("small", 5, N=6)
+    img = synth.observation("small", 5)
+    ctx = _ctx(spec, params)
+    ctx.loc_set_proposal(prop)
+    ctx.loc_set_fine_mode(1)
+    g = _run(torch, ctx, img, cam, 1, 12, poses, 3, 4)
+    o = mcl.update_particles(spec, params, img, cam, 1, 12, poses, None, 0.0, 0.0, 3, 4, proposal=prop)
+    _compare(g, o, list(range(6)))
+    ctx.close()
+
+
+def test_grid_map_in_the_localisation_loop(torch_dev):
+    """Two iterations of the localisation loop on a small grid map: the loop's
+    trace against oracle updates of the same sets (weights), indices exact."""
+    torch = torch_dev
+    spec = synth.grid_spec(n_coarse=24, n_fine=0, levels=4, log2_table=12, n_min=4, n_max=64, L_dir=4)
+    params = synth.grid_params(spec, 6)
+    cam = synth.camera("small")
+    poses = synth.particles("small", 6, N=10)
+    img = synth.observation("small", 6)
+    dev = torch.device("cuda", 0)
+    ctx = _ctx(spec, params)
+    stages = [(2, 8, 10, 1e9), (1, 8, 8, 0.0)]
+    out = ctx.loc_localize(torch.as_tensor(img, device=dev), cam, stages, 2,
+                           torch.as_tensor(poses, device=dev).contiguous(), seed=7, trace_capacity=20)
+    tw = out["trace"]["weight"].cpu().numpy()
+    tp = out["trace"]["pose"].cpu().numpy()
+    ti = out["trace"]["idx"].cpu().numpy()
+    assert [r["stage"] for r in out["steps"]] == [0, 1]
+    o0 = mcl.update_particles(spec, params, img, cam, 2, 8, poses, None, 0.0, 0.0, 7, 0)
+    big = o0["weight"] > 1e-6
+    assert np.all(np.abs(tw[:10] - o0["weight"])[big] <= TOL["W"] * o0["weight"][big])
+    idx0 = mcl.resample(tw[:10], 8, 7, 0)
+    assert np.array_equal(ti[:8], np.asarray(idx0, np.int32))
+    X1 = tp[:10][np.asarray(idx0)]
+    o1 = mcl.update_particles(spec, params, img, cam, 1, 8, X1, None, 0.0, 0.0, 7, 1)
+    big = o1["weight"] > 1e-6
+    assert np.all(np.abs(tw[10:18] - o1["weight"])[big] <= TOL["W"] * o1["weight"][big])
+    ctx.close()
+
+
+def test_grid_map_level_path_is_unsupported(torch_dev):
+    torch = torch_dev
+    from paper_2406_12202_amd.binding import LocError
+    spec = synth.grid_spec(n_coarse=32, n_fine=0, levels=4, log2_table=12, n_min=4, n_max=64)
+    ctx = _ctx(spec, synth.grid_params(spec, 7))
+    dev = torch.device("cuda", 0)
+    cam = synth.camera("small")
+    with pytest.raises(LocError):
+        ctx.loc_update_levels(torch.as_tensor(synth.observation("small", 7), device=dev), cam, [(1, 4, 4)],
+                              torch.as_tensor(synth.particles("small", 7, N=4), device=dev).contiguous())
+    ctx.close()
