@@ -4,7 +4,8 @@
 //
 // Network: x = [gamma_6(o), gamma_6(d)] (78), h1 = relu(W1 x + b1) (64),
 // h2 = relu(W2 h1 + b2) (64), z = W3 h2 + b3 (32), p = softmax(z); parameters
-// in the flat order W1, b1, W2, b2, W3, b3 (row-major).  One wave handles one
+// in the flat order W1, b1, W2, b2, W3, b3 (row-major).  Inference runs on the
+// matrix cores, 32 rays per wave (layout below).  Training has one wave per
 // ray at a time with hidden unit j on lane j; the vector a layer reads is
 // broadcast lane by lane with v_readlane, so no LDS traffic is needed for
 // activations.
@@ -48,79 +49,182 @@ __device__ __forceinline__ float softmax32(float z, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// inference + placement: one wave per ray, weight rows in registers
-__global__ __launch_bounds__(256) void k_proposal_fine(const ProposalArgs a) {
-  const int lane = threadIdx.x & 63;
+// inference + placement on the matrix cores (v_mfma_f32_32x32x2_f32, float32
+// products and sums).  A wave takes a tile of 32 rays: the layers are computed
+// transposed, out^T = W in^T, with the rays as the 32 columns.  In an
+// instruction lane l = 32 h + n supplies column n and k-row h of the input; the
+// accumulator holds, in lane (n, h) and register v, output row
+// 8 (v / 4) + 4 h + v % 4 of column n.  Register v of accumulator tile b is
+// then used directly as the input of k-step 16 b + v of the next layer, with
+// the matching weights: the contraction index is permuted, not the data.
+// Layer 1's k-step kb pairs feature kb of gamma_6(o) (half 0) with feature kb
+// of gamma_6(d) (half 1).  The weights, in that operand order, and the biases
+// are staged in LDS once per workgroup.
+constexpr int kPropWaves = 4;
+constexpr int PK1 = PENC;   // 39 k-steps of layer 1
+constexpr int PW1 = 2 * PK1 * 64, PW2 = 2 * 32 * 64, PW3 = 32 * 64;
+typedef float pf32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int prop_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+__device__ __forceinline__ void prop_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const ProposalArgs a) {
+  __shared__ float s_w[PW1 + PW2 + PW3];
+  __shared__ float s_b[PH + PH + PB];
+  __shared__ float s_c[kPropWaves][32][33];   // per ray: inclusive prefix of the bin masses
   const float* __restrict__ P = a.params;
-  float w1[PIN], w2[PH], w3[PH];
-#pragma unroll
-  for (int k = 0; k < PIN; ++k) w1[k] = P[P_W1 + lane * PIN + k];
-#pragma unroll
-  for (int k = 0; k < PH; ++k) w2[k] = P[P_W2 + lane * PH + k];
-  const int l3 = lane < PB ? lane : 0;
-#pragma unroll
-  for (int k = 0; k < PH; ++k) w3[k] = P[P_W3 + l3 * PH + k];
-  const float b1 = P[P_B1 + lane], b2 = P[P_B2 + lane], b3 = P[P_B3 + l3];
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int ray = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ray < a.n_rays; ray += waves) {
-    const float4 o = a.ray_o[ray], d = a.ray_d[ray];
-    const float x0 = prop_feature(o, d, lane);
-    const float x1v = lane + 64 < PIN ? prop_feature(o, d, lane + 64) : 0.0f;
-    float s1 = b1;
-#pragma unroll
-    for (int k = 0; k < PIN; ++k) s1 = fmaf(w1[k], k < 64 ? bcast(x0, k) : bcast(x1v, k - 64), s1);
-    const float h1 = fmaxf(s1, 0.0f);
-    float s2 = b2;
-#pragma unroll
-    for (int k = 0; k < PH; ++k) s2 = fmaf(w2[k], bcast(h1, k), s2);
-    const float h2 = fmaxf(s2, 0.0f);
-    float z = b3;
-#pragma unroll
-    for (int k = 0; k < PH; ++k) z = fmaf(w3[k], bcast(h2, k), z);
-    const float p = softmax32(z, lane);
-    if (a.hist && lane < PB) a.hist[(long)ray * PB + lane] = p;
-    if (a.Sf <= 0) continue;
-    // pdf 0.99 p + 0.01 / 32 on 32 equal bins; inclusive prefix over lanes 0..31
-    const float mass = lane < PB ? 0.99f * p + 0.01f / PB : 0.0f;
-    float c = mass;
-#pragma unroll
-    for (int off = 1; off < PB; off <<= 1) {
-      const float u = __shfl_up(c, off, 64);
-      if ((lane & 31) >= off) c += u;
+  for (int e = threadIdx.x; e < PW1 + PW2 + PW3; e += blockDim.x) {
+    const int ln = e & 63, n = ln & 31, h = ln >> 5, blk = e >> 6;
+    float v;
+    if (blk < 2 * PK1) {                   // layer 1: block mt * 39 + kb
+      const int mt = blk / PK1, kb = blk - mt * PK1;
+      v = P[P_W1 + (mt * 32 + n) * PIN + (h ? PENC + kb : kb)];
+    } else if (blk < 2 * PK1 + 64) {      // layer 2: block mt * 32 + s, s = 16 b + r
+      const int q = blk - 2 * PK1, mt = q >> 5, st = q & 31;
+      v = P[P_W2 + (mt * 32 + n) * PH + 32 * (st >> 4) + prop_row(st & 15, h)];
+    } else {                               // layer 3: block s
+      const int st = blk - 2 * PK1 - 64;
+      v = P[P_W3 + n * PH + 32 * (st >> 4) + prop_row(st & 15, h)];
     }
-    const float total = __shfl(c, PB - 1, 64);
+    s_w[e] = v;
+  }
+  for (int e = threadIdx.x; e < PH + PH + PB; e += blockDim.x)
+    s_b[e] = e < PH ? P[P_B1 + e] : (e < 2 * PH ? P[P_B2 + e - PH] : P[P_B3 + e - 2 * PH]);
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 31, h = lane >> 5;
+  const float* w1 = s_w;
+  const float* w2 = s_w + PW1;
+  const float* w3 = s_w + PW1 + PW2;
+  float (*c_ray)[33] = s_c[wv];
+  const int tiles = (a.n_rays + 31) / 32;
+  for (int tile = blockIdx.x * kPropWaves + wv; tile < tiles; tile += gridDim.x * kPropWaves) {
+    const int ray = tile * 32 + n;
+    const bool valid = ray < a.n_rays;
+    const float4 v = (h ? a.ray_d : a.ray_o)[valid ? ray : a.n_rays - 1];
+    // gamma_6 of o (half 0) or d (half 1), canonical order
+    float x[PK1];
+    x[0] = v.x; x[1] = v.y; x[2] = v.z;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const float vc[3] = {v.x, v.y, v.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float sn, cs;
+        sincospif(ldexpf(vc[c], l), &sn, &cs);
+        x[3 + 6 * l + c] = sn;
+        x[3 + 6 * l + 3 + c] = cs;
+      }
+    }
+    // layer 1: 64 hidden rows in two tiles
+    pf32x16 h1[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h1[mt][r] = s_b[32 * mt + prop_row(r, h)];
+#pragma unroll
+    for (int kb = 0; kb < PK1; ++kb)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        h1[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[(mt * PK1 + kb) * 64 + lane], x[kb], h1[mt], 0, 0, 0);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h1[mt][r] = fmaxf(h1[mt][r], 0.0f);
+    // layer 2
+    pf32x16 h2[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h2[mt][r] = s_b[PH + 32 * mt + prop_row(r, h)];
+#pragma unroll
+    for (int st = 0; st < 32; ++st)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+        h2[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w2[(mt * 32 + st) * 64 + lane], h1[st >> 4][st & 15], h2[mt],
+                                                      0, 0, 0);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h2[mt][r] = fmaxf(h2[mt][r], 0.0f);
+    // layer 3: 32 logits; two accumulators over alternating k-steps (summed
+    // once at the end) so that consecutive instructions are independent
+    pf32x16 z0, z1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { z0[r] = s_b[2 * PH + prop_row(r, h)]; z1[r] = 0.0f; }
+#pragma unroll
+    for (int st = 0; st < 32; st += 2) {
+      z0 = __builtin_amdgcn_mfma_f32_32x32x2f32(w3[st * 64 + lane], h2[st >> 4][st & 15], z0, 0, 0, 0);
+      z1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w3[(st + 1) * 64 + lane], h2[(st + 1) >> 4][(st + 1) & 15], z1, 0,
+                                                0, 0);
+    }
+    // softmax over the 32 logits of column n (16 in each lane half)
+    float m = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { z0[r] += z1[r]; m = fmaxf(m, z0[r]); }
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    float sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { z0[r] = expf(z0[r] - m); sum += z0[r]; }
+    sum += __shfl_xor(sum, 32, 64);
+    const float inv_sum = 1.0f / sum;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z0[r] *= inv_sum;
+    if (a.hist && valid) {
+      float4* hp = reinterpret_cast<float4*>(a.hist + (long)ray * PB);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hp[2 * q + h] = make_float4(z0[4 * q], z0[4 * q + 1], z0[4 * q + 2], z0[4 * q + 3]);
+    }
+    if (a.Sf <= 0) continue;
+    // pdf 0.99 p + 0.01 / 32 on 32 equal bins: masses to LDS, then the
+    // inclusive prefix of each ray's bins in bin order (lane half 0)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c_ray[n][prop_row(r, h)] = 0.99f * z0[r] + 0.01f / PB;
+    prop_wave_sync();
+    if (h == 0) {
+      float c = 0.0f;
+      for (int b = 0; b < PB; ++b) { c += c_ray[n][b]; c_ray[n][b] = c; }
+    }
+    prop_wave_sync();
+    const float total = c_ray[n][PB - 1];
     const int i = ray / a.B, j = ray - (ray / a.B) * a.B;
     const float width = (a.far_ - a.near_) / PB;
-    // uniform control flow: every lane runs every round so that the
-    // cross-lane reads below always address active lanes
-    for (int m0 = 0; m0 < a.Sf; m0 += 64) {
-      const int m = m0 + lane;
-      const int mm = m < a.Sf ? m : a.Sf - 1;
-      float xi = 0.5f;
-      if (a.jitter) xi = unit24(pick(draw(a.seed, a.iter, kStreamJitFine, i, j, mm >> 2), mm & 3));
-      const float target = ((float)mm + xi) / (float)a.Sf * total;
-      // largest bin b with exclusive prefix c[b - 1] <= target (fixed 5 steps)
-      int b = 0;
+    // samples 4 q .. 4 q + 3 of the ray share one draw; quads alternate
+    // between the lane halves
+    for (int q = h; valid && 4 * q < a.Sf; q += 2) {
+      u32x4 rnd = {0u, 0u, 0u, 0u};
+      if (a.jitter) rnd = draw(a.seed, a.iter, kStreamJitFine, i, j, q);
 #pragma unroll
-      for (int step = 16; step > 0; step >>= 1) {
-        const float ce = __shfl(c, b + step - 1, 64);
-        if (ce <= target) b += step;
+      for (int e = 0; e < 4; ++e) {
+        const int mm = 4 * q + e;
+        if (mm >= a.Sf) break;
+        const float xi = a.jitter ? unit24(pick(rnd, e)) : 0.5f;
+        const float target = ((float)mm + xi) / (float)a.Sf * total;
+        // largest bin b with exclusive prefix c[b - 1] <= target (fixed 5 steps)
+        int b = 0;
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1)
+          if (c_ray[n][b + step - 1] <= target) b += step;
+        const float c0 = b > 0 ? c_ray[n][b - 1] : 0.0f;
+        float frac = (target - c0) / (c_ray[n][b] - c0);
+        frac = fminf(fmaxf(frac, 0.0f), 1.0f);
+        a.t_fine[(long)ray * a.Sf + mm] = fminf(a.near_ + ((float)b + frac) * width, a.near_ + (b + 1) * width);
       }
-      const float cb = __shfl(c, b > 0 ? b - 1 : 0, 64);
-      const float c0 = b > 0 ? cb : 0.0f;
-      const float mb = __shfl(mass, b, 64);
-      float frac = (target - c0) / mb;
-      frac = fminf(fmaxf(frac, 0.0f), 1.0f);
-      if (m < a.Sf)
-        a.t_fine[(long)ray * a.Sf + m] = fminf(a.near_ + ((float)b + frac) * width, a.near_ + (b + 1) * width);
     }
+    prop_wave_sync();   // the next tile overwrites c_ray
   }
 }
 
 hipError_t launch_proposal_fine(const ProposalArgs& a, hipStream_t st) {
   if (a.n_rays <= 0) return hipSuccess;
-  const int waves = (a.n_rays + 3) / 4 < 2048 ? (a.n_rays + 3) / 4 : 2048;
-  hipLaunchKernelGGL(k_proposal_fine, dim3((waves + 3) / 4), dim3(256), 0, st, a);
+  const long tiles = ((long)a.n_rays + 31) / 32;
+  const long want = (tiles + kPropWaves - 1) / kPropWaves;
+  const long blocks = want < 2048 ? want : 2048;
+  hipLaunchKernelGGL(k_proposal_fine, dim3((unsigned)blocks), dim3(64 * kPropWaves), 0, st, a);
   return hipGetLastError();
 }
 

@@ -131,145 +131,174 @@ hipError_t launch_fine(const FineArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// compositing (Eq. 1), Eq. 5 depths, F and the Eq. 6 score.  One workgroup per
-// particle, one wave per ray at a time.  The coarse and fine sample lists
-// (each sorted) are merged by rank in LDS (ties: coarse first); each lane then
-// owns a contiguous run of merged samples; transmittance is a wave scan of
-// tau in log space.
-constexpr int kMaxS = 512;   // Sc + Sf
+// compositing (Eq. 1), Eq. 5 depths and F per ray, then the Eq. 6 score per
+// particle.  One wave per ray over the whole grid (kCompWaves rays per
+// workgroup, independent of each other).  The coarse and fine sample lists
+// (each sorted) are merged by rank in the wave's LDS (ties: coarse first);
+// each lane then owns a contiguous run of merged samples; transmittance is a
+// wave scan of tau in log space.  A wave's LDS is sized from S = Sc + Sf at
+// launch (32 S bytes), so short lists leave room for many rays in flight.
 constexpr int kCompWaves = 4;
 
-__global__ __launch_bounds__(256) void k_composite(const CompositeArgs a) {
-  __shared__ float s_tm[kCompWaves][kMaxS];     // merged t
-  __shared__ float s_sg[kCompWaves][kMaxS];     // merged sigma
-  __shared__ float s_lt[kCompWaves][kMaxS];     // log T at each merged sample
-  __shared__ float4 s_rgb[kCompWaves][kMaxS];   // merged colour (rgb, pad)
-  __shared__ float s_tc[kCompWaves][256];       // coarse t (sorted) for ranking
-  __shared__ float s_tf[kCompWaves][256];       // fine t (sorted)
-  __shared__ float s_ef[1024];
-  __shared__ float s_f[1024];
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kCompWaves) void k_composite(const CompositeArgs a) {
+  extern __shared__ float4 s_dyn[];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x;
   const int Sc = a.Sc, Sf = a.Sf, S = Sc + Sf;
+  float4* s_rgb = s_dyn + (long)wv * 2 * S;    // merged colour (rgb, pad)
+  float* s_tm = (float*)(s_rgb + S);           // merged t
+  float* s_sg = s_tm + S;                      // merged sigma
+  float* s_lt = s_sg + S;                      // log T at each merged sample
+  float* s_tc = s_lt + S;                      // coarse t (sorted) for ranking
+  float* s_tf = s_tc + Sc;                     // fine t (sorted)
+  const long ray = (long)blockIdx.x * kCompWaves + wv;
+  if (ray >= a.n_rays) return;                 // whole waves leave; no block barriers follow
   const int cpl = (S + 63) / 64;
-  // every wave runs the same number of rounds so that block barriers match
-  for (int jb = 0; jb < a.B; jb += kCompWaves) {
-    const int j = jb + wv;
-    const bool act = j < a.B && (long)i * a.B + j < a.n_rays;
-    const long ray = (long)i * a.B + (act ? j : 0);
-    // gather and merge
-    if (act) {
-      for (int k = lane; k < Sc; k += 64) s_tc[wv][k] = a.t_coarse[ray * Sc + k];
-      for (int m = lane; m < Sf; m += 64) s_tf[wv][m] = a.t_fine[ray * Sf + m];
-    }
-    __syncthreads();
-    for (int k = lane; act && k < Sc; k += 64) {
-      const float tk = s_tc[wv][k];
-      int lo = 0, hi = Sf;                 // count of fine < tk
-      while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tf[wv][mid] < tk) lo = mid + 1; else hi = mid; }
-      const int pos = k + lo;
-      const float4 q = a.out_coarse[ray * Sc + k];
-      s_tm[wv][pos] = tk; s_sg[wv][pos] = q.x; s_rgb[wv][pos] = make_float4(q.y, q.z, q.w, 0.0f);
-    }
-    for (int m = lane; act && m < Sf; m += 64) {
-      const float tm = s_tf[wv][m];
-      int lo = 0, hi = Sc;                 // count of coarse <= tm
-      while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tc[wv][mid] <= tm) lo = mid + 1; else hi = mid; }
-      const int pos = m + lo;
-      const float4 q = a.out_fine[ray * Sf + m];
-      s_tm[wv][pos] = tm; s_sg[wv][pos] = q.x; s_rgb[wv][pos] = make_float4(q.y, q.z, q.w, 0.0f);
-    }
-    __syncthreads();
-    // per-lane run [lane * cpl, lane * cpl + cpl)
-    const int k0 = lane * cpl;
-    float lsum = 0.0f;
-    for (int e = 0; e < cpl; ++e) {
-      const int k = k0 + e;
-      if (act && k < S) {
-        const float tn = (k + 1 < S) ? s_tm[wv][k + 1] : a.far_;
-        lsum += s_sg[wv][k] * (tn - s_tm[wv][k]);
-      }
-    }
-    const float incl = wave_incl_scan(lsum, lane);
-    const float log_t_end = -__shfl(incl, 63, 64);
-    float run = -(incl - lsum);
-    float cr = 0.0f, cg = 0.0f, cb = 0.0f, acc = 0.0f;
-    int ktr = 1 << 30, kop = 1 << 30;
-    for (int e = 0; e < cpl; ++e) {
-      const int k = k0 + e;
-      if (act && k < S) {
-        const float tn = (k + 1 < S) ? s_tm[wv][k + 1] : a.far_;
-        const float tau = s_sg[wv][k] * (tn - s_tm[wv][k]);
-        const float w = expf(run) * -expm1f(-tau);
-        s_lt[wv][k] = run;
-        const float4 c = s_rgb[wv][k];
-        cr = fmaf(w, c.x, cr); cg = fmaf(w, c.y, cg); cb = fmaf(w, c.z, cb);
-        acc += w;
-        run -= tau;
-        if (run <= a.log_trans && k < ktr) ktr = k;
-        if (run < a.log_opq && k < kop) kop = k;
-      }
-    }
-    cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb); acc = wave_sum(acc);
-    ktr = wave_min_int(ktr);
-    kop = wave_min_int(kop);
-    __syncthreads();
-    if (a.hist && act && lane < 32) {
-      // teacher histogram: bin b collects the weights of samples with depth in
-      // [e_b, e_{b+1}); they are consecutive in the sorted list, and their sum
-      // telescopes to T(first in bin) - T(first in next bin)
-      const float width = (a.far_ - a.near_) / 32.0f;
-      int kb[2];
+  // gather (depths and map outputs in flight together), then merge
+  constexpr int kPer = 4;              // Sc, Sf <= 256 = 4 x 64
+  float tc[kPer], tf[kPer];
+  float4 qc[kPer], qf[kPer];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const float edge = a.near_ + (float)(lane + e) * width;
-        int lo = 0, hi = S;                // first merged index with t >= edge
-        if (lane + e == 32) lo = S;
-        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tm[wv][mid] < edge) lo = mid + 1; else hi = mid; }
-        kb[e] = lo;
-      }
-      const float t0 = kb[0] < S ? expf(s_lt[wv][kb[0]]) : expf(log_t_end);
-      const float t1 = kb[1] < S ? expf(s_lt[wv][kb[1]]) : expf(log_t_end);
-      const float den = -expm1f(log_t_end);
-      a.hist[ray * 32 + lane] = acc < 1e-3f ? 1.0f / 32.0f : (t0 - t1) / den;
-    }
-    if (act && lane == 0) {
-      float F = a.tau;
-      if (ktr < S) {
-        const float zt = s_tm[wv][ktr] + (s_lt[wv][ktr] - a.log_trans) / s_sg[wv][ktr];
-        const float zo = (kop < S) ? s_tm[wv][kop] + (s_lt[wv][kop] - a.log_opq) / s_sg[wv][kop] : a.far_;
-        F = fmaxf(zo - zt, a.tau);
-      }
-      float E = 0.0f;
-      if (a.obs) {
-        const float4 ob = a.obs[ray];
-        const float er = ob.x - cr, eg = ob.y - cg, eb = ob.z - cb;
-        E = er * er + eg * eg + eb * eb;
-      }
-      a.ray_rgba[ray] = make_float4(cr, cg, cb, acc);
-      a.ray_fe[ray] = make_float2(F, E);
-      s_ef[j] = E * F;
-      s_f[j] = F;
-    }
-    __syncthreads();
+  for (int e = 0; e < kPer; ++e) {
+    const int k = lane + 64 * e;
+    if (k < Sc) { tc[e] = a.t_coarse[ray * Sc + k]; qc[e] = a.out_coarse[ray * Sc + k]; }
+    if (k < Sf) { tf[e] = a.t_fine[ray * Sf + k]; qf[e] = a.out_fine[ray * Sf + k]; }
   }
-  __syncthreads();
-  if (wv == 0 && a.loglik) {
-    // lanes 0 .. G-1 form the particle's group; the rest add nothing
-    const int G = particle_group(a.B);
-    double S_i = 0.0, Fs = 0.0;
-    particle_sums([&](int j, float& ef, float& f) { ef = s_ef[j]; f = s_f[j]; }, lane < G ? a.B : 0, G, lane,
-                  S_i, Fs);
-    if (lane == 0) {
-      const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
-      a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
-      if (a.uncert) a.uncert[i] = (float)(Fs / a.B);
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int k = lane + 64 * e;
+    if (k < Sc) s_tc[k] = tc[e];
+    if (k < Sf) s_tf[k] = tf[e];
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int k = lane + 64 * e;
+    if (k < Sc) {
+      int lo = 0, hi = Sf;               // count of fine < t
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tf[mid] < tc[e]) lo = mid + 1; else hi = mid; }
+      const int pos = k + lo;
+      s_tm[pos] = tc[e]; s_sg[pos] = qc[e].x; s_rgb[pos] = make_float4(qc[e].y, qc[e].z, qc[e].w, 0.0f);
     }
+    if (k < Sf) {
+      int lo = 0, hi = Sc;               // count of coarse <= t
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tc[mid] <= tf[e]) lo = mid + 1; else hi = mid; }
+      const int pos = k + lo;
+      s_tm[pos] = tf[e]; s_sg[pos] = qf[e].x; s_rgb[pos] = make_float4(qf[e].y, qf[e].z, qf[e].w, 0.0f);
+    }
+  }
+  wave_lds_sync();
+  // per-lane run [lane * cpl, lane * cpl + cpl)
+  const int k0 = lane * cpl;
+  float lsum = 0.0f;
+  for (int e = 0; e < cpl; ++e) {
+    const int k = k0 + e;
+    if (k < S) {
+      const float tn = (k + 1 < S) ? s_tm[k + 1] : a.far_;
+      lsum += s_sg[k] * (tn - s_tm[k]);
+    }
+  }
+  const float incl = wave_incl_scan(lsum, lane);
+  const float log_t_end = -__shfl(incl, 63, 64);
+  float run = -(incl - lsum);
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, acc = 0.0f;
+  int ktr = 1 << 30, kop = 1 << 30;
+  for (int e = 0; e < cpl; ++e) {
+    const int k = k0 + e;
+    if (k < S) {
+      const float tn = (k + 1 < S) ? s_tm[k + 1] : a.far_;
+      const float tau = s_sg[k] * (tn - s_tm[k]);
+      const float w = expf(run) * -expm1f(-tau);
+      s_lt[k] = run;
+      const float4 c = s_rgb[k];
+      cr = fmaf(w, c.x, cr); cg = fmaf(w, c.y, cg); cb = fmaf(w, c.z, cb);
+      acc += w;
+      run -= tau;
+      if (run <= a.log_trans && k < ktr) ktr = k;
+      if (run < a.log_opq && k < kop) kop = k;
+    }
+  }
+  cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb); acc = wave_sum(acc);
+  ktr = wave_min_int(ktr);
+  kop = wave_min_int(kop);
+  wave_lds_sync();
+  if (a.hist && lane < 32) {
+    // teacher histogram: bin b collects the weights of samples with depth in
+    // [e_b, e_{b+1}); they are consecutive in the sorted list, and their sum
+    // telescopes to T(first in bin) - T(first in next bin)
+    const float width = (a.far_ - a.near_) / 32.0f;
+    int kb[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float edge = a.near_ + (float)(lane + e) * width;
+      int lo = 0, hi = S;                // first merged index with t >= edge
+      if (lane + e == 32) lo = S;
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_tm[mid] < edge) lo = mid + 1; else hi = mid; }
+      kb[e] = lo;
+    }
+    const float t0 = kb[0] < S ? expf(s_lt[kb[0]]) : expf(log_t_end);
+    const float t1 = kb[1] < S ? expf(s_lt[kb[1]]) : expf(log_t_end);
+    const float den = -expm1f(log_t_end);
+    a.hist[ray * 32 + lane] = acc < 1e-3f ? 1.0f / 32.0f : (t0 - t1) / den;
+  }
+  if (lane == 0) {
+    float F = a.tau;
+    if (ktr < S) {
+      const float zt = s_tm[ktr] + (s_lt[ktr] - a.log_trans) / s_sg[ktr];
+      const float zo = (kop < S) ? s_tm[kop] + (s_lt[kop] - a.log_opq) / s_sg[kop] : a.far_;
+      F = fmaxf(zo - zt, a.tau);
+    }
+    float E = 0.0f;
+    if (a.obs) {
+      const float4 ob = a.obs[ray];
+      const float er = ob.x - cr, eg = ob.y - cg, eb = ob.z - cb;
+      E = er * er + eg * eg + eb * eb;
+    }
+    a.ray_rgba[ray] = make_float4(cr, cg, cb, acc);
+    a.ray_fe[ray] = make_float2(F, E);
+  }
+}
+
+// Eq. 6 per particle from the per-ray (F, E): G = particle_group(B) lanes per
+// particle, the fixed summation order of particle_sums.
+__global__ __launch_bounds__(256) void k_particle_scores(const CompositeArgs a) {
+  const int G = particle_group(a.B);
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = threadIdx.x & (G - 1);
+  const long i = tid / G;
+  if (i >= a.N) return;   // whole groups leave together
+  double S_i, Fs;
+  particle_sums([&](int j, float& ef, float& f) {
+    const float2 fe = a.ray_fe[i * a.B + j];
+    ef = fe.y * fe.x;
+    f = fe.x;
+  }, a.B, G, g, S_i, Fs);
+  if (g == 0) {
+    const double Sfl = (S_i > 1e-12 || isnan(S_i)) ? S_i : 1e-12;   // NaN stays NaN
+    a.loglik[i] = 4.0 * (log((double)a.B) - log(Sfl));
+    if (a.uncert) a.uncert[i] = (float)(Fs / a.B);
   }
 }
 
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_composite, dim3(a.N), dim3(64 * kCompWaves), 0, st, a);
+  const int S = a.Sc + a.Sf;
+  if (a.Sc < 1 || a.Sc > 256 || a.Sf < 0 || a.Sf > 256) return hipErrorInvalidValue;
+  if (a.loglik && (long)a.N * a.B != a.n_rays) return hipErrorInvalidValue;
+  if (a.n_rays > 0) {
+    const size_t lds = (size_t)kCompWaves * 32 * S;
+    hipLaunchKernelGGL(k_composite, dim3((unsigned)((a.n_rays + kCompWaves - 1) / kCompWaves)),
+                       dim3(64 * kCompWaves), lds, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!a.loglik || a.N <= 0) return hipSuccess;
+  const long threads = (long)a.N * particle_group(a.B);
+  hipLaunchKernelGGL(k_particle_scores, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

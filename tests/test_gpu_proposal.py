@@ -135,14 +135,19 @@ def test_adam_trajectory_matches_oracle(torch_dev):
     assert d.max() <= 1e-3 * lr
 
 
-def test_update_with_proposal_matches_oracle(torch_dev):
-    s, p, cam, poses, img = inputs("nerf", 36, N=4, n_fine=32)
+@pytest.mark.parametrize("N,B,n_fine", [(4, 8, 32), (3, 13, 13)])
+def test_update_with_proposal_matches_oracle(torch_dev, N, B, n_fine):
+    """Proposal-placed fine samples inside the particle update; the second
+    case has a ray count that leaves the last 32-ray tile of the proposal
+    kernel partly empty and a fine count that is not a multiple of the four
+    samples one random draw serves."""
+    s, p, cam, poses, img = inputs("nerf", 36, N=N, n_fine=n_fine)
     theta = synth.proposal_params(8)
     c = ctx(s, p)
     c.loc_set_proposal(theta)
     c.loc_set_fine_mode(1)
-    g = run_gpu(c, img, cam, 1, 8, poses, seed=2, it=3)
-    o = run_oracle(s, p, img, cam, 1, 8, poses, seed=2, it=3, proposal=theta)
+    g = run_gpu(c, img, cam, 1, B, poses, seed=2, it=3)
+    o = run_oracle(s, p, img, cam, 1, B, poses, seed=2, it=3, proposal=theta)
     rC = stats("C", g["C"], o["C"])
     rF = stats("F", g["F"], o["F"])
     rL = stats("loglik", g["loglik"], o["loglik"])
