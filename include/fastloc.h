@@ -392,10 +392,14 @@ enum { LOC_FLAG_DEGENERATE_WEIGHTS = 1, LOC_FLAG_DEGENERATE_RESAMPLE = 2, LOC_FL
 loc_status loc_sync(loc_ctx* ctx, int* flags);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * every launch while enabled.  loc_kernel_stats waits for the stream and
- * fills up to max entries (name, launches, summed milliseconds, summed
- * algorithmic FLOP and HBM bytes of those launches); *n receives the number
- * of kernels.  Enabling clears the counters. */
+ * launches: enable = 1 times every launch, 2 only the map-evaluation launches
+ * (the MLP or grid kernels and the fused level ray kernel), so that a timed
+ * region carries two events per map launch and nothing around the small
+ * kernels; 0 switches timing off; other values are LOC_E_ARG.
+ * loc_kernel_stats waits for the stream and fills up to max entries (name,
+ * launches, summed milliseconds, summed algorithmic FLOP and HBM bytes of
+ * those launches); *n receives the number of kernels.  Any call of
+ * loc_set_profiling clears the counters. */
 typedef struct {
   char name[48];
   long long launches;

@@ -289,7 +289,8 @@ class Context:
         return f.value
 
     def loc_set_profiling(self, enable):
-        self._check(self.lib.loc_set_profiling(self.h, int(bool(enable))), "loc_set_profiling")
+        """0 off, 1 (or True) every launch, 2 map-evaluation launches only."""
+        self._check(self.lib.loc_set_profiling(self.h, int(enable)), "loc_set_profiling")
 
     def loc_kernel_stats(self):
         arr = (KernelStat * 32)()

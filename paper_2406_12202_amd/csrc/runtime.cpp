@@ -112,7 +112,7 @@ struct loc_ctx {
   int* flags = nullptr;
   int last_N = 0, last_B = 0;
   // profiling
-  bool prof = false;
+  int prof = 0;               // 0 off, 1 every launch, 2 map-evaluation launches only
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
   long long launches[K_COUNT] = {};
@@ -172,14 +172,16 @@ hipEvent_t get_event(loc_ctx* c) {
 template <class F>
 loc_status timed(loc_ctx* c, int kid, double flop, double bytes, F fn) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (c->prof) {
+  const bool map_kernel = kid == K_MLP_COARSE || kid == K_MLP_FINE || kid == K_MLP_BOTH || kid == K_LV_RAYS;
+  const bool rec = c->prof == 1 || (c->prof == 2 && map_kernel);
+  if (rec) {
     a = get_event(c);
     b = get_event(c);
     if (a) hipEventRecord(a, c->stream);
   }
   hipError_t e = fn();
   if (e != hipSuccess) return fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
-  if (c->prof && a && b) {
+  if (rec && a && b) {
     hipEventRecord(b, c->stream);
     c->pending.push_back({kid, a, b, flop, bytes});
   }
@@ -893,7 +895,8 @@ loc_status loc_set_profiling(loc_ctx* c, int enable) {
   for (auto& p : c->pending) { c->free_events.push_back(p.a); c->free_events.push_back(p.b); }
   c->pending.clear();
   for (int k = 0; k < K_COUNT; ++k) { c->launches[k] = 0; c->ms[k] = c->flop[k] = c->bytes[k] = 0.0; }
-  c->prof = enable != 0;
+  if (enable < 0 || enable > 2) return fail(c, LOC_E_ARG, "profiling mode must be 0, 1 or 2");
+  c->prof = enable;
   return LOC_OK;
 }
 
@@ -1522,7 +1525,7 @@ loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* c
     if (pe != hipSuccess) return fail(c, LOC_E_HIP, "pending HIP error: %s", hipGetErrorString(pe));
   }
   if ((s = upload_key(c, motion, sigma_t, sigma_r, seed, iter))) return s;
-  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof);
+  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof != 0);
   std::vector<double> sig = level_signature(c, q);
   if (!c->gexec || sig != c->graph_sig) {
     drop_graph(c);
@@ -1619,8 +1622,8 @@ loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera*
     return s;
   }
   for (int L = 0; L < n_levels; ++L) c->lv[L].ntl = c->lv[L].waves = c->lv[L].blocks = 0;
-  const bool prof = c->prof;
-  c->prof = false;
+  const int prof = c->prof;
+  c->prof = 0;
   s = upload_key(c, nullptr, 0.0, 0.0, 12345, 0);
   if (!s) s = enqueue_levels(c, q, c->stream, false);
   // cached choices
