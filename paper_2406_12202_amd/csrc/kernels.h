@@ -154,6 +154,8 @@ struct GridDev {
   uint32_t dense_mask;     // bit l: level l indexes its vertices densely
   int res[kGridMaxLevels];
   float bound;
+  float2* feat;            // encoding workspace: levels x feat_cap (f_2l, f_2l+1) per sample
+  long feat_cap;           // samples per encoding chunk
 };
 hipError_t launch_grid_map(const GridDev& g, const MlpArgs& a, hipStream_t st);
 

@@ -63,6 +63,7 @@ struct loc_ctx {
   double bytes_per_sample = 20.0;   // algorithmic bytes of one map evaluation (grid: its table reads)
   uint32_t* grid_tab = nullptr;
   float* grid_mlp = nullptr;
+  float2* grid_feat = nullptr;   // encoding workspace of the grid map
   bool f8_ready = false;
   int f8_ew[12] = {}, f8_ea[12] = {};
   float f8_amax[12] = {};
@@ -734,6 +735,7 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->heads_f8);
   hipFree(c->grid_tab);
   hipFree(c->grid_mlp);
+  hipFree(c->grid_feat);
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
@@ -2097,8 +2099,11 @@ loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx**
     const _Float16 a = (_Float16)g->tables[2 * i], b = (_Float16)g->tables[2 * i + 1];
     H[i] = (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
   }
+  // encoding workspace: 2^21 samples per chunk (16 MB per level)
+  d.feat_cap = 1L << 21;
   bool ok = hipMalloc(&c->flags, sizeof(int)) == hipSuccess && hipMalloc(&c->grid_tab, n_tab * 4) == hipSuccess &&
             hipMalloc(&c->grid_mlp, n_mlp * 4) == hipSuccess &&
+            hipMalloc(&c->grid_feat, (size_t)d.feat_cap * L * sizeof(float2)) == hipSuccess &&
             hipMemcpy(c->grid_tab, H.data(), n_tab * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(c->grid_mlp, g->mlp, n_mlp * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) == hipSuccess &&
@@ -2110,6 +2115,7 @@ loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx**
   }
   d.tables = c->grid_tab;
   d.mlp = c->grid_mlp;
+  d.feat = c->grid_feat;
   *out = c;
   return LOC_OK;
 }
