@@ -155,6 +155,7 @@ struct GridDev {
   int res[kGridMaxLevels];
   float bound;
   float2* feat;            // encoding workspace: levels x feat_cap (f_2l, f_2l+1) per sample
+  float4* pts;             // feat_cap sample positions (u in the unit cube, inside flag)
   long feat_cap;           // samples per encoding chunk
 };
 hipError_t launch_grid_map(const GridDev& g, const MlpArgs& a, hipStream_t st);

@@ -64,6 +64,7 @@ struct loc_ctx {
   uint32_t* grid_tab = nullptr;
   float* grid_mlp = nullptr;
   float2* grid_feat = nullptr;   // encoding workspace of the grid map
+  float4* grid_pts = nullptr;    // sample positions of the grid map's chunk
   bool f8_ready = false;
   int f8_ew[12] = {}, f8_ea[12] = {};
   float f8_amax[12] = {};
@@ -736,6 +737,7 @@ void loc_destroy(loc_ctx* c) {
   hipFree(c->grid_tab);
   hipFree(c->grid_mlp);
   hipFree(c->grid_feat);
+  hipFree(c->grid_pts);
   hipFree(c->flags);
   hipFree(c->ray_o.p); hipFree(c->ray_d.p); hipFree(c->obs.p); hipFree(c->out_c.p); hipFree(c->out_f.p);
   hipFree(c->rgba.p); hipFree(c->fe.p); hipFree(c->t_c.p); hipFree(c->t_f.p); hipFree(c->prefix.p);
@@ -2104,6 +2106,7 @@ loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx**
   bool ok = hipMalloc(&c->flags, sizeof(int)) == hipSuccess && hipMalloc(&c->grid_tab, n_tab * 4) == hipSuccess &&
             hipMalloc(&c->grid_mlp, n_mlp * 4) == hipSuccess &&
             hipMalloc(&c->grid_feat, (size_t)d.feat_cap * L * sizeof(float2)) == hipSuccess &&
+            hipMalloc(&c->grid_pts, (size_t)d.feat_cap * sizeof(float4)) == hipSuccess &&
             hipMemcpy(c->grid_tab, H.data(), n_tab * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(c->grid_mlp, g->mlp, n_mlp * 4, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemsetAsync(c->flags, 0, sizeof(int), c->stream) == hipSuccess &&
@@ -2116,6 +2119,7 @@ loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx**
   d.tables = c->grid_tab;
   d.mlp = c->grid_mlp;
   d.feat = c->grid_feat;
+  d.pts = c->grid_pts;
   *out = c;
   return LOC_OK;
 }
