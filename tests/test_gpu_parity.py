@@ -103,6 +103,19 @@ def test_nerf_map_hierarchical_parity(torch_dev):
     _compare(g, o, TOL["nerf"])
 
 
+@pytest.mark.parametrize("n_coarse,n_fine", [(256, 256), (200, 57)])
+def test_nerf_map_longest_and_ragged_sample_lists(torch_dev, n_coarse, n_fine):
+    """The largest sample lists the compositing kernel takes (256 + 256: four
+    samples of each list per lane, 64 KB of LDS per workgroup) and lists that
+    are not multiples of the wave width."""
+    s, p, cam, poses, img = inputs("nerf", 9, N=2, n_coarse=n_coarse, n_fine=n_fine)
+    ctx = _ctx(s, p)
+    kw = dict(seed=5, it=1)
+    g = run_gpu(ctx, img, cam, 1, 5, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 5, poses, **kw)
+    _compare(g, o, TOL["nerf"])
+
+
 def test_nerf_map_full_size_sampled(torch_dev):
     # the bench workload: 400 particles x 64 rays x (64 + 128) samples; the
     # oracle checks three particles one by one
