@@ -194,7 +194,7 @@ def _resample_gpu(ctx, w, n_out, seed, it):
     return idx.cpu().numpy().tolist(), flags
 
 
-@pytest.mark.parametrize("case", ["random", "uniform", "onehot", "ties", "tiny", "large", "upsample", "mixed"])
+@pytest.mark.parametrize("case", ["random", "uniform", "onehot", "ties", "tiny", "large", "upsample", "lds_edge", "past_lds", "mixed"])
 def test_resample_bit_exact(torch_dev, case):
     s, p, _, _, _ = inputs("small", 0, N=1)
     ctx = _ctx(s, p)
@@ -216,6 +216,10 @@ def test_resample_bit_exact(torch_dev, case):
     elif case == "upsample":
         w = rng.random(100)
         n_out = 3000
+    elif case == "lds_edge":            # the largest set whose prefix is kept in LDS
+        w = rng.random(4096) ** 4
+    elif case == "past_lds":            # one more: the prefix goes to memory
+        w = rng.random(4097) ** 4
     else:
         w = rng.random(2000)
         w[::7] = 0.0
