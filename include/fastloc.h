@@ -143,7 +143,11 @@ typedef struct { int W, H; double fx, fy, cx, cy; } loc_camera;
  * levels in {4, 8, 16}, L_dir in {2, 4} (LOC_E_UNSUPPORTED otherwise),
  * log2_table in [10, 24], 2 <= n_min <= n_max <= 2^16.  Every update,
  * render and localisation call accepts the context; the coarse-to-fine level
- * path, FP8 calibration and map training return LOC_E_UNSUPPORTED. */
+ * path, FP8 calibration and map training return LOC_E_UNSUPPORTED.  Besides
+ * the tables (4 B per entry) the context owns an evaluation workspace of
+ * 2^21 samples: 8 B per sample and level of features plus 16 B per sample of
+ * positions (288 MB at 16 levels); larger sample sets are evaluated in chunks
+ * of that size, with results independent of the chunking. */
 typedef struct {
   int levels, log2_table, n_min, n_max;
   float bound;
