@@ -183,6 +183,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
         default: ray_setup<8>(a, seed, iter, r, rs); break;
       }
     }
+    // once per batch: the direction encoding of lane q's ray (lanes q mod
+    // kRayBatch hold it), and the jitter draws of all its rays, lane 8 q + g
+    // holding the draw of ray q's samples 4 g .. 4 g + 3
+    bf16x8 gdr[2][LS::KBD];
+    posenc_both<LS::LD, LS::KBD>(rs.d[0], rs.d[1], rs.d[2], gdr);
+    u32x4 jd = {0u, 0u, 0u, 0u};
+    if (a.jitter) {
+      static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
+      const int qd = lane >> 3;
+      jd = draw(seed, iter, kStreamJitCoarse, __shfl(rs.i, qd, 64), __shfl(rs.j, qd, 64), lane & 7);
+    }
     for (int q0 = 0; q0 < kRayBatch; q0 += 2) {
       // this lane's ray (q0 + h) and sample n
       const int q = q0 + h;
@@ -190,15 +201,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
       const float4 o = make_float4(__shfl(rs.o[0], q, 64), __shfl(rs.o[1], q, 64), __shfl(rs.o[2], q, 64), 0.0f);
       const float4 d = make_float4(__shfl(rs.d[0], q, 64), __shfl(rs.d[1], q, 64), __shfl(rs.d[2], q, 64), 0.0f);
       const float ob0 = __shfl(rs.obs[0], q, 64), ob1 = __shfl(rs.obs[1], q, 64), ob2 = __shfl(rs.obs[2], q, 64);
-      const int i = __shfl(rs.i, q, 64), j = __shfl(rs.j, q, 64);
       const int k = n;
       float xi = 0.0f;
-      if (a.jitter) xi = unit24(pick(draw(seed, iter, kStreamJitCoarse, i, j, k >> 2), k & 3));
+      if (a.jitter) {
+        const int src = 8 * q + (k >> 2);
+        const u32x4 dq = {(uint32_t)__shfl((int)jd.x, src, 64), (uint32_t)__shfl((int)jd.y, src, 64),
+                          (uint32_t)__shfl((int)jd.z, src, 64), (uint32_t)__shfl((int)jd.w, src, 64)};
+        xi = unit24(pick(dq, k & 3));
+      }
       const float tk = a.near_ + ((float)k + xi) * a.dt;
       {
         bf16x8 gx[2][LS::KBX], gd[2][LS::KBD];
         posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), gx);
-        posenc_both<LS::LD, LS::KBD>(d.x, d.y, d.z, gd);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+          for (int kb = 0; kb < LS::KBD; ++kb) {
+            uint4 u = __builtin_bit_cast(uint4, gdr[hh][kb]);
+            u.x = (uint32_t)__shfl((int)u.x, q, 64);
+            u.y = (uint32_t)__shfl((int)u.y, q, 64);
+            u.z = (uint32_t)__shfl((int)u.z, q, 64);
+            u.w = (uint32_t)__shfl((int)u.w, q, 64);
+            gd[hh][kb] = __builtin_bit_cast(bf16x8, u);
+          }
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
 #pragma unroll
