@@ -136,26 +136,72 @@ __device__ __forceinline__ int half_min_int(int v) {
   return v;
 }
 
+#ifndef FL_LEVEL_WAVES_PER_EU
+#define FL_LEVEL_WAVES_PER_EU 3
+#endif
+
 template <int WAVES>
 struct LevelCfg {
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + (long)WAVES * 2 * (LS::KBX + LS::KBD) * 1024;
+  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4;
 };
+
+// the head tile with the direction operands in registers (head_tile's
+// arithmetic, operand gd[nt][kb] for column tile nt)
+template <int NTL>
+__device__ __forceinline__ void head_tile_r(const uint4* w, const float* bl, const bf16x8 (&x)[NTL][LS::KBH],
+                                            const bf16x8 (&gd)[NTL][LS::KBD], const int lane, f32x16 (&acc)[NTL]) {
+  f32x16 binit;
+  const float4* b4 = reinterpret_cast<const float4*>(bl);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 v = b4[i];
+    binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
+  }
+#pragma unroll
+  for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
+#pragma unroll
+  for (int kb = 0; kb < LS::KBH; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, w[kb * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[nt][kb], acc[nt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int kb = 0; kb < LS::KBD; ++kb) {
+    const bf16x8 a = __builtin_bit_cast(bf16x8, w[(LS::KBH + kb) * 64 + lane]);
+#pragma unroll
+    for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, gd[nt][kb], acc[nt], 0, 0, 0);
+  }
+}
+
+// operands of column tile nt for lane (n, h) from the lane that computed
+// sample n of ray nt (lane n + 32 nt): its own half-h operand when nt == h,
+// else the partner lane's (lane xor 32), which sends its half-(1 - h) operand
+__device__ __forceinline__ void tile_operands(const bf16x8& mine, const bf16x8& other_half, const int h,
+                                              bf16x8& t0, bf16x8& t1) {
+  uint4 u = __builtin_bit_cast(uint4, other_half);
+  u.x = (uint32_t)__shfl_xor((int)u.x, 32, 64);
+  u.y = (uint32_t)__shfl_xor((int)u.y, 32, 64);
+  u.z = (uint32_t)__shfl_xor((int)u.z, 32, 64);
+  u.w = (uint32_t)__shfl_xor((int)u.w, 32, 64);
+  const bf16x8 recv = __builtin_bit_cast(bf16x8, u);
+  t0 = h == 0 ? mine : recv;
+  t1 = h == 1 ? mine : recv;
+}
 
 // Rays go through the wave in pairs: lane (n, h) = lane n + 32 h owns sample
 // n of ray h of the pair for everything outside the MFMAs (jitter, depth,
 // encoding, head nonlinearities, compositing), so no lane repeats another's
-// work; the encodings are written in the MFMA operand layout of column tile h
-// (both k-halves of sample n), the map runs on the two tiles, and the head
-// rows of tile 1 are moved from half 0 to half 1 by one shuffle per row.
+// work; a lane computes both k-halves of its sample's encoding operands and
+// exchanges one half with lane xor 32 to hold the MFMA operands of both
+// column tiles, the map runs on the two tiles, and the head rows of tile 1
+// are moved from half 0 to half 1 by one shuffle per row.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(FL_LEVEL_WAVES_PER_EU))) void k_level_rays(const LevelRayArgs a) {
   using C = LevelCfg<WAVES>;
   constexpr int NTL = 2;
   __shared__ uint4 s_w[LS::BLOCKS * 64];
   __shared__ float4 s_bias[LS::BIASES / 4];
-  __shared__ uint4 s_gx[WAVES][NTL * LS::KBX * 64];
-  __shared__ uint4 s_gd[WAVES][NTL * LS::KBD * 64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 31, h = lane >> 5;
   {
@@ -210,6 +256,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
         xi = unit24(pick(dq, k & 3));
       }
       const float tk = a.near_ + ((float)k + xi) * a.dt;
+      bf16x8 x0[NTL][LS::KBX], gdt[NTL][LS::KBD];
       {
         bf16x8 gx[2][LS::KBX], gd[2][LS::KBD];
         posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), gx);
@@ -225,24 +272,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
             gd[hh][kb] = __builtin_bit_cast(bf16x8, u);
           }
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
+        for (int kb = 0; kb < LS::KBX; ++kb)
+          tile_operands(h ? gx[1][kb] : gx[0][kb], h ? gx[0][kb] : gx[1][kb], h, x0[0][kb], x0[1][kb]);
 #pragma unroll
-          for (int kb = 0; kb < LS::KBX; ++kb)
-            s_gx[wv][(h * LS::KBX + kb) * 64 + n + 32 * hh] = __builtin_bit_cast(uint4, gx[hh][kb]);
-#pragma unroll
-          for (int kb = 0; kb < LS::KBD; ++kb)
-            s_gd[wv][(h * LS::KBD + kb) * 64 + n + 32 * hh] = __builtin_bit_cast(uint4, gd[hh][kb]);
-        }
+        for (int kb = 0; kb < LS::KBD; ++kb)
+          tile_operands(h ? gd[1][kb] : gd[0][kb], h ? gd[0][kb] : gd[1][kb], h, gdt[0][kb], gdt[1][kb]);
       }
-      // the encodings written by other lanes of this wave are read below
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // the map on both column tiles (layer order and arithmetic of k_mlp_bf16)
       bf16x8 xa[NTL][LS::KBH], xb[NTL][LS::KBH];
-      dense_res<NTL, LS::MT, LS::KBX, LS::KBH, true, LS::KBH>(s_w + LS::block_base(0) * 64,
-                                                             bias + LS::bias_base(0) + h * 16, true, xb, s_gx[wv],
-                                                             xa, lane);
+      dense_res<NTL, LS::MT, LS::KBX, LS::KBX, false, LS::KBH>(s_w + LS::block_base(0) * 64,
+                                                              bias + LS::bias_base(0) + h * 16, true, x0, nullptr,
+                                                              xa, lane);
 #pragma unroll
       for (int l = 1; l < LS::D; ++l) {
         dense_res<NTL, LS::MT, LS::KBH, LS::KBH, false, LS::KBH>(s_w + LS::block_base(l) * 64,
@@ -254,7 +294,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_level_rays(const LevelRayArgs a)
           for (int qq = 0; qq < LS::KBH; ++qq) xa[nt][qq] = xb[nt][qq];
       }
       f32x16 hacc[NTL];
-      head_tile<LS, NTL>(s_w + LS::HEAD_BLOCK * 64, bias + LS::HEAD_BIAS + h * 16, xa, s_gd[wv], lane, hacc);
+      head_tile_r<NTL>(s_w + LS::HEAD_BLOCK * 64, bias + LS::HEAD_BIAS + h * 16, xa, gdt, lane, hacc);
       // head rows 0..3 of tile h: half 0 holds them for both tiles
       float hv[4];
 #pragma unroll
