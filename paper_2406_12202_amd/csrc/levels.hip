@@ -136,6 +136,10 @@ __device__ __forceinline__ int half_min_int(int v) {
   return v;
 }
 
+// Waves per SIMD the ray kernel is compiled for (at most 168 registers, a
+// few spilled): measured on MI355X, three waves hide more of each ray pair's
+// dependent chain than two at 240 registers (185 against 201 us per
+// coarse-to-fine update).
 #ifndef FL_LEVEL_WAVES_PER_EU
 #define FL_LEVEL_WAVES_PER_EU 3
 #endif
@@ -197,7 +201,8 @@ __device__ __forceinline__ void tile_operands(const bf16x8& mine, const bf16x8& 
 // column tiles, the map runs on the two tiles, and the head rows of tile 1
 // are moved from half 0 to half 1 by one shuffle per row.
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(FL_LEVEL_WAVES_PER_EU))) void k_level_rays(const LevelRayArgs a) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(FL_LEVEL_WAVES_PER_EU))) void
+k_level_rays(const LevelRayArgs a) {
   using C = LevelCfg<WAVES>;
   constexpr int NTL = 2;
   __shared__ uint4 s_w[LS::BLOCKS * 64];
