@@ -137,6 +137,22 @@ def test_bf16_proposal_one_launch_for_coarse_and_fine(torch_dev):
     _check(g, o)
 
 
+def test_bf16_proposal_ragged_fine_count(torch_dev):
+    """The merged coarse + proposal launch with 13 fine samples per ray (not a
+    multiple of the four samples per draw, so the two sample sets meet at
+    odd offsets inside column tiles) and a ragged ray count."""
+    from paper_2406_12202_amd import synth
+    s, p, cam, poses, img = inputs("nerf", 28, N=3, n_fine=13)
+    theta = synth.proposal_params(28)
+    c = ctx(s, p, "bf16")
+    c.loc_set_proposal(theta)
+    c.loc_set_fine_mode(1)
+    kw = dict(seed=6, it=1)
+    g = run_gpu(c, img, cam, 1, 11, poses, **kw)
+    o = run_oracle(s, p, img, cam, 1, 11, poses, proposal=theta, **kw)
+    _check(g, o)
+
+
 def test_bf16_proposal_full_size_sampled(torch_dev):
     """The headline configuration as bench.py times it: 400 particles x 64
     rays, 64 coarse + 32 proposal-placed samples in one BF16 launch (a seeded

@@ -55,10 +55,13 @@ def test_cast_rays_match_oracle(torch_dev):
             assert np.abs(d[i * 8 + j] - rd_).max() <= 2e-7
 
 
-def test_teacher_histograms_match_oracle(torch_dev):
+@pytest.mark.parametrize("n_rays", [24, 23])
+def test_teacher_histograms_match_oracle(torch_dev, n_rays):
+    """Teacher targets (the compositing kernel's histogram mode); 23 rays leave
+    the last workgroup of four one-ray waves partly empty."""
     torch = torch_dev
     s, p, _, _, _ = inputs("nerf", 32)
-    O, D = _rays(24, 1)
+    O, D = _rays(n_rays, 1)
     # rays start outside the scene: move origins to radius 4 looking inward
     O = (4.0 * O / np.linalg.norm(O, axis=1, keepdims=True)).astype(np.float32)
     D = (-O / np.linalg.norm(O, axis=1, keepdims=True) + 0.3 * D).astype(np.float32)
@@ -135,12 +138,13 @@ def test_adam_trajectory_matches_oracle(torch_dev):
     assert d.max() <= 1e-3 * lr
 
 
-@pytest.mark.parametrize("N,B,n_fine", [(4, 8, 32), (3, 13, 13)])
+@pytest.mark.parametrize("N,B,n_fine", [(4, 8, 32), (3, 13, 13), (2, 3, 256)])
 def test_update_with_proposal_matches_oracle(torch_dev, N, B, n_fine):
     """Proposal-placed fine samples inside the particle update; the second
     case has a ray count that leaves the last 32-ray tile of the proposal
     kernel partly empty and a fine count that is not a multiple of the four
-    samples one random draw serves."""
+    samples one random draw serves; the third places the most fine samples a
+    ray takes (256, 32 draws per lane half)."""
     s, p, cam, poses, img = inputs("nerf", 36, N=N, n_fine=n_fine)
     theta = synth.proposal_params(8)
     c = ctx(s, p)
