@@ -3,11 +3,14 @@ FP64 oracle (oracle/grid.py through mcl.update_particles).
 
 The grid path computes in float32: the cell coordinate p = u N_l carries a
 relative rounding of about 2^-24 times N_l (up to 2048), so the trilinear
-weights move by up to ~1e-4 and the encoding, which is continuous across cell
-faces, by that times the feature scale.  Tolerances (set from that bound and
-the measured spread): colour and opacity 5e-4, F: 99% of rays within 2e-3
-and all within 0.1 (thin-density crossings amplify rounding as for the NeRF
-map), log-likelihood 1e-2, weights 5e-2 relative above 1e-6.
+weights move by up to ~1.2e-4 and a level's features, which are continuous
+across cell faces, by that times the spread of the corner entries (up to ~3
+for N(0, 0.5^2) entries), ~4e-4; the tiny MLP and the density gain carry that
+into colour and opacity with a gain of a few on the rays whose density is
+steep.  Tolerances: colour and opacity p99 5e-4 (the measured bulk, 1e-4 at
+p99) and max 2e-3 (the bound above for the steepest rays), F: 99% of rays
+within 2e-3 and all within 0.1 (thin-density crossings amplify rounding as
+for the NeRF map), log-likelihood 1e-2, weights 5e-2 relative above 1e-6.
 """
 import numpy as np
 import pytest
@@ -18,7 +21,7 @@ from parity_util import frac_over, stats
 
 pytestmark = pytest.mark.gpu
 
-TOL = dict(C=5e-4, F=2e-3, F_MAX=0.1, L=1e-2, W=5e-2)
+TOL = dict(C=5e-4, C_MAX=2e-3, F=2e-3, F_MAX=0.1, L=1e-2, W=5e-2)
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +52,8 @@ def _compare(g, o, idx):
     rA = stats("A", g["A"][idx], o["A"])
     rF = stats("F", g["F"][idx], o["F"])
     rL = stats("loglik", g["loglik"][idx], o["loglik"])
-    assert rC["max"] <= TOL["C"] and rA["max"] <= TOL["C"]
+    assert rC["p99"] <= TOL["C"] and rA["p99"] <= TOL["C"]
+    assert rC["max"] <= TOL["C_MAX"] and rA["max"] <= TOL["C_MAX"]
     assert frac_over(g["F"][idx], o["F"], TOL["F"]) <= 0.01
     assert rF["max"] <= TOL["F_MAX"]
     assert rL["max"] <= TOL["L"]
@@ -70,6 +74,28 @@ def test_grid_map_update_full_size_sampled_particles(torch_dev):
     o = mcl.update_particles(spec, params, img, cam, 1, 64, poses, None, 0.01, 0.01, 5, 2, subset=idx)
     _compare(g, o, idx)
     assert np.all(np.isfinite(g["loglik"])) and abs(g["weight"].sum() - 1.0) < 1e-12
+    ctx.close()
+
+
+def test_grid_map_chunk_boundary_inside_a_ray(torch_dev):
+    """400 particles x 64 rays x (64 + 112) samples: the fine set of 2,867,200
+    samples is evaluated in two chunks of at most 2^21, and the boundary,
+    sample 2,097,152, falls inside ray 18724 (particle 292, ray 36, fine
+    sample 64 of 112; a ray through the box); that particle, the first and
+    the last against the oracle."""
+    torch = torch_dev
+    spec = synth.grid_spec(n_coarse=64, n_fine=112)
+    params = synth.grid_params(spec, 8)
+    cam = synth.camera("nerf")
+    poses = synth.particles("nerf", 8)
+    img = synth.observation("nerf", 8)
+    ctx = _ctx(spec, params)
+    g = _run(torch, ctx, img, cam, 1, 64, poses, 9, 1)
+    assert (1 << 21) // 112 == 18724 and (1 << 21) % 112 == 64
+    idx = [0, 292, 399]
+    o = mcl.update_particles(spec, params, img, cam, 1, 64, poses, None, 0.0, 0.0, 9, 1, subset=idx)
+    assert o["A"][1][36] > 0.1      # the boundary ray is not empty
+    _compare(g, o, idx)
     ctx.close()
 
 
