@@ -138,13 +138,14 @@ def test_adam_trajectory_matches_oracle(torch_dev):
     assert d.max() <= 1e-3 * lr
 
 
-@pytest.mark.parametrize("N,B,n_fine", [(4, 8, 32), (3, 13, 13), (2, 3, 256)])
+@pytest.mark.parametrize("N,B,n_fine", [(4, 8, 32), (3, 13, 13), (2, 3, 256), (1, 1, 32)])
 def test_update_with_proposal_matches_oracle(torch_dev, N, B, n_fine):
     """Proposal-placed fine samples inside the particle update; the second
     case has a ray count that leaves the last 32-ray tile of the proposal
     kernel partly empty and a fine count that is not a multiple of the four
     samples one random draw serves; the third places the most fine samples a
-    ray takes (256, 32 draws per lane half)."""
+    ray takes (256, 32 draws per lane half); the fourth is one ray (31 empty
+    columns in the proposal kernel's tile)."""
     s, p, cam, poses, img = inputs("nerf", 36, N=N, n_fine=n_fine)
     theta = synth.proposal_params(8)
     c = ctx(s, p)
