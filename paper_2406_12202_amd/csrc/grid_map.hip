@@ -15,7 +15,8 @@
 //   encode   one thread per (sample, level), launched level-major (grid.y is
 //            the level, so the blocks in flight read one level's table, 2 MB
 //            at 2^19 entries, which stays in every XCD's L2), the 8 corner
-//            reads and the blend, float32 features to the workspace;
+//            reads (x-neighbours in one 8-byte read where they share one)
+//            and the blend, float32 features to the workspace;
 //   mlp      the tiny MLP on the matrix cores, 32 samples per wave.
 // Positions and features are computed as by a single pass per sample, so
 // results do not depend on the chunking.
@@ -120,40 +121,84 @@ __device__ __forceinline__ void grid_corners(const GridDev& g, const float4 u, c
   const bool dense = (g.dense_mask >> l) & 1u;
   const uint32_t n1 = (uint32_t)N + 1u;
   const uint32_t tmask = (1u << g.log2_table) - 1u;
+  // per-axis terms of the two corner coordinates on each axis, combined per
+  // corner by + (dense) or xor (hash); the same integers as forming each
+  // corner's index from its own coordinates
+  const uint32_t x0 = (uint32_t)c0i, y0 = (uint32_t)c1i, z0 = (uint32_t)c2i;
+  uint32_t ty[2], tz[2];
+  if (dense) {
+    ty[0] = n1 * y0;
+    tz[0] = n1 * n1 * z0;
+    ty[1] = ty[0] + n1;
+    tz[1] = tz[0] + n1 * n1;
+  } else {
+    ty[0] = y0 * 2654435761u;
+    tz[0] = z0 * 805459861u;
+    ty[1] = ty[0] + 2654435761u;
+    tz[1] = tz[0] + 805459861u;
+  }
 #pragma unroll
   for (int corner = 0; corner < 8; ++corner) {
-    const uint32_t a0 = (uint32_t)(c0i + (corner & 1)), a1 = (uint32_t)(c1i + ((corner >> 1) & 1)),
-                   a2 = (uint32_t)(c2i + ((corner >> 2) & 1));
-    idx[corner] = dense ? a0 + n1 * (a1 + n1 * a2) : ((a0 * 1u) ^ (a1 * 2654435761u) ^ (a2 * 805459861u)) & tmask;
-    wt[corner] = ((corner & 1) ? w0 : 1.0f - w0) * (((corner >> 1) & 1) ? w1 : 1.0f - w1) *
-                 (((corner >> 2) & 1) ? w2 : 1.0f - w2);
+    const uint32_t tx = x0 + (uint32_t)(corner & 1), yz = (corner >> 1) & 1, zz = (corner >> 2) & 1;
+    idx[corner] = dense ? tx + ty[yz] + tz[zz] : (tx ^ ty[yz] ^ tz[zz]) & tmask;
+    wt[corner] = ((corner & 1) ? w0 : 1.0f - w0) * (yz ? w1 : 1.0f - w1) * (zz ? w2 : 1.0f - w2);
   }
 }
 
 // Samples per thread of the encoding pass: the reads of all of a thread's
 // samples are issued before any blend, so that more of them are in flight
 // (measured on MI355X, 16 levels of 2^19 entries: two samples per thread
-// 10% faster than one, four no better than two).
+// 2.5% faster than one over the whole map launch, four no better than two).
+// At the finer levels the pass is bound by the rate of L2 line requests
+// (about six distinct lines per sample and level); the index arithmetic is
+// not on the critical path.
 #ifndef FL_GRID_SPT
 #define FL_GRID_SPT 2
 #endif
 constexpr int kGridSpt = FL_GRID_SPT;
+// raw buffer resource word 3 of the gfx9 family (no format, no swizzle), and
+// an offset beyond every level's table (at most 2^24 entries of 4 B)
+constexpr int kRawBufferFlags = 0x00020000;
+constexpr uint32_t kGridNoRead = 0x80000000u;
+typedef uint32_t gu32x2 __attribute__((ext_vector_type(2)));
 
 // samples c0 .. c0 + n - 1, level blockIdx.y; thread samples q0 + 256 i
 __global__ __launch_bounds__(256) void k_grid_encode(const GridDev g, const MlpArgs a, const long c0, const long n) {
   const long q0 = (long)blockIdx.x * blockDim.x * kGridSpt + threadIdx.x;
   const int l = blockIdx.y;
   const uint32_t* tab = g.tables + ((long)l << g.log2_table);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(tab), 0, (int)(4u << g.log2_table), kRawBufferFlags);
+  // every position first, so that no wait for one of them also waits for
+  // table reads issued before it
+  float4 u[kGridSpt];
+#pragma unroll
+  for (int i = 0; i < kGridSpt; ++i) {
+    const long q = q0 + (long)i * blockDim.x;
+    u[i] = q < n ? g.pts[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
   uint32_t e[kGridSpt][8];
   float wt[kGridSpt][8];
 #pragma unroll
   for (int i = 0; i < kGridSpt; ++i) {
-    const long q = q0 + (long)i * blockDim.x;
+    const bool live = q0 + (long)i * blockDim.x < n;
     uint32_t idx[8];
-    if (q < n) {
-      grid_corners(g, g.pts[q], l, idx, wt[i]);
+    grid_corners(g, u[i], l, idx, wt[i]);
+    // the x-neighbours c and c + e_0 share one aligned 8-byte word of the
+    // table whenever their indices differ only in bit 0 (even c_0 under the
+    // hash, whose x factor is 1; an even dense index): one 64-bit read then
+    // serves both, and the odd neighbour's own read (like every read of a
+    // thread past the last sample) is given an offset past the buffer's end,
+    // which returns 0 without touching memory; no branches, so all reads of
+    // the thread are in flight together
 #pragma unroll
-      for (int corner = 0; corner < 8; ++corner) e[i][corner] = tab[idx[corner]];
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i0 = idx[2 * k], i1 = idx[2 * k + 1];
+      const bool paired = i1 == (i0 ^ 1u);
+      const gu32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, live ? (i0 & ~1u) * 4u : kGridNoRead, 0, 0);
+      const uint32_t lone = __builtin_amdgcn_raw_buffer_load_b32(rs, live && !paired ? i1 * 4u : kGridNoRead, 0, 0);
+      e[i][2 * k] = (i0 & 1u) ? w.y : w.x;
+      e[i][2 * k + 1] = paired ? ((i1 & 1u) ? w.y : w.x) : lone;
     }
   }
 #pragma unroll
