@@ -174,7 +174,8 @@ loc_status loc_init_map(const loc_map_desc* map, void* hip_stream, loc_ctx** out
  *   cam        HOST   full-resolution intrinsics; W and H divisible by inv_R
  *   inv_R      level factor s in {1, 2, 4, 8}: R_t = 1/s; the observation is
  *              box-averaged over s x s blocks (downscale(I_t, R_t))
- *   B, N       query pixels per particle B_t (1..1024) and particles (>= 1)
+ *   B, N       query pixels per particle B_t (1..1024) and particles (>= 1,
+ *              N B <= 2^22 rays per call; LOC_E_ARG otherwise)
  *   pose_in    DEVICE N x 12 float64 camera-to-world [R | t], row-major
  *   motion     HOST   12 float64 O_t, or NULL for the identity
  *   sigma_t, sigma_r  prediction noise (scene units, radians), >= 0

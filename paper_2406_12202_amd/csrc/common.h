@@ -7,6 +7,19 @@ namespace fl {
 
 constexpr int kWave = 64;
 
+// A dispatch counts work-items per grid dimension in 32 bits, so launches of
+// many workgroups are folded into rows (grid.y) of at most kGridRow
+// workgroups, and the kernel recovers its workgroup number with
+// flat_block(); the last row may end past the work, so a kernel leaves
+// whole workgroups whose number is out of range.  Rows are short enough that
+// ordinary map launches (a few million samples) already span several.
+constexpr long kGridRow = 1L << 13;
+inline dim3 folded_grid(const long blocks) {
+  const long rows = (blocks + kGridRow - 1) / kGridRow;
+  return dim3((unsigned)((blocks + rows - 1) / rows), (unsigned)rows);
+}
+__device__ __forceinline__ long flat_block() { return (long)blockIdx.y * gridDim.x + blockIdx.x; }
+
 // Philox stream tags (top byte of counter word 3); see fastloc.h.
 enum : uint32_t { kStreamPix = 1, kStreamJitCoarse = 2, kStreamJitFine = 3,
                   kStreamMotion = 4, kStreamResample = 5 };

@@ -180,6 +180,8 @@ __device__ __forceinline__ NextGroup first_group(const int l) {
 template <class S, int NTL, int WAVES, int MPC>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
   using C = BCfg<S, NTL, WAVES, MPC>;
+  const long blk = flat_block();
+  if (blk * C::SAMPLES >= a.n_samples + a.n_samples2) return;   // whole workgroup, before any barrier
   __shared__ uint4 slot0[C::SLOT_KB * 64];
   __shared__ uint4 slot1[C::SLOT_KB * 64];
   __shared__ uint4 s_gx[WAVES][NTL * S::KBX * 64];   // per wave: [column tile][k-block][lane]
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
   for (int i = threadIdx.x; i < S::BIASES / 4; i += C::THREADS)
     s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
 
-  const long tile = (long)blockIdx.x * WAVES + wv;
+  const long tile = blk * WAVES + wv;
   long sidx[NTL];
   bool valid[NTL], seg2[NTL];
   stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid, seg2);
@@ -264,7 +266,7 @@ template <class S, int NTL, int WAVES, int MPC>
 hipError_t launch_mlp_bf16_t(const MlpArgs& a, hipStream_t st) {
   using C = BCfg<S, NTL, WAVES, MPC>;
   const long blocks = (a.n_samples + a.n_samples2 + C::SAMPLES - 1) / C::SAMPLES;
-  hipLaunchKernelGGL((k_mlp_bf16<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(C::THREADS), 0, st, a);
+  hipLaunchKernelGGL((k_mlp_bf16<S, NTL, WAVES, MPC>), folded_grid(blocks), dim3(C::THREADS), 0, st, a);
   return hipGetLastError();
 }
 

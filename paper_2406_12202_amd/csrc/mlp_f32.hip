@@ -97,7 +97,9 @@ template <class S>
 __global__ __launch_bounds__(256) void k_mlp_f32(const MlpArgs a) {
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  const long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long blk = flat_block();
+  if (blk * 64 >= a.n_samples) return;   // whole workgroup
+  const long tile = blk * 4 + (threadIdx.x >> 6);
   const long s = tile * 16 + n;
   const bool valid = s < a.n_samples;
   const long sc = valid ? s : a.n_samples - 1;
@@ -174,7 +176,7 @@ template <class S>
 hipError_t launch_mlp_f32(const MlpArgs& a, hipStream_t st) {
   const long tiles = (a.n_samples + 15) / 16;
   const long blocks = (tiles + 3) / 4;
-  hipLaunchKernelGGL(k_mlp_f32<S>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_mlp_f32<S>, folded_grid(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

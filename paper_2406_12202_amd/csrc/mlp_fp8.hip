@@ -164,6 +164,8 @@ template <class S, int NTL, int WAVES, int MPC>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   constexpr int SLOT_U = MPC * S::MAX_U;
   constexpr int THREADS = 64 * WAVES;
+  const long blk = flat_block();
+  if (blk * (32 * NTL * WAVES) >= a.n_samples + a.n_samples2) return;   // whole workgroup, before any barrier
   __shared__ uint4 slot0[SLOT_U * 64];
   __shared__ uint4 slot1[SLOT_U * 64];
   __shared__ uint4 s_gx[WAVES][NTL * S::KBX * 64];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   for (int i = threadIdx.x; i < S::BIASES / 4; i += THREADS) s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
   for (int i = threadIdx.x; i < S::HEADS / 4; i += THREADS) s_heads[i] = reinterpret_cast<const float4*>(a.heads)[i];
 
-  const long tile = (long)blockIdx.x * WAVES + wv;
+  const long tile = blk * WAVES + wv;
   long sidx[NTL];
   bool valid[NTL], seg2[NTL];
   stage_samples<S::LX, S::LD, S::KBX, S::KBD, NTL>(a, tile, lane, s_gx[wv], s_gd[wv], sidx, valid, seg2);
@@ -235,7 +237,7 @@ template <class S, int NTL, int WAVES, int MPC>
 hipError_t launch_mlp_fp8_t(const MlpArgs& a, hipStream_t st) {
   constexpr int SAMPLES = 32 * NTL * WAVES;
   const long blocks = (a.n_samples + a.n_samples2 + SAMPLES - 1) / SAMPLES;
-  hipLaunchKernelGGL((k_mlp_fp8<S, NTL, WAVES, MPC>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, st, a);
+  hipLaunchKernelGGL((k_mlp_fp8<S, NTL, WAVES, MPC>), folded_grid(blocks), dim3(64 * WAVES), 0, st, a);
   return hipGetLastError();
 }
 

@@ -95,6 +95,20 @@ def test_bf16_small_map_ragged(torch_dev):
     _check(g, o)
 
 
+def test_bf16_maximum_ray_count_folded_launch(torch_dev):
+    # 2^22 rays x 128 samples: 2^29 samples in one launch of 2^21 workgroups,
+    # folded into 256 grid rows; first, middle and last particle against the
+    # oracle
+    s, p, cam, poses, img = inputs("small", 11, N=4096, n_coarse=128)
+    c = ctx(s, p, "bf16")
+    kw = dict(seed=5, it=2)
+    g = run_gpu(c, img, cam, 1, 1024, poses, **kw)
+    sub = [0, 2047, 4095]
+    o = run_oracle(s, p, img, cam, 1, 1024, poses, subset=sub, **kw)
+    _check(g, o, subset=sub)
+    assert np.all(np.isfinite(g["loglik"]))
+
+
 def test_bf16_nerf_map(torch_dev):
     s, p, cam, poses, img = inputs("nerf", 23, N=6)
     c = ctx(s, p, "bf16")

@@ -130,6 +130,26 @@ def test_nerf_map_full_size_sampled(torch_dev):
     assert np.all(np.isfinite(g["loglik"]))
 
 
+def test_maximum_ray_count_folded_launch(torch_dev):
+    # the largest call the interface accepts: N B = 2^22 rays (1024 rays for
+    # each of 4096 particles) with 128 samples per ray, 2^29 samples in one
+    # map launch whose workgroups are folded into 1024 grid rows; the oracle
+    # checks the first, a middle and the last particle (the last row's
+    # workgroups), and one particle more is refused
+    from paper_2406_12202_amd import binding
+    s, p, cam, poses, img = inputs("small", 11, N=4096, n_coarse=128)
+    ctx = _ctx(s, p)
+    kw = dict(seed=5, it=2)
+    g = run_gpu(ctx, img, cam, 1, 1024, poses, **kw)
+    sub = [0, 2047, 4095]
+    o = run_oracle(s, p, img, cam, 1, 1024, poses, subset=sub, **kw)
+    _compare(g, o, TOL["small"], subset=sub)
+    assert abs(g["weight"].sum() - 1.0) < 1e-12
+    assert np.all(np.isfinite(g["loglik"]))
+    with pytest.raises(binding.LocError):
+        run_gpu(ctx, img, cam, 1, 1024, np.concatenate([poses, poses[:1]]), **kw)
+
+
 def test_tau_dominant_reduces_to_eq4(torch_dev):
     # tau >= far - near: F = tau on every ray, so the normalised weights equal
     # normalised (B / sum_j E_j)^4 computed from the GPU's own E
