@@ -204,7 +204,7 @@ loc_status loc_update_particles(loc_ctx* ctx, const float* image_rgb, const loc_
  * ... + q_i > theta_k}.  Every step is exact or a correctly rounded division,
  * so the indices are bit-identical to any exact implementation.  If Q = 0 all
  * indices are -1 and loc_sync reports LOC_FLAG_DEGENERATE_RESAMPLE.
- * 1 <= n_in, n_out <= 2^24.
+ * 1 <= n_in <= 2^24 - 1 (so that Q < 2^64) and 1 <= n_out <= 2^24.
  */
 loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
                         uint64_t seed, uint64_t iter, int32_t* idx_out);
@@ -342,7 +342,7 @@ loc_status loc_render_image(loc_ctx* ctx, const loc_camera* cam, int inv_R, cons
 typedef struct {
   int inv_R;      /* level scale 1/inv_R, inv_R in {1, 2, 4, 8} */
   int B;          /* rays per particle, [1, 1024] */
-  int N;          /* particles drawn while in this stage, [1, 2^24] */
+  int N;          /* particles drawn while in this stage, [1, 2^24 - 1] */
   double delta;   /* variance threshold that ends the stage */
   double noise;   /* factor (>= 0) on sigma_t and sigma_r for the iterations
                      this stage weights (the paper fixes no noise schedule) */
@@ -371,7 +371,7 @@ typedef struct {
 } loc_trace;
 
 /* image DEVICE H x W x 3 float32; stages HOST n_stages (1..8); pose_in
- * DEVICE n_in x 12 float64, the initial set (n_in in [1, 2^24]); motion,
+ * DEVICE n_in x 12 float64, the initial set (n_in in [1, 2^24 - 1]); motion,
  * sigma_t, sigma_r, seed as loc_update_particles; pose_out DEVICE (max N over
  * the stages) x 12 float64 receives the final set and *n_out its size (0 if
  * the loop ended on a set without weight); info HOST n_iters records or NULL;

@@ -287,6 +287,33 @@ def resample(weight, n_out, seed, it):
     return out
 
 
+def resample_at(weight, n_out, seed, it, ks):
+    """The draws idx_k of resample() for the k in ks only, for particle sets
+    too large for its pure-Python loops: the same q_i (one float64 division,
+    an exact scaling by 2^40 and a floor per weight), the inclusive prefix as
+    a uint64 cumulative sum (exact: fewer than 2^24 terms of at most 2^40
+    keep every partial sum below 2^64), theta_k in Python integers, and the
+    smallest i with prefix_i > theta_k by binary search (searchsorted to the
+    right of equal keys).  Returns None when Q = 0."""
+    w = np.asarray(weight, dtype=np.float64)
+    assert w.size < 2 ** 24, "the uint64 prefix is exact below 2^24 weights"
+    wt = np.where(np.isfinite(w) & (w > 0.0), w, 0.0)
+    wmax = float(wt.max()) if wt.size else 0.0
+    if wmax <= 0.0:
+        return None
+    q = np.floor(wt / wmax * 2.0 ** 40).astype(np.uint64)
+    prefix = np.cumsum(q, dtype=np.uint64)
+    Q = int(prefix[-1])
+    if Q == 0:
+        return None
+    r0 = int(px.draw_words(seed, it, px.S_RESAMPLE, 0, 0, 0)[0])
+    out = []
+    for k in ks:
+        theta = ((int(k) << 32) + r0) * Q // (n_out << 32)
+        out.append(int(np.searchsorted(prefix, np.uint64(theta), side="right")))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # coarse-to-fine levels with 1-sigma rejection (Alg. 1 with per-iteration
 # R_t, B_t, N_t; Sec. III-C)

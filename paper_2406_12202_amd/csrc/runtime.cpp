@@ -865,8 +865,9 @@ loc_status loc_resample(loc_ctx* c, const double* weight, int n_in, int n_out, u
   if (!c) return LOC_E_ARG;
   c->err.clear();
   if (!weight || !idx_out) return fail(c, LOC_E_ARG, "null pointer argument");
-  if (n_in < 1 || n_in > (1 << 24) || n_out < 1 || n_out > (1 << 24))
-    return fail(c, LOC_E_ARG, "n_in and n_out must be in [1, 2^24]");
+  // n_in < 2^24 keeps Q = sum q_i (each q_i <= 2^40) below 2^64
+  if (n_in < 1 || n_in >= (1 << 24) || n_out < 1 || n_out > (1 << 24))
+    return fail(c, LOC_E_ARG, "n_in must be in [1, 2^24 - 1] and n_out in [1, 2^24]");
   loc_status s;
   if ((s = ensure(c, c->prefix, (size_t)n_in))) return s;
   return timed(c, K_RESAMPLE, 0, 8.0 * n_in * 2 + 4.0 * n_out, [&] {
@@ -1815,13 +1816,13 @@ loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, i
     const loc_stage& g = stages[k];
     if (g.inv_R != 1 && g.inv_R != 2 && g.inv_R != 4 && g.inv_R != 8)
       return fail(c, LOC_E_ARG, "stage %d: inv_R must be 1, 2, 4 or 8", k);
-    if (g.B < 1 || g.B > 1024 || g.N < 1 || g.N > (1 << 24))
+    if (g.B < 1 || g.B > 1024 || g.N < 1 || g.N >= (1 << 24))
       return fail(c, LOC_E_ARG, "stage %d: B or N out of range", k);
     if (k + 1 < n_stages && std::isnan(g.delta)) return fail(c, LOC_E_ARG, "stage %d: delta is NaN", k);
     if (!(g.noise >= 0.0) || !std::isfinite(g.noise)) return fail(c, LOC_E_ARG, "stage %d: noise factor", k);
     n_max = std::max(n_max, g.N);
   }
-  if (n_in < 1 || n_in > (1 << 24)) return fail(c, LOC_E_ARG, "n_in must be in [1, 2^24]");
+  if (n_in < 1 || n_in >= (1 << 24)) return fail(c, LOC_E_ARG, "n_in must be in [1, 2^24 - 1]");
   if (trace && trace->capacity > 0 && (!trace->pose || !trace->weight || !trace->idx))
     return fail(c, LOC_E_ARG, "trace buffers missing");
   loc_status s;

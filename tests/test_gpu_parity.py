@@ -254,6 +254,28 @@ def test_resample_bit_exact(torch_dev, case):
         assert flags == 0
 
 
+def test_resample_largest_set(torch_dev):
+    # n_in = 2^24 - 1, the largest set a draw accepts (Q = sum q_i stays below
+    # 2^64): equal weights draw every particle once (closed form), random
+    # weights agree with the oracle's sampled draws (first, last and 1000
+    # random k) and are non-decreasing; one particle more is refused
+    from paper_2406_12202_amd import binding
+    s, p, _, _, _ = inputs("small", 0, N=1)
+    ctx = _ctx(s, p)
+    n = 2 ** 24 - 1
+    got, flags = _resample_gpu(ctx, np.full(n, 1.0 / n), n, 5, 9)
+    assert flags == 0 and np.array_equal(np.asarray(got), np.arange(n))
+    rng = np.random.default_rng(24)
+    w = rng.random(n) ** 4
+    got, flags = _resample_gpu(ctx, w, n, 77, 12345)
+    got = np.asarray(got)
+    assert flags == 0 and np.all(np.diff(got) >= 0)
+    ks = np.concatenate([np.arange(64), rng.integers(0, n, 1000), np.arange(n - 64, n)])
+    assert got[ks].tolist() == mcl.resample_at(w, n, 77, 12345, ks)
+    with pytest.raises(binding.LocError):
+        _resample_gpu(ctx, np.full(n + 1, 1.0), n, 1, 1)
+
+
 def test_resample_degenerate(torch_dev):
     s, p, _, _, _ = inputs("small", 0, N=1)
     ctx = _ctx(s, p)

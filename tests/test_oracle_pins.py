@@ -502,6 +502,44 @@ def test_resample_threshold_equal_to_prefix_takes_next_index():
     assert mcl.resample(w, 1, seed, it) == [1]
 
 
+@pytest.mark.parametrize("case", ["random", "ties", "zeros", "upsample", "onehot"])
+def test_resample_at_agrees_with_the_full_draw(case):
+    # the sampled form used at the largest particle counts returns the same
+    # indices as the full draw on sets small enough for both
+    rng = np.random.default_rng(sum(map(ord, case)))
+    n_out = 400
+    if case == "random":
+        w = rng.random(700) ** 6
+    elif case == "ties":
+        w = np.repeat(rng.random(7), 60)
+    elif case == "zeros":
+        w = rng.random(500)
+        w[::3] = 0.0
+        w[4] = np.nan
+        w[8] = -2.0
+    elif case == "upsample":
+        w = rng.random(37)
+        n_out = 1500
+    else:
+        w = np.zeros(250)
+        w[17] = 3.0
+    for seed, it in [(1, 0), (99, 4321)]:
+        full = mcl.resample(w, n_out, seed, it)
+        ks = list(range(n_out))
+        assert mcl.resample_at(w, n_out, seed, it, ks) == full
+    assert mcl.resample_at(np.zeros(10), 5, 1, 1, [0]) is None
+
+
+def test_resample_uniform_weights_draw_each_particle_once():
+    # equal weights with n_out = n_in: q_i = 2^40, Q = n 2^40 and
+    # theta_k = k 2^40 + r0 2^8 with r0 2^8 < 2^40, so idx_k = k exactly
+    for n in (1, 2, 1000):
+        assert mcl.resample(np.full(n, 0.5), n, 5, 9) == list(range(n))
+    n = 2 ** 20
+    ks = [0, 1, n // 2, n - 2, n - 1]
+    assert mcl.resample_at(np.full(n, 1.0 / n), n, 5, 9, ks) == ks
+
+
 def test_resample_matches_fraction_arithmetic():
     # brute force: systematic resampling with exact rationals, u_k = (k + r0 / 2^32) / n
     w = np.array([0.1, 0.25, 0.05, 0.3, 0.3])
