@@ -47,6 +47,10 @@ TRAFFIC = {
              "bytes": {"headline": 15.876e6 + 45.875e6}},
     "fp32": {"sources": ("mlp_f32.hip", "maplayout.h", "common.h"), "digest": "b72475d2eab2bfe1",
              "bytes": {"headline": ((26.500e6 + 32.768e6) + (39.606e6 + 52.429e6)) / 2}},
+    # grid map: points + encoding + tiny MLP passes of one map launch, mean of
+    # the coarse launch (1101.5 MB) and the fine launch in two chunks (2176.7 MB)
+    "grid": {"sources": ("grid_map.hip", "kernels.h", "common.h"), "digest": "73e588cce07c1153",
+             "bytes": {"grid": (1101.5e6 + 2176.7e6) / 2}},
 }
 
 
@@ -542,7 +546,8 @@ def bench_grid(args, torch):
                                   "of two fp16 features per level) + 64-wide tiny MLP, 400x400 view" % (N, B)},
            "particle_updates_per_s": N * args.steps / (ms * 1e-3),
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                        "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_grid_encode + k_grid_mlp (16 levels)",
+                        "frac": round(achieved / 8000.0, 4), "traffic": traffic("grid", "grid"),
+                        "kernel": "k_grid_encode + k_grid_mlp (16 levels)",
                         "bytes_per_launch": m_bytes / m_launch, "avg_launch_ms": m_ms / m_launch},
            "kernels": kernels, "flags": flags}
     print(json.dumps(out), flush=True)
