@@ -209,6 +209,25 @@ loc_status loc_update_particles(loc_ctx* ctx, const float* image_rgb, const loc_
 loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
                         uint64_t seed, uint64_t iter, int32_t* idx_out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * loc_resample without any allocation.  Same arguments, result and flags as
+ * loc_resample (bit-identical indices); the integer prefix lives in a fixed
+ * library-owned device array of LOC_NOALLOC_MAX_WEIGHTS uint64 entries
+ * (8 MiB), one per GPU, held from library load until the process ends, whose
+ * address is resolved when a context is created.  The call allocates
+ * nothing and calls no allocating routine.
+ *   1 <= n_in <= LOC_NOALLOC_MAX_WEIGHTS, else LOC_E_ARG (no launch);
+ *   1 <= n_out <= 2^24.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU (several streams or
+ * contexts) race, and the caller must serialise them.
+ */
+#define LOC_NOALLOC_MAX_WEIGHTS (1 << 20)
+loc_status loc_resample_noalloc(loc_ctx* ctx, const double* weight, int n_in, int n_out,
+                                uint64_t seed, uint64_t iter, int32_t* idx_out);
+
 /* FP8 calibration of an LOC_FP8_E4M3 context (per-layer amax scaling): the
  * float32 map is evaluated at the midpoints of the n_coarse strata of each of
  * n_rays rays (o, d: DEVICE n_rays x 3 float32, e.g. loc_cast_rays output),

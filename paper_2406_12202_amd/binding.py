@@ -14,9 +14,10 @@ LIB_PATH = os.path.join(PKG, "libfastloc.so")
 LOC_OK, LOC_E_ARG, LOC_E_HIP, LOC_E_OOM, LOC_E_DEGENERATE, LOC_E_UNSUPPORTED, LOC_E_STATE = 0, -1, -2, -3, -4, -5, -6
 LOC_FP32, LOC_BF16, LOC_FP8_E4M3 = 0, 1, 2
 FLAG_DEGENERATE_WEIGHTS, FLAG_DEGENERATE_RESAMPLE = 1, 2
+LOC_NOALLOC_MAX_WEIGHTS = 1 << 20     # scratch entries of loc_resample_noalloc
 PRECISIONS = {"fp32": LOC_FP32, "bf16": LOC_BF16, "fp8": LOC_FP8_E4M3}
 
-EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
+EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_resample_noalloc", "loc_ray_outputs", "loc_sync",
            "loc_set_profiling", "loc_kernel_stats", "loc_destroy", "loc_status_str", "loc_last_error",
            "loc_cast_rays", "loc_teacher_histograms", "loc_set_proposal", "loc_get_proposal",
            "loc_set_fine_mode", "loc_proposal_forward", "loc_proposal_grad", "loc_train_proposal",
@@ -102,6 +103,7 @@ def load(path=LIB_PATH):
     lib.loc_update_particles.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, c_int, c_int, vp, vp,
                                          c_dbl, c_dbl, c_u64, c_u64, vp, vp, vp, vp]
     lib.loc_resample.argtypes = [vp, vp, c_int, c_int, c_u64, c_u64, vp]
+    lib.loc_resample_noalloc.argtypes = [vp, vp, c_int, c_int, c_u64, c_u64, vp]
     lib.loc_ray_outputs.argtypes = [vp, vp, vp, vp, vp]
     lib.loc_sync.argtypes = [vp, ctypes.POINTER(c_int)]
     lib.loc_set_profiling.argtypes = [vp, c_int]
@@ -141,7 +143,7 @@ def load(path=LIB_PATH):
     lib.loc_localize.argtypes = [vp, vp, ctypes.POINTER(Camera), c_int, ctypes.POINTER(Stage), c_int, c_int, vp, vp,
                                  c_dbl, c_dbl, c_u64, c_u64, vp, ctypes.POINTER(c_int), ctypes.POINTER(StepInfo),
                                  ctypes.POINTER(c_int), ctypes.POINTER(Trace)]
-    for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_ray_outputs", "loc_sync",
+    for f in ("loc_init_map", "loc_update_particles", "loc_resample", "loc_resample_noalloc", "loc_ray_outputs", "loc_sync",
               "loc_set_profiling", "loc_kernel_stats", "loc_cast_rays", "loc_teacher_histograms",
               "loc_set_proposal", "loc_get_proposal", "loc_set_fine_mode", "loc_proposal_forward",
               "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
@@ -266,6 +268,19 @@ class Context:
         st = self.lib.loc_resample(self.h, _ptr(weight, torch.float64, n_in, "weight"), int(n_in), int(n_out),
                                    int(seed), int(iter), _ptr(idx_out, torch.int32, n_out, "idx_out"))
         self._check(st, "loc_resample")
+        return idx_out
+
+    def loc_resample_noalloc(self, weight, n_out, seed=0, iter=0, idx_out=None):
+        """loc_resample through the allocation-free entry point (idx_out is
+        allocated here by torch when not given; the library allocates nothing)."""
+        import torch
+        n_in = weight.numel()
+        if idx_out is None:
+            idx_out = torch.empty(n_out, dtype=torch.int32, device=weight.device)
+        st = self.lib.loc_resample_noalloc(self.h, _ptr(weight, torch.float64, n_in, "weight"), int(n_in),
+                                           int(n_out), int(seed), int(iter),
+                                           _ptr(idx_out, torch.int32, n_out, "idx_out"))
+        self._check(st, "loc_resample_noalloc")
         return idx_out
 
     def loc_ray_outputs(self):

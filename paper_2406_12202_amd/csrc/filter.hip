@@ -1,6 +1,8 @@
 // Per-step particle-filter kernels in float64: prediction, weight
 // normalisation, integer-exact systematic resampling, the gather of resampled
 // poses and the pose read-out (device functions in filter_dev.h).
+#include <mutex>
+
 #include "filter_dev.h"
 
 namespace fl {
@@ -40,6 +42,40 @@ hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t s
   hipLaunchKernelGGL(k_resample, dim3(1), dim3(kRedThreads), 0, st, weight, n_in, n_out, seed, iter,
                      prefix, idx, flags);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free resampling call: the inclusive prefix of the
+// integer weights, kNoAllocMaxWeights entries (8 MiB).  Each GPU the library
+// runs on holds its own copy from module load to process end; every call on
+// that GPU shares it, so calls that overlap in time on one GPU race.  Every
+// entry the kernel reads is written earlier in the same launch (the prefix
+// of all n_in weights precedes the searches), so nothing needs clearing.
+static __device__ __align__(256) u64 scratch[kNoAllocMaxWeights];
+
+// Device address of this GPU's scratch, looked up once per device with that
+// device current (host code never passes the array's own name to a kernel:
+// on the host that name is a stand-in, not a device address).
+hipError_t noalloc_scratch(int device, u64** out) {
+  static std::mutex mu;
+  static u64* ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    ptr[device] = static_cast<u64*>(p);
+  }
+  *out = ptr[device];
+  return hipSuccess;
 }
 
 // out[k] = in[idx[k]] (idx < 0 copies nothing)

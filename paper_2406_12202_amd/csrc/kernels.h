@@ -190,6 +190,11 @@ hipError_t launch_normalize(const double* loglik, double* weight, int N, int* fl
 
 hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
                            unsigned long long* prefix, int32_t* idx, int* flags, hipStream_t st);
+// the allocation-free resampling call's scratch (kNoAllocMaxWeights uint64
+// entries per GPU): its device address on `device`, resolved once per device
+constexpr int kNoAllocMaxWeights = 1 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, unsigned long long** out);
 
 hipError_t launch_gather_poses(const double* in, const int32_t* idx, int n_in, int n_out, double* out,
                                hipStream_t st);

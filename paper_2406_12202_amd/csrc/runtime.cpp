@@ -45,6 +45,7 @@ struct DevBuf {
 
 struct loc_ctx {
   int device = 0;
+  unsigned long long* noalloc_prefix = nullptr;   // this device's scratch of loc_resample_noalloc
   hipStream_t stream = nullptr;
   loc_map_desc desc{};
   int kind = kMapSmall;
@@ -686,6 +687,11 @@ loc_status loc_init_map(const loc_map_desc* d, void* hip_stream, loc_ctx** out) 
   c->macs = macs;
   c->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return LOC_E_HIP; }
+  if (noalloc_scratch(c->device, &c->noalloc_prefix) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return LOC_E_HIP;
+  }
   if (hipMalloc(&c->flags, sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     loc_destroy(c);
@@ -873,6 +879,23 @@ loc_status loc_resample(loc_ctx* c, const double* weight, int n_in, int n_out, u
   return timed(c, K_RESAMPLE, 0, 8.0 * n_in * 2 + 4.0 * n_out, [&] {
     return launch_resample(weight, n_in, n_out, seed, iter, c->prefix.p, idx_out, c->flags, c->stream);
   });
+}
+
+static_assert(LOC_NOALLOC_MAX_WEIGHTS == fl::kNoAllocMaxWeights, "scratch size");
+
+loc_status loc_resample_noalloc(loc_ctx* c, const double* weight, int n_in, int n_out, uint64_t seed,
+                                uint64_t iter, int32_t* idx_out) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (!weight || !idx_out) return fail(c, LOC_E_ARG, "null pointer argument");
+  if (n_in < 1 || n_in > LOC_NOALLOC_MAX_WEIGHTS || n_out < 1 || n_out > (1 << 24))
+    return fail(c, LOC_E_ARG, "n_in must be in [1, %d] (the fixed scratch) and n_out in [1, 2^24]",
+                LOC_NOALLOC_MAX_WEIGHTS);
+  if (!c->noalloc_prefix) return fail(c, LOC_E_STATE, "scratch address not resolved at init");
+  const hipError_t e = launch_resample(weight, n_in, n_out, seed, iter, c->noalloc_prefix, idx_out, c->flags,
+                                       c->stream);
+  if (e != hipSuccess) return fail(c, LOC_E_HIP, "launch of k_resample failed: %s", hipGetErrorString(e));
+  return LOC_OK;
 }
 
 loc_status loc_ray_outputs(loc_ctx* c, float* rgb, float* opacity, float* F, float* E) {
@@ -2080,6 +2103,11 @@ loc_status loc_init_grid_map(const loc_grid_desc* g, void* hip_stream, loc_ctx**
     hipDeviceProp_t prop;
     if (hipGetDevice(&c->device) == hipSuccess && hipGetDeviceProperties(&prop, c->device) == hipSuccess)
       c->n_cu = prop.multiProcessorCount;
+  }
+  if (noalloc_scratch(c->device, &c->noalloc_prefix) != hipSuccess) {
+    (void)hipGetLastError();
+    loc_destroy(c);
+    return LOC_E_HIP;
   }
   // resolutions N_l = floor(N_min b^l + 1e-6), b = exp((ln N_max - ln N_min) / (L - 1))
   GridDev& d = c->grid;

@@ -74,6 +74,7 @@ def test_update_and_resample_reject_null_context(lib):
     assert lib.loc_update_particles(None, None, ctypes.byref(cam), 1, 1, 1, None, None, 0.0, 0.0, 0, 0,
                                     None, None, None, None) == binding.LOC_E_ARG
     assert lib.loc_resample(None, None, 1, 1, 0, 0, None) == binding.LOC_E_ARG
+    assert lib.loc_resample_noalloc(None, None, 1, 1, 0, 0, None) == binding.LOC_E_ARG
     assert lib.loc_sync(None, None) == binding.LOC_E_ARG
     assert lib.loc_ray_outputs(None, None, None, None, None) == binding.LOC_E_ARG
     lib.loc_destroy(None)
