@@ -93,22 +93,154 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(spec, params, img, cam, B, poses, seed, n_particles):
-    """The FP64 oracle, as it stands, timed on a bounded sample of the same
-    workload; scaled to MLP samples/s."""
-    from oracle import mcl
+def _cpu_info():
+    """Host CPU model, logical CPU count and the CPUs this process may use."""
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    t0 = time.perf_counter()
-    mcl.update_particles(spec, params, img, cam, 1, B, poses, seed=seed, it=0, subset=list(range(n_particles)))
-    dt = time.perf_counter() - t0
-    samples = n_particles * B * (spec["n_coarse"] + spec["n_fine"])
-    return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d particles x %d rays x (%d + %d) samples, float64 numpy, %.1f s"
-                      % (n_particles, poses.shape[0], B, spec["n_coarse"], spec["n_fine"], dt)}
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+# the box's CPU share for one GPU: worker pools stay within it whatever the
+# host's CPU count
+CPU_SHARE = 16
+
+
+def _worker_init():
+    from threadpoolctl import threadpool_limits
+    global _BLAS_LIMIT
+    _BLAS_LIMIT = threadpool_limits(1)     # one BLAS thread per worker process
+
+
+def _oracle_chunk(job):
+    """One worker's share of a weighting pass: the oracle on a subset of the
+    particles (the pixel set and streams are keyed by particle index, so any
+    split gives the same per-particle results)."""
+    from oracle import mcl
+    spec, params, img, cam, inv_R, B, poses, seed, it, sub, proposal = job
+    o = mcl.update_particles(spec, params, img, cam, inv_R, B, poses, seed=seed, it=it, subset=sub,
+                             proposal=proposal)
+    return o["loglik"], o["uncert"], o["pose"]
+
+
+def _oracle_update(pool, spec, params, img, cam, inv_R, B, poses, seed, it, sub, proposal=None):
+    """The oracle's weighting pass over the particles `sub`, in one process
+    (pool None) or split into contiguous chunks over the pool's workers."""
+    from oracle import mcl
+    if pool is None:
+        o = mcl.update_particles(spec, params, img, cam, inv_R, B, poses, seed=seed, it=it, subset=sub,
+                                 proposal=proposal)
+        return o["loglik"], o["uncert"], o["pose"]
+    k = pool._processes
+    chunks = [c for c in np.array_split(np.asarray(sub), k) if len(c)]
+    parts = pool.map(_oracle_chunk, [(spec, params, img, cam, inv_R, B, poses, seed, it, [int(i) for i in c],
+                                      proposal) for c in chunks])
+    return (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
+            np.concatenate([p[2] for p in parts]))
+
+
+def _oracle_levels(pool, spec, params, img, cam, levels, poses, seed):
+    """The coarse-to-fine update of the oracle (mcl.update_levels: weighting,
+    1-sigma rejection, normalisation, resampling per level) with each level's
+    weighting split over the pool."""
+    from oracle import mcl
+    X = np.asarray(poses, dtype=np.float64)
+    for L, (inv_R, B, n_out) in enumerate(levels):
+        ll, un, P = _oracle_update(pool, spec, params, img, cam, inv_R, B, X, seed, L, list(range(X.shape[0])))
+        ll, _ = mcl.reject_1sigma(un, ll)
+        idx = mcl.resample(mcl.normalise(ll), n_out, seed, L)
+        X = P[idx]
+    return X
+
+
+def cpu_baselines(args):
+    """The FP64 oracle, as it stands, timed on the host's cores before the GPU
+    is touched: single-threaded (one process, BLAS limited to one thread) and
+    on all usable cores up to the box's share (CPU-only worker processes,
+    one BLAS thread each, particles split into contiguous chunks).
+    Workloads: the headline BF16 + proposal workload (64 coarse + 32
+    proposal-placed samples, seeded untrained proposal; the same particles,
+    pixels and jitter) on a fixed subset of particles, extrapolated linearly
+    to the full set (work is linear in the particle count); the small
+    workload (32 particles x 16 rays x 32 samples) and the coarse-to-fine
+    workload (1000 -> 300 -> 100 particles, 16/64/256 rays, 1-sigma
+    rejection, resampling) in full."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from paper_2406_12202_amd import synth
+    info = _cpu_info()
+    n_workers = max(1, min(CPU_SHARE, info["usable_cpus"]))
+    seed = args.seed
+    # headline workload
+    spec_p = synth.spec("proposal")
+    params = synth.map_params(spec_p, seed)
+    cam = synth.camera("proposal")
+    img = synth.observation("proposal", seed)
+    poses = synth.particles("proposal", seed)
+    theta = synth.proposal_params(seed)
+    Wp = synth.WORKLOADS["proposal"]
+    N, B, S = Wp["N"], Wp["B"], spec_p["n_coarse"] + spec_p["n_fine"]
+    n_sub1 = args.cpu_particles or 6
+    n_subk = max(n_workers * 2, n_sub1)
+    # small workload
+    spec_s = synth.spec("small")
+    par_s = synth.map_params(spec_s, seed)
+    cam_s = synth.camera("small")
+    img_s = synth.observation("small", seed)
+    pos_s = synth.particles("small", seed)
+    Ws = synth.WORKLOADS["small"]
+    # coarse-to-fine workload
+    spec_c = synth.spec("c2f")
+    par_c = synth.map_params(spec_c, seed)
+    cam_c = synth.camera("c2f")
+    img_c = synth.observation("c2f", seed)
+    pos_c = synth.particles("c2f", seed)
+    levels = [(4, 16, 300), (2, 64, 100), (1, 256, 100)]
+    c2f_samples = 32 * (pos_c.shape[0] * 16 + 300 * 64 + 100 * 256)
+    c2f_parts = pos_c.shape[0] + 300 + 100
+
+    def runs(pool):
+        r = {}
+        n_sub = n_sub1 if pool is None else n_subk
+        t0 = time.perf_counter()
+        _oracle_update(pool, spec_p, params, img, cam, 1, B, poses, seed, 0, list(range(n_sub)), theta)
+        dt = time.perf_counter() - t0
+        r["headline"] = {"samples_per_s": n_sub * B * S / dt, "particle_updates_per_s": n_sub / dt,
+                         "seconds": dt, "particles_timed": n_sub,
+                         "extrapolated_ms_per_update": 1e3 * dt * N / n_sub}
+        t0 = time.perf_counter()
+        _oracle_update(pool, spec_s, par_s, img_s, cam_s, 1, Ws["B"], pos_s, seed, 0, list(range(pos_s.shape[0])))
+        dt = time.perf_counter() - t0
+        r["small_full"] = {"samples_per_s": pos_s.shape[0] * Ws["B"] * 32 / dt,
+                           "particle_updates_per_s": pos_s.shape[0] / dt, "ms_per_update": 1e3 * dt}
+        t0 = time.perf_counter()
+        _oracle_levels(pool, spec_c, par_c, img_c, cam_c, levels, pos_c, seed)
+        dt = time.perf_counter() - t0
+        r["c2f_full"] = {"samples_per_s": c2f_samples / dt, "particle_updates_per_s": c2f_parts / dt,
+                         "ms_per_update": 1e3 * dt}
+        return r
+
+    with threadpool_limits(1):
+        single = runs(None)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(n_workers, initializer=_worker_init) as pool:
+        pool.map(_oracle_chunk, [(spec_s, par_s, img_s, cam_s, 1, 2, pos_s, seed, 0, [0], None)] * n_workers)
+        multi = runs(pool)
+    return {"value": multi["headline"]["samples_per_s"], "unit": "samples/s", "cores": n_workers, "kind": "oracle",
+            "sample": "headline workload (64 coarse + 32 proposal-placed samples, float64 numpy): %d of %d "
+                      "particles x %d rays on %d worker processes (%.1f s), extrapolated linearly in the "
+                      "particle count; small and coarse-to-fine workloads timed in full"
+                      % (n_subk, N, B, n_workers, multi["headline"]["seconds"]),
+            "host": info, "single_thread": single, "all_cores": multi}
 
 
 def time_path(ctx, img_d, cam, B, pose_a, steps, warmup, seed, torch):
@@ -563,6 +695,9 @@ def main():
         print("bench.py measures one GPU: the particle update is built and timed on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         return 2
+    cpu = None
+    if args.mode == "headline" and not args.no_cpu_baseline:
+        cpu = cpu_baselines(args)       # before the GPU is touched: worker processes stay CPU-only
     import torch
     if args.mode == "copy":
         return copy_reference(args, torch)
@@ -651,9 +786,8 @@ def main():
                "fp32_plain": {"samples_per_s": r32["samples_per_s"], "ms_per_step": r32["ms_per_step"],
                               "particle_updates_per_s": r32["particle_updates_per_s"],
                               "roofline": r32["roofline"], "kernels": r32["kernels"], "flags": fl32}}
-    if not args.no_cpu_baseline:
-        n_cpu = args.cpu_particles or (48 if wl == "nerf" else 32)
-        out["cpu_baseline"] = cpu_baseline(spec, params, img, cam, B, poses, args.seed, n_cpu)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 

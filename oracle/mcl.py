@@ -95,9 +95,13 @@ def unpack_map(spec, params):
 
 
 def map_eval(spec, P, x, d):
-    """sigma and rgb of the map at points x seen along d."""
+    """sigma and rgb of the map at points x seen along d; spec["precision"] ==
+    "bf16" evaluates the NeRF map in its BF16 configuration (render.mlp_bf16),
+    otherwise in float64."""
     if spec.get("map_type") == "grid":
         return gr.mlp(spec, P, x, d)
+    if spec.get("precision") == "bf16":
+        return rd.mlp_bf16(spec, P, x, d)
     return rd.mlp(spec, P, x, d)
 
 

@@ -116,6 +116,56 @@ def mlp(spec, P, x, d):
     return sigma, rgb
 
 
+def round_bf16(x):
+    """Nearest bfloat16 value (8 significant bits, ties to even; the float32
+    exponent range): with x = m 2^e, 1/2 <= |m| < 1, the value
+    rint(m 2^8) 2^(e - 8), where rint rounds halves to even."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)
+    e = np.maximum(e, -125)            # below 2^-126 the spacing stays 2^-133
+    m = np.ldexp(x, -e)
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+def split_bf16(w):
+    """A weight carried as two bfloat16 numbers: hi = bf16(w), lo = bf16(w - hi)."""
+    hi = round_bf16(w)
+    return hi + round_bf16(np.asarray(w, dtype=np.float64) - hi)
+
+
+def mlp_bf16(spec, P, x, d):
+    """The map in the BF16 configuration: every product of a hidden, feature
+    or direction layer multiplies bfloat16 operands -- the encodings
+    gamma(x), gamma(d), the layer's weights and the previous layer's output,
+    each rounded to the nearest bfloat16 -- and sums them with the float32
+    bias exactly (float32 accumulation on the device); each layer's output
+    (after ReLU where the layer has one) is rounded to bfloat16 as the next
+    layer's input.  The density and colour heads act on those bfloat16
+    activations with weights carried as a pair of bfloat16 numbers
+    (split_bf16).  softplus and sigmoid as in mlp."""
+    r = round_bf16
+    gx = r(posenc(x, spec["L_xyz"]))
+    gd = r(posenc(d, spec["L_dir"]))
+    h = gx
+    for l in range(spec["n_layers"]):
+        if l == spec["skip_layer"] and l > 0:
+            h = np.concatenate([h, gx], axis=-1)
+        W, b = P["h%d" % l]
+        h = r(np.maximum(h @ r(W).T + b, 0.0))
+    ws, bs = P["sigma"]
+    sigma = softplus(h @ split_bf16(ws).T + bs)[:, 0]
+    if spec["dir_width"] > 0:
+        Wf, bf = P["feature"]
+        f = r(h @ r(Wf).T + bf)
+        Wv, bv = P["dir"]
+        g = r(np.maximum(np.concatenate([f, gd], axis=-1) @ r(Wv).T + bv, 0.0))
+    else:
+        g = np.concatenate([h, gd], axis=-1)
+    Wc, bc = P["rgb"]
+    rgb = sigmoid(g @ split_bf16(Wc).T + bc)
+    return sigma, rgb
+
+
 def pixel_ray(pose, u, v, fx, fy, cx, cy):
     """Camera ray through pixel (u, v) of a pinhole camera with intrinsics
     (fx, fy, cx, cy) (Eq. 4: r(p, x) with intrinsics K).  OpenGL convention

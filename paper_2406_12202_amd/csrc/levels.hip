@@ -300,12 +300,13 @@ k_level_rays(const LevelRayArgs a) {
       }
       f32x16 hacc[NTL];
       head_tile_r<NTL>(s_w + LS::HEAD_BLOCK * 64, bias + LS::HEAD_BIAS + h * 16, xa, gdt, lane, hacc);
-      // head rows 0..3 of tile h: half 0 holds them for both tiles
+      // head rows 0..3 of tile h (each the sum of a weight row's high and
+      // low bf16 parts, rows r and r + 8): half 0 holds them for both tiles
       float hv[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float t1 = __shfl(hacc[1][v], n, 64);
-        hv[v] = h ? t1 : hacc[0][v];
+        const float t1 = __shfl(hacc[1][v] + hacc[1][v + 4], n, 64);
+        hv[v] = h ? t1 : hacc[0][v] + hacc[0][v + 4];
       }
       // everything below reads only lanes of the same half before the
       // shuffles of the next pair

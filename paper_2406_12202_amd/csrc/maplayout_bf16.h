@@ -22,7 +22,10 @@
 // (density, over the trunk output) and 1..3 (colour, over the trunk output
 // and gamma(d)), KBH + KBD blocks; a map with a direction layer has a density
 // tile (row 0 over the trunk output, KBH blocks) and a colour tile (rows 0..2
-// over the direction layer's output, DW / 16 blocks).
+// over the direction layer's output, DW / 16 blocks).  A head weight w is
+// stored as hi = bf16(w) in its row r and lo = bf16(w - hi) in row r + 8
+// (bias 0), so a head output is the sum of two accumulator rows (values v and
+// v + 4 of lane half 0) and the head weights keep 16 significant bits.
 #pragma once
 
 namespace fl {

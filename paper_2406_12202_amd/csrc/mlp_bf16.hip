@@ -12,7 +12,10 @@
 // bias enters as the accumulator input of the first MFMA of a tile, and ReLU
 // runs on packed bf16 pairs after rounding, so the epilogue of a tile is one
 // conversion and one packed max per pair of outputs.  The density and colour
-// heads are tiles of the same stream, evaluated on MFMA like the layers.
+// heads are tiles of the same stream, evaluated on MFMA like the layers, with
+// each head weight split into a high and a low bf16 part in two rows of the
+// tile (the density head carries the map's density gain, so its weights keep
+// 16 significant bits; the tile has rows to spare).
 #include "mfma_util.h"
 #include "maplayout_bf16.h"
 
@@ -229,21 +232,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
       for (int i = 0; i < S::KBH; ++i) xa[nt][i] = xb[nt][i];
   }
   // heads: rows of the head tiles in lanes of half 0 (density row 0; colour
-  // rows 1..3 of the single tile, or rows 0..2 of the colour tile)
+  // rows 1..3 of the single tile, or rows 0..2 of the colour tile); each
+  // head weight is a pair of bf16 numbers whose low parts sit 8 rows further
+  // down (accumulator values v + 4), so a head output is the sum of two rows
   float sigma[NTL], rgb[NTL][3];
   f32x16 hacc[NTL];
   if constexpr (S::DW == 0) {
     head_b<NTL, WAVES, S::KBH, S::KBD>(st, bias + S::SIG_BIAS + h * 16, NextGroup{0, 0}, xa, s_gd[wv], hacc);
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt) {
-      sigma[nt] = softplus_b(hacc[nt][0]);
+      sigma[nt] = softplus_b(hacc[nt][0] + hacc[nt][4]);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][1 + c]);
+      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][1 + c] + hacc[nt][5 + c]);
     }
   } else {
     head_b<NTL, WAVES, S::KBH, 0>(st, bias + S::SIG_BIAS + h * 16, first_group<S, MPC>(S::D), xa, nullptr, hacc);
 #pragma unroll
-    for (int nt = 0; nt < NTL; ++nt) sigma[nt] = softplus_b(hacc[nt][0]);
+    for (int nt = 0; nt < NTL; ++nt) sigma[nt] = softplus_b(hacc[nt][0] + hacc[nt][4]);
     dense_b<S, NTL, WAVES, MPC, S::MT, S::KBH, S::KBD, S::KBH, false>(
         st, S::block_base(S::D), bias + S::bias_base(S::D) + h * 16, false, false, first_group<S, MPC>(S::D + 1),
         xa, nullptr, s_gd[wv], xb);
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_bf16(const MlpArgs a) {
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][c]);
+      for (int c = 0; c < 3; ++c) rgb[nt][c] = sigmoid_b(hacc[nt][c] + hacc[nt][4 + c]);
   }
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt)

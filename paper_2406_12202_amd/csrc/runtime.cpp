@@ -351,10 +351,20 @@ PackedB pack_map_bf16(const loc_map_desc& d) {
           P.bias[S::bias_base(l) + (mt * 2 + h) * 16 + v] = cn.b[ci][32 * mt + 8 * (v / 4) + 4 * h + v % 4];
   }
   {
-    // tail tiles (maplayout_bf16.h): row r of a tile, lane half h, slot q
+    // tail tiles (maplayout_bf16.h): row r of a tile, lane half h, slot q.
+    // A head weight w is carried as two bf16 numbers, hi = bf16(w) in row r
+    // and lo = bf16(w - hi) in row r + 8 (16 significant bits in all); the
+    // kernels add the two rows' float32 sums
     const int ci = (int)cn.W.size() - 1;   // colour head
     auto put = [&](long blk0, int kb, int lane, int q, float v) {
-      P.blocks[(size_t)((blk0 + kb) * 64 + lane) * 8 + q] = to_bf16(v);
+      const int row = lane % 32;
+      if (row >= 8) return;
+      const uint16_t hi = to_bf16(v);
+      const uint32_t hb = (uint32_t)hi << 16;
+      float hv;
+      std::memcpy(&hv, &hb, 4);
+      P.blocks[(size_t)((blk0 + kb) * 64 + lane) * 8 + q] = hi;
+      P.blocks[(size_t)((blk0 + kb) * 64 + lane + 8) * 8 + q] = to_bf16(v - hv);
     };
     for (int kb = 0; kb < S::SIG_KB; ++kb)
       for (int lane = 0; lane < 64; ++lane)

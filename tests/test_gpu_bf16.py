@@ -1,31 +1,39 @@
 """GPU parity of the BF16 map path (bf16 weights and activations on MFMA,
-float32 accumulation, float32 compositing) against the FP64 oracle.
+float32 accumulation, float32 compositing) against two oracles.
 
-The BF16 path approximates the map on purpose, so the bar is an error budget
-(derivation in the design notes) rather than rounding-level agreement.  The
-density logit is the 256-term head product times the synthetic map's density
-gain (16), so bf16 rounding (2^-9 per value) reaches the optical depth as a
-relative error of up to EPS_TAU = 0.15:
-  opacity A           : |dA| <= (1 - A) tau EPS_TAU + 2e-3 for 99% of rays
-                        (tau = -ln(1 - A) of the oracle), all |dA| <= 5e-2
-  colour C            : p99 <= 4e-2, max <= 5e-2
-  uncertainty F       : per ray |dF| <= EPS_TAU (|ln(1-alpha)| / sigma_trans +
-                        |ln alpha| / sigma_opaque) + 2e-3 for 99% of rays, where
-                        sigma_* are the oracle's densities at the two Eq. 5
-                        crossings: a relative error eps of the optical depths
-                        moves each crossing by |ln L| eps / sigma (first order);
-                        p50 <= 5e-3
-  log-likelihood l    : within the bound propagated from the per-ray errors,
-                        4 sum_j |E F (gpu) - E F (oracle)| / min(S) + 1e-3, and
-                        consistent with the GPU's own per-ray E and F
+1. The FP64 oracle, with an error budget: the BF16 path approximates the map
+   on purpose.  A CPU evaluation of the map with exactly the BF16
+   configuration's roundings (oracle render.mlp_bf16) shows how large that
+   approximation is on its own, and the bars below hold it with margin on
+   every workload (measured maxima in tests/TOLERANCES.md):
+     colour C, opacity A : p99 <= 2e-2
+     opacity A           : 99% of rays within (1 - A) tau EPS_TAU + 2e-3
+                           (tau = -ln(1 - A) of the oracle: a relative
+                           optical-depth error EPS_TAU = 0.1)
+     uncertainty F       : 99% of rays within EPS_TAU (|ln(1-alpha)| /
+                           sigma_trans + |ln alpha| / sigma_opaque) + 2e-3,
+                           sigma_* the oracle's densities at the two Eq. 5
+                           crossings (a relative optical-depth error eps moves
+                           the crossing of level L by |ln L| eps / sigma);
+                           median <= 2e-3
+     log-likelihood l    : |dl| <= 0.1, and consistent with the GPU's own
+                           per-ray E and F
+     weights (Eq. 3)     : |dw| <= 5e-3, the weights of a sampled subset
+                           renormalised over the subset on both sides
+2. The BF16-configuration oracle (the same roundings, float64 sums), which
+   must agree far more closely: what remains is float32 accumulation order
+   and the kernels' float32 positions and encodings, which move some of the
+   highest-band encoding values across a bf16 rounding boundary.
+     C, A: p99 <= 4e-3, max <= 1e-2; F: p99 <= 2e-2; l: <= 1e-2; w: <= 2e-3
 Structural mistakes (a missing k-block, a permuted feature) move colours by
-O(0.1-1) and fail these bounds; bf16 rounding moves them by O(1e-3 - 1e-2).
+O(0.1 - 1) and fail both.
 """
 import math
 import numpy as np
 import pytest
 
-from parity_util import ctx, frac_over, inputs, run_gpu, run_oracle, stats
+from oracle import mcl, se3
+from parity_util import ctx, gt_observation, inputs, run_gpu, run_oracle, stats
 
 pytestmark = pytest.mark.gpu
 
@@ -37,19 +45,28 @@ def torch_dev():
     return torch
 
 
-EPS_TAU = 0.15
+EPS_TAU = 0.1
+FP64_BARS = dict(C_P99=2e-2, A_P99=2e-2, F_P50=2e-3, L_MAX=0.1, W_MAX=5e-3)
+FIDELITY_BARS = dict(C_P99=4e-3, C_MAX=1e-2, F_P99=2e-2, L_MAX=1e-2, W_MAX=2e-3)
 
 
-def _check(g, o, alpha=0.05, subset=None):
+def _subset_weights(ll):
+    ll = np.asarray(ll, dtype=np.float64)
+    e = np.exp(ll - ll.max())
+    return e / e.sum()
+
+
+def _check(g, o, alpha=0.05, subset=None, o16=None):
     idx = list(range(g["loglik"].shape[0])) if subset is None else list(subset)
     rC = stats("C", g["C"][idx], o["C"])
     rA = stats("A", g["A"][idx], o["A"])
     rF = stats("F", g["F"][idx], o["F"])
     stats("E", g["E"][idx], o["E"])
     rL = stats("loglik", g["loglik"][idx], o["loglik"])
+    dw = np.abs(_subset_weights(g["loglik"][idx]) - o["weight"])
+    print("weight     max=%.3e" % dw.max())
     assert np.allclose(g["pose"][idx].reshape(len(idx), 12), o["pose"].reshape(len(idx), 12), atol=1e-12, rtol=0)
-    assert rC["p99"] <= 4e-2 and rC["max"] <= 5e-2
-    assert rA["max"] <= 5e-2
+    assert rC["p99"] <= FP64_BARS["C_P99"] and rA["p99"] <= FP64_BARS["A_P99"]
     # opacity: a relative optical-depth error EPS_TAU moves A = 1 - e^-tau by
     # (1 - A) tau EPS_TAU (at most EPS_TAU / e)
     Ao = np.clip(o["A"], 0.0, 1.0 - 1e-12)
@@ -65,17 +82,33 @@ def _check(g, o, alpha=0.05, subset=None):
     inside = (dF <= bound).mean()
     print("F within conditioning bound: %.4f of %d rays" % (inside, dF.size))
     assert inside >= 0.99 or (dF.size < 100 and (dF > bound).sum() <= 1)
-    assert rF["p50"] <= 5e-3
-    # log-likelihood: GPU-internal consistency and the propagated bound
+    assert rF["p50"] <= FP64_BARS["F_P50"]
+    # log-likelihood: GPU-internal consistency and the bar against the oracle
     EFg = (g["E"][idx] * g["F"][idx]).astype(np.float64)
-    EFo = o["E"] * o["F"]
     B = EFg.shape[1]
-    Sg, So = EFg.sum(1), EFo.sum(1)
-    assert np.allclose(g["loglik"][idx], 4 * (math.log(B) - np.log(np.maximum(Sg, 1e-12))), atol=1e-4, rtol=0)
-    prop = 4 * np.abs(EFg - EFo).sum(1) / np.minimum(Sg, So) + 1e-3
-    assert np.all(np.abs(g["loglik"][idx] - o["loglik"]) <= prop)
-    if len(idx) >= 16:
-        assert rL["p50"] <= 5e-2
+    assert np.allclose(g["loglik"][idx], 4 * (math.log(B) - np.log(np.maximum(EFg.sum(1), 1e-12))), atol=1e-4,
+                       rtol=0)
+    assert rL["max"] <= FP64_BARS["L_MAX"]
+    assert dw.max() <= FP64_BARS["W_MAX"]
+    if o16 is not None:
+        print("-- against the BF16-configuration oracle")
+        fC = stats("C", g["C"][idx], o16["C"])
+        fA = stats("A", g["A"][idx], o16["A"])
+        fF = stats("F", g["F"][idx], o16["F"])
+        fL = stats("loglik", g["loglik"][idx], o16["loglik"])
+        fw = np.abs(_subset_weights(g["loglik"][idx]) - o16["weight"]).max()
+        print("weight     max=%.3e" % fw)
+        for r in (fC, fA):
+            assert r["p99"] <= FIDELITY_BARS["C_P99"] and r["max"] <= FIDELITY_BARS["C_MAX"]
+        assert fF["p99"] <= FIDELITY_BARS["F_P99"]
+        assert fL["max"] <= FIDELITY_BARS["L_MAX"] and fw <= FIDELITY_BARS["W_MAX"]
+
+
+def _both(spec, params, img, cam, inv_R, B, poses, subset=None, proposal=None, **kw):
+    o = run_oracle(spec, params, img, cam, inv_R, B, poses, subset=subset, proposal=proposal, **kw)
+    o16 = run_oracle(dict(spec, precision="bf16"), params, img, cam, inv_R, B, poses, subset=subset,
+                     proposal=proposal, **kw)
+    return o, o16
 
 
 def test_bf16_small_map(torch_dev):
@@ -83,16 +116,16 @@ def test_bf16_small_map(torch_dev):
     c = ctx(s, p, "bf16")
     kw = dict(seed=5, it=3)
     g = run_gpu(c, img, cam, 1, 16, poses, **kw)
-    o = run_oracle(s, p, img, cam, 1, 16, poses, **kw)
-    _check(g, o)
+    o, o16 = _both(s, p, img, cam, 1, 16, poses, **kw)
+    _check(g, o, o16=o16)
 
 
 def test_bf16_small_map_ragged(torch_dev):
     s, p, cam, poses, img = inputs("small", 22, N=3, n_coarse=37)
     c = ctx(s, p, "bf16")
     g = run_gpu(c, img, cam, 2, 5, poses, seed=1, it=1)
-    o = run_oracle(s, p, img, cam, 2, 5, poses, seed=1, it=1)
-    _check(g, o)
+    o, o16 = _both(s, p, img, cam, 2, 5, poses, seed=1, it=1)
+    _check(g, o, o16=o16)
 
 
 def test_bf16_maximum_ray_count_folded_launch(torch_dev):
@@ -104,8 +137,8 @@ def test_bf16_maximum_ray_count_folded_launch(torch_dev):
     kw = dict(seed=5, it=2)
     g = run_gpu(c, img, cam, 1, 1024, poses, **kw)
     sub = [0, 2047, 4095]
-    o = run_oracle(s, p, img, cam, 1, 1024, poses, subset=sub, **kw)
-    _check(g, o, subset=sub)
+    o, o16 = _both(s, p, img, cam, 1, 1024, poses, subset=sub, **kw)
+    _check(g, o, subset=sub, o16=o16)
     assert np.all(np.isfinite(g["loglik"]))
 
 
@@ -113,8 +146,8 @@ def test_bf16_nerf_map(torch_dev):
     s, p, cam, poses, img = inputs("nerf", 23, N=6)
     c = ctx(s, p, "bf16")
     g = run_gpu(c, img, cam, 1, 8, poses, seed=11, it=2)
-    o = run_oracle(s, p, img, cam, 1, 8, poses, seed=11, it=2)
-    _check(g, o)
+    o, o16 = _both(s, p, img, cam, 1, 8, poses, seed=11, it=2)
+    _check(g, o, o16=o16)
 
 
 def test_bf16_nerf_map_full_size_sampled(torch_dev):
@@ -122,8 +155,8 @@ def test_bf16_nerf_map_full_size_sampled(torch_dev):
     c = ctx(s, p, "bf16")
     g = run_gpu(c, img, cam, 1, 64, poses, seed=3, it=7)
     sub = [0, 137, 399]
-    o = run_oracle(s, p, img, cam, 1, 64, poses, subset=sub, seed=3, it=7)
-    _check(g, o, subset=sub)
+    o, o16 = _both(s, p, img, cam, 1, 64, poses, subset=sub, seed=3, it=7)
+    _check(g, o, subset=sub, o16=o16)
 
 
 def test_bf16_deterministic(torch_dev):
@@ -147,8 +180,8 @@ def test_bf16_proposal_one_launch_for_coarse_and_fine(torch_dev):
     c.loc_set_fine_mode(1)
     kw = dict(seed=3, it=2)
     g = run_gpu(c, img, cam, 1, 37, poses, **kw)
-    o = run_oracle(s, p, img, cam, 1, 37, poses, proposal=theta, **kw)
-    _check(g, o)
+    o, o16 = _both(s, p, img, cam, 1, 37, poses, proposal=theta, **kw)
+    _check(g, o, o16=o16)
 
 
 def test_bf16_proposal_ragged_fine_count(torch_dev):
@@ -163,8 +196,8 @@ def test_bf16_proposal_ragged_fine_count(torch_dev):
     c.loc_set_fine_mode(1)
     kw = dict(seed=6, it=1)
     g = run_gpu(c, img, cam, 1, 11, poses, **kw)
-    o = run_oracle(s, p, img, cam, 1, 11, poses, proposal=theta, **kw)
-    _check(g, o)
+    o, o16 = _both(s, p, img, cam, 1, 11, poses, proposal=theta, **kw)
+    _check(g, o, o16=o16)
 
 
 def test_bf16_proposal_full_size_sampled(torch_dev):
@@ -184,6 +217,58 @@ def test_bf16_proposal_full_size_sampled(torch_dev):
     c.loc_set_fine_mode(1)
     g = run_gpu(c, img, cam, 1, 64, poses, seed=2024, it=3)
     sub = [0, 199, 399]
-    o = run_oracle(s, p, img, cam, 1, 64, poses, subset=sub, proposal=theta, seed=2024, it=3)
-    _check(g, o, subset=sub)
+    o, o16 = _both(s, p, img, cam, 1, 64, poses, subset=sub, proposal=theta, seed=2024, it=3)
+    _check(g, o, subset=sub, o16=o16)
     assert abs(g["weight"].sum() - 1.0) < 1e-12
+
+
+def test_bf16_proposal_lockstep_pose(torch_dev):
+    """The headline configuration's filter in lockstep with the oracle (Alg.
+    1; pose errors as in Sec. IV-A): the 8x256 map in BF16 with a proposal
+    network trained on the map's own compositing weights (64 coarse + 32
+    proposal-placed samples), 64 particles x 64 rays, ten iterations with
+    motion noise sigma_t = 0.02 m, sigma_r = 1 deg (O = I), on the
+    forward-facing view whose query pixels are the oracle's render from the
+    true pose; particles start within +-1 m / +-30 deg.  Both sides weight the
+    same set and the oracle's draw carries it on.  At every iteration the
+    GPU's pose estimate lies within 1 cm / 0.5 deg of the oracle's and every
+    weight within 5e-3."""
+    from paper_2406_12202_amd import synth
+    torch = torch_dev
+    dev = torch.device("cuda", 0)
+    wl, seed, N, B, iters = "large", 71, 64, 64, 10
+    s = synth.spec(wl)
+    p = synth.map_params(s, seed)
+    cam = synth.camera(wl)
+    c = ctx(s, p, "bf16")
+    tp = torch.as_tensor(synth.training_poses(wl, seed, 2048), device=dev)
+    O, D = c.loc_cast_rays(cam, 1, 64, tp, seed=seed + 1, iter=0)
+    T = c.loc_teacher_histograms(O, D, 128, seed=seed + 1, iter=1)
+    c.loc_set_proposal(synth.proposal_params(seed))
+    c.loc_train_proposal(O, D, T, 4096, 1500, lr=2e-3)
+    theta = c.loc_get_proposal()
+    c.loc_set_fine_mode(1)
+    del O, D, T, tp
+    gt = synth.gt_pose(wl, seed)
+    img = gt_observation(s, p, cam, gt, B, seed, iters, synth.observation(wl, seed))
+    X = synth.particles(wl, seed, N=N)
+    sig_t, sig_r = 0.02, math.radians(1.0)
+    worst = (0.0, 0.0, 0.0)
+    for it in range(iters):
+        g = run_gpu(c, img, cam, 1, B, X, sigma_t=sig_t, sigma_r=sig_r, seed=seed, it=it)
+        o = run_oracle(s, p, img, cam, 1, B, X, sigma_t=sig_t, sigma_r=sig_r, seed=seed, it=it, proposal=theta)
+        assert np.allclose(g["pose"].reshape(N, 12), o["pose"].reshape(N, 12), atol=1e-12, rtol=0)
+        pose_d = torch.as_tensor(np.ascontiguousarray(g["pose"]), device=dev)
+        w_d = torch.as_tensor(np.ascontiguousarray(g["weight"]), device=dev)
+        est_g = c.loc_pose_estimate(pose_d, w_d).cpu().numpy()
+        est_o = se3.pose_estimate(o["pose"], o["weight"])
+        dt, dr = se3.pose_errors(est_g, est_o)
+        dw = float(np.abs(g["weight"] - o["weight"]).max())
+        gt_t, gt_r = se3.pose_errors(est_o, gt)
+        print("iter %d: GPU vs oracle %.5f m %.4f deg | max |dw| %.3e | max |dl| %.3e | oracle vs truth %.3f m "
+              "%.2f deg" % (it, dt, dr, dw, np.abs(g["loglik"] - o["loglik"]).max(), gt_t, gt_r), flush=True)
+        worst = (max(worst[0], dt), max(worst[1], dr), max(worst[2], dw))
+        assert dt <= 0.01 and dr <= 0.5 and dw <= 5e-3, (it, dt, dr, dw)
+        X = o["pose"][mcl.resample(o["weight"], N, seed, it)]
+    print("worst over iterations: %.5f m %.4f deg, |dw| %.3e" % worst)
+    c.close()

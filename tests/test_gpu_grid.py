@@ -5,12 +5,19 @@ The grid path computes in float32: the cell coordinate p = u N_l carries a
 relative rounding of about 2^-24 times N_l (up to 2048), so the trilinear
 weights move by up to ~1.2e-4 and a level's features, which are continuous
 across cell faces, by that times the spread of the corner entries (up to ~3
-for N(0, 0.5^2) entries), ~4e-4; the tiny MLP and the density gain carry that
-into colour and opacity with a gain of a few on the rays whose density is
-steep.  Tolerances: colour and opacity p99 5e-4 (the measured bulk, 1e-4 at
-p99) and max 2e-3 (the bound above for the steepest rays), F: 99% of rays
-within 2e-3 and all within 0.1 (thin-density crossings amplify rounding as
-for the NeRF map), log-likelihood 1e-2, weights 5e-2 relative above 1e-6.
+for N(0, 0.5^2) entries), ~4e-4; the tiny MLP's density logit takes them
+with a gain of about 3, and softplus turns a logit error dz into a relative
+density error of at most dz, so each sample's optical depth carries a
+relative error of about 1e-3 per level: EPS_GRID = 4e-3 over 16 levels of
+independent signs.  Per ray, a relative optical-depth error eps moves the
+opacity A = 1 - e^-tau by (1 - A) tau eps, and the colour by as much plus
+the colour head's own share of the feature error (sigmoid slope <= 1/4 on a
+logit error of ~1e-3).  Bars: every ray within (1 - A) tau EPS_GRID + 1e-4
+(opacity) and + 3e-4 (colour), tau = -ln(1 - A) of the oracle; colour and
+opacity p99 <= 5e-4; F: 99% of rays within 2e-3 and all within 0.1
+(thin-density crossings amplify rounding as for the NeRF map);
+log-likelihood 1e-3; weights 1e-4 absolute (a weight moves by at most
+w (1 - w) |dl| <= |dl| / 4).
 """
 import numpy as np
 import pytest
@@ -21,7 +28,8 @@ from parity_util import frac_over, stats
 
 pytestmark = pytest.mark.gpu
 
-TOL = dict(C=5e-4, C_MAX=2e-3, F=2e-3, F_MAX=0.1, L=1e-2, W=5e-2)
+TOL = dict(C=5e-4, F=2e-3, F_MAX=0.1, L=1e-3, W=5e-2)
+EPS_GRID = 4e-3
 
 
 @pytest.fixture(scope="module")
@@ -53,7 +61,17 @@ def _compare(g, o, idx):
     rF = stats("F", g["F"][idx], o["F"])
     rL = stats("loglik", g["loglik"][idx], o["loglik"])
     assert rC["p99"] <= TOL["C"] and rA["p99"] <= TOL["C"]
-    assert rC["max"] <= TOL["C_MAX"] and rA["max"] <= TOL["C_MAX"]
+    Ao = np.clip(o["A"], 0.0, 1.0 - 1e-12)
+    tau_term = (1.0 - Ao) * -np.log1p(-Ao) * EPS_GRID
+    okA = np.abs(g["A"][idx] - o["A"]) <= tau_term + 1e-4
+    okC = np.all(np.abs(g["C"][idx] - o["C"]) <= tau_term[..., None] + 3e-4, axis=-1)
+    print("rays within the per-ray bound: opacity %.4f, colour %.4f of %d" % (okA.mean(), okC.mean(), okA.size))
+    assert okA.all() and okC.all()
+    ll = g["loglik"][idx]
+    ws = np.exp(ll - ll.max())
+    dw = np.abs(ws / ws.sum() - o["weight"]).max()
+    print("weight     max=%.3e" % dw)
+    assert dw <= 1e-4
     assert frac_over(g["F"][idx], o["F"], TOL["F"]) <= 0.01
     assert rF["max"] <= TOL["F_MAX"]
     assert rL["max"] <= TOL["L"]
