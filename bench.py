@@ -587,19 +587,20 @@ def bench_room(args, torch):
             for k, g in enumerate(gts)]
     ctxs = {}
 
-    def ctx_for(tau):
-        if tau not in ctxs:
-            ctxs[tau] = binding.Context(dict(spec, tau=tau), params, precision="bf16", stream=stream)
-        return ctxs[tau]
+    def ctx_for(tau, mode=0):
+        if (tau, mode) not in ctxs:
+            ctxs[(tau, mode)] = binding.Context(dict(spec, tau=tau), params, precision="bf16", stream=stream)
+            ctxs[(tau, mode)].loc_set_empty_ray_uncertainty(mode)
+        return ctxs[(tau, mode)]
 
-    def run(tau, stages, n0=None):
-        c = ctx_for(tau)
+    def run(tau, stages, n0=None, mode=0, spread=(1.0, 15.0)):
+        c = ctx_for(tau, mode)
         stages = [tuple(g) for g in stages]
         if n0 is not None:
             stages[0] = (stages[0][0], stages[0][1], n0, stages[0][3])
         res = []
         for k, gt in enumerate(gts):
-            p0 = torch.as_tensor(synth.room_particles(args.seed + k, stages[0][2], gt, 1.0, 15.0), device=dev)
+            p0 = torch.as_tensor(synth.room_particles(args.seed + k, stages[0][2], gt, *spread), device=dev)
             w0 = time.perf_counter()
             out = c.loc_localize(imgs[k], cam, stages, args.iters, p0.contiguous(), sigma_t=sigma_t, sigma_r=sigma_r,
                                  seed=args.seed + k)
@@ -625,6 +626,18 @@ def bench_room(args, torch):
     ablation = {"full": tau_sweep["0.1"], "wo_rejection": tau_sweep["%g" % far_near],
                 "wo_c2f": run(0.1, ROOM_SINGLE), "wo_both": run(far_near, ROOM_SINGLE)}
     print("# ablation: %s" % json.dumps(ablation), flush=True)
+    # the other reading of Eq. 5 for rays whose opacity never reaches alpha:
+    # F = far - near instead of tau (without rejection weighting F is
+    # constant either way)
+    ablation_span = {"full": run(0.1, ROOM_STAGES, mode=1), "wo_c2f": run(0.1, ROOM_SINGLE, mode=1)}
+    print("# ablation, empty rays maximally uncertain: %s" % json.dumps(ablation_span), flush=True)
+    # a wide start, +-3.5 m (+-1.75 m vertically) and +-30 deg: about a tenth
+    # of the particles start behind a wall, outside the trained room
+    wide = (3.5, 30.0)
+    ablation_wide = {"full": run(0.1, ROOM_STAGES, spread=wide), "wo_rejection": run(far_near, ROOM_STAGES, spread=wide),
+                     "wo_c2f": run(0.1, ROOM_SINGLE, spread=wide), "wo_both": run(far_near, ROOM_SINGLE, spread=wide),
+                     "full_empty_rays_span": run(0.1, ROOM_STAGES, mode=1, spread=wide)}
+    print("# ablation, wide start: %s" % json.dumps(ablation_wide), flush=True)
     out = {"metric": "localisation on a trained room map: time per update step (with accuracy sweeps)",
            "value": ablation["full"]["ms_per_step"], "unit": "ms/step", "n_gpus": 1, "steps": args.iters,
            "warmup": 1, "ms_per_step": ablation["full"]["ms_per_step"], "higher_is_better": False,
@@ -634,7 +647,8 @@ def bench_room(args, torch):
                                   "and 9600/600/100 particles; %d iterations, %d true poses" % (args.iters, args.trials)},
            "training": {"steps": 3000, "batch": 2048, "rays": int(O.shape[0]), "seconds": train_s,
                         "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
-           "tau_sweep": tau_sweep, "initial_particles": n_sweep, "ablation": ablation}
+           "tau_sweep": tau_sweep, "initial_particles": n_sweep, "ablation": ablation,
+           "ablation_empty_rays_span": ablation_span, "ablation_wide_start": ablation_wide}
     print(json.dumps(out), flush=True)
     for c in ctxs.values():
         c.close()

@@ -228,6 +228,18 @@ loc_status loc_resample(loc_ctx* ctx, const double* weight, int n_in, int n_out,
 loc_status loc_resample_noalloc(loc_ctx* ctx, const double* weight, int n_in, int n_out,
                                 uint64_t seed, uint64_t iter, int32_t* idx_out);
 
+/*
+ * Eq. 5 for a ray whose accumulated opacity never reaches alpha: the set
+ * defining z_trans is empty.  mode 0 (default): inf of the empty set is
+ * +inf, so the gap z_opaque - z_trans is -inf and F = tau (the smallest
+ * factor; an empty ray is scored by its colour error alone).  mode 1: such a
+ * ray has no transition from transparent to opaque in the sampled span and
+ * counts as maximally uncertain, F = far - near.  Applies to later update,
+ * level, localisation and render calls (a captured level graph is dropped).
+ * LOC_E_ARG for another mode.
+ */
+loc_status loc_set_empty_ray_uncertainty(loc_ctx* ctx, int mode);
+
 /* FP8 calibration of an LOC_FP8_E4M3 context (per-layer amax scaling): the
  * float32 map is evaluated at the midpoints of the n_coarse strata of each of
  * n_rays rays (o, d: DEVICE n_rays x 3 float32, e.g. loc_cast_rays output),

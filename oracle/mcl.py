@@ -152,6 +152,9 @@ def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False
             ts.append(tc[r])
             sigs.append(sig_c[s])
             rgbs.append(rgb_c[s])
+    # F of a ray whose opacity never reaches alpha: tau (inf of the empty set
+    # is +inf), or far - near under spec["empty_ray"] == "span"
+    empty = far - spec["near"] if spec.get("empty_ray") == "span" else None
     out = {k: np.zeros(B) for k in ("A", "z_trans", "z_opaque", "F", "sig_trans", "sig_opaque")}
     out["C"] = np.zeros((B, 3))
     if keep_samples:
@@ -159,7 +162,7 @@ def render_rays(spec, P, rays, keys, seed, it, proposal=None, keep_samples=False
     for r in range(B):
         w, logT, out["C"][r], out["A"][r] = rd.composite(ts[r], sigs[r], rgbs[r], far)
         out["z_trans"][r], out["z_opaque"][r] = rd.ray_quantiles(ts[r], sigs[r], logT, far, spec["alpha"])
-        out["F"][r] = rd.uncertainty(out["z_trans"][r], out["z_opaque"][r], spec["tau"])
+        out["F"][r] = rd.uncertainty(out["z_trans"][r], out["z_opaque"][r], spec["tau"], empty)
         out["sig_trans"][r], out["sig_opaque"][r] = rd.crossing_densities(ts[r], sigs[r], logT, spec["alpha"])
         if keep_samples:
             out["t"].append(ts[r])

@@ -240,11 +240,14 @@ def crossing_densities(t, sigma, logT, alpha):
     return st, so
 
 
-def uncertainty(z_trans, z_opaque, tau):
-    """F = max(z_opaque - z_trans, tau) (Sec. III-B, below Eq. 6); a ray that
-    never becomes non-transparent (z_trans = +inf) gets F = tau."""
+def uncertainty(z_trans, z_opaque, tau, empty=None):
+    """F = max(z_opaque - z_trans, tau) (Sec. III-B, below Eq. 6).  A ray that
+    never becomes non-transparent (z_trans = inf of the empty set = +inf)
+    gets F = tau; with ``empty`` given (the reading that such a ray has no
+    transparent-to-opaque transition in the sampled span and is maximally
+    uncertain, far - near) it gets F = empty."""
     if not np.isfinite(z_trans):
-        return float(tau)
+        return float(tau if empty is None else empty)
     return float(max(z_opaque - z_trans, tau))
 
 

@@ -24,7 +24,7 @@ EXPORTS = ["loc_init_map", "loc_update_particles", "loc_resample", "loc_resample
            "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
            "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
            "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-           "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map"]
+           "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map", "loc_set_empty_ray_uncertainty"]
 SMALL_MAP_PARAMS = 15345
 PROPOSAL_PARAMS = 11296
 
@@ -104,6 +104,7 @@ def load(path=LIB_PATH):
                                          c_dbl, c_dbl, c_u64, c_u64, vp, vp, vp, vp]
     lib.loc_resample.argtypes = [vp, vp, c_int, c_int, c_u64, c_u64, vp]
     lib.loc_resample_noalloc.argtypes = [vp, vp, c_int, c_int, c_u64, c_u64, vp]
+    lib.loc_set_empty_ray_uncertainty.argtypes = [vp, c_int]
     lib.loc_ray_outputs.argtypes = [vp, vp, vp, vp, vp]
     lib.loc_sync.argtypes = [vp, ctypes.POINTER(c_int)]
     lib.loc_set_profiling.argtypes = [vp, c_int]
@@ -149,7 +150,8 @@ def load(path=LIB_PATH):
               "loc_proposal_grad", "loc_train_proposal", "loc_gather_poses", "loc_pose_estimate", "loc_calibrate_fp8", "loc_fp8_scales",
               "loc_update_levels", "loc_set_graph_mode", "loc_level_outputs", "loc_level_ray_outputs",
               "loc_autotune_levels", "loc_set_level_tiles", "loc_position_variance", "loc_render_image",
-              "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map"):
+              "loc_localize", "loc_map_grad", "loc_train_map", "loc_get_map", "loc_init_grid_map",
+              "loc_set_empty_ray_uncertainty"):
         getattr(lib, f).restype = c_int
     _LIB = lib
     return lib
@@ -282,6 +284,10 @@ class Context:
                                            _ptr(idx_out, torch.int32, n_out, "idx_out"))
         self._check(st, "loc_resample_noalloc")
         return idx_out
+
+    def loc_set_empty_ray_uncertainty(self, mode):
+        """0: F = tau for a ray whose opacity never reaches alpha; 1: F = far - near."""
+        self._check(self.lib.loc_set_empty_ray_uncertainty(self.h, int(mode)), "loc_set_empty_ray_uncertainty")
 
     def loc_ray_outputs(self):
         """Per-ray (rgb (N,B,3), opacity (N,B), F (N,B), E (N,B)) of the last update."""

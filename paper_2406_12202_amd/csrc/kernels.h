@@ -100,6 +100,7 @@ struct CompositeArgs {
   const float4* obs;
   int N, B, Sc, Sf;
   float far_, log_trans, log_opq, tau;   // log(1 - alpha), log(alpha)
+  float empty_F;                         // F of a ray that never reaches opacity alpha
   float4* ray_rgba;        // per ray (C, A)
   float2* ray_fe;          // per ray (F, E)
   double* loglik;          // per particle, or NULL (teacher mode)
@@ -226,6 +227,7 @@ struct LevelRayArgs {
   const float* bias;
   const float* heads;
   float near_, dt, far_, log_trans, log_opq, tau;
+  float empty_F;                         // F of a ray that never reaches opacity alpha
   int jitter;
   float4* ray_rgba;       // per ray (C, A)
   float2* ray_fe;         // per ray (F, E)

@@ -333,7 +333,7 @@ k_level_rays(const LevelRayArgs a) {
       cr = half_sum(cr); cg = half_sum(cg); cb = half_sum(cb); accw = half_sum(accw);
       ktr = half_min_int(ktr);
       kop = half_min_int(kop);
-      float F = a.tau;
+      float F = a.empty_F;
       if (ktr < kLevelSpr) {
         const float t_tr = __shfl(tk, ktr, 32), l_tr = __shfl(lt, ktr, 32), s_tr = __shfl(sg, ktr, 32);
         const int ko = kop < kLevelSpr ? kop : 0;

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(64 * kCompWaves) void k_composite(const CompositeAr
     a.hist[ray * 32 + lane] = acc < 1e-3f ? 1.0f / 32.0f : (t0 - t1) / den;
   }
   if (lane == 0) {
-    float F = a.tau;
+    float F = a.empty_F;
     if (ktr < S) {
       const float zt = s_tm[ktr] + (s_lt[ktr] - a.log_trans) / s_sg[ktr];
       const float zo = (kop < S) ? s_tm[kop] + (s_lt[kop] - a.log_opq) / s_sg[kop] : a.far_;

@@ -46,6 +46,7 @@ struct DevBuf {
 struct loc_ctx {
   int device = 0;
   unsigned long long* noalloc_prefix = nullptr;   // this device's scratch of loc_resample_noalloc
+  int empty_span = 0;   // 1: F = far - near for rays that never reach opacity alpha (else tau)
   hipStream_t stream = nullptr;
   loc_map_desc desc{};
   int kind = kMapSmall;
@@ -858,6 +859,7 @@ loc_status loc_update_particles(loc_ctx* c, const float* image, const loc_camera
   ca.log_trans = (float)std::log1p(-(double)d.alpha);
   ca.log_opq = (float)std::log((double)d.alpha);
   ca.tau = d.tau;
+  ca.empty_F = c->empty_span ? d.far_ - d.near_ : d.tau;
   ca.ray_rgba = c->rgba.p;
   ca.ray_fe = c->fe.p;
   ca.loglik = loglik_out;
@@ -1083,6 +1085,7 @@ loc_status loc_teacher_histograms(loc_ctx* c, const float* ray_o, const float* r
   ca.log_trans = (float)std::log1p(-(double)d.alpha);
   ca.log_opq = (float)std::log((double)d.alpha);
   ca.tau = d.tau;
+  ca.empty_F = c->empty_span ? d.far_ - d.near_ : d.tau;
   ca.ray_rgba = c->rgba.p;
   ca.ray_fe = c->fe.p;
   ca.loglik = nullptr;
@@ -1396,6 +1399,7 @@ LevelRayArgs level_ray_args(const loc_ctx* c, const LevelCall& q, int L) {
   a.log_trans = (float)std::log1p(-(double)d.alpha);
   a.log_opq = (float)std::log((double)d.alpha);
   a.tau = d.tau;
+  a.empty_F = c->empty_span ? d.far_ - d.near_ : d.tau;
   a.jitter = d.jitter;
   a.ray_rgba = c->lv[L].rgba.p;
   a.ray_fe = c->lv[L].fe.p;
@@ -1580,6 +1584,15 @@ loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* c
     c->graph_sig = sig;
   }
   HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+  return LOC_OK;
+}
+
+loc_status loc_set_empty_ray_uncertainty(loc_ctx* c, int mode) {
+  if (!c) return LOC_E_ARG;
+  c->err.clear();
+  if (mode != 0 && mode != 1) return fail(c, LOC_E_ARG, "mode must be 0 (F = tau) or 1 (F = far - near)");
+  if (mode != c->empty_span) drop_graph(c);    // a captured level graph holds the old value
+  c->empty_span = mode;
   return LOC_OK;
 }
 
@@ -1821,6 +1834,7 @@ loc_status loc_render_image(loc_ctx* c, const loc_camera* cam, int inv_R, const 
   ca.log_trans = (float)std::log1p(-(double)d.alpha);
   ca.log_opq = (float)std::log((double)d.alpha);
   ca.tau = d.tau;
+  ca.empty_F = c->empty_span ? d.far_ - d.near_ : d.tau;
   ca.ray_rgba = c->rgba.p;
   ca.ray_fe = c->fe.p;
   ca.loglik = nullptr;

@@ -68,15 +68,18 @@ def _same(a, b):
     return np.array_equal(a, b, equal_nan=True)
 
 
-def test_levels_equal_unfused_path_bitwise(torch_dev):
+@pytest.mark.parametrize("empty_mode", [0, 1])
+def test_levels_equal_unfused_path_bitwise(torch_dev, empty_mode):
     torch = torch_dev
     s, p, cam, poses, img = _setup(71, 100)
     c = ctx(s, p, "bf16")
+    c.loc_set_empty_ray_uncertainty(empty_mode)
     img_d = _dev(img, torch)
     kw = dict(motion=MOTION, sigma_t=0.02, sigma_r=0.01, seed=5, iter=3)
     r = _run_levels(c, img_d, cam, LEVELS_SMALL, _dev(poses, torch), torch, reject=False, **kw)
     assert r["flags"] == 0
     u = ctx(s, p, "bf16")
+    u.loc_set_empty_ray_uncertainty(empty_mode)
     X = poses
     for L, (inv_R, B, n_out) in enumerate(LEVELS_SMALL):
         po, ll, w, un = u.loc_update_particles(img_d, cam, inv_R, B, _dev(X, torch), MOTION, 0.02, 0.01, 5, 3 + L)

@@ -156,6 +156,28 @@ def test_maximum_ray_count_folded_launch(torch_dev):
         run_gpu(ctx, img, cam, 1, 1024, np.concatenate([poses, poses[:1]]), **kw)
 
 
+def test_empty_ray_uncertainty_readings(torch_dev):
+    """Eq. 5 for rays whose opacity never reaches alpha (most rays of the
+    small workload, whose particles look in random directions): F = tau by
+    default, F = far - near under the other reading; both against the oracle
+    in the same reading, and other modes refused."""
+    from paper_2406_12202_amd.binding import LocError
+    s, p, cam, poses, img = inputs("small", 12, N=8)
+    c = _ctx(s, p)
+    kw = dict(seed=3, it=1)
+    for mode, reading in ((1, "span"), (0, None)):
+        c.loc_set_empty_ray_uncertainty(mode)
+        g = run_gpu(c, img, cam, 1, 16, poses, **kw)
+        o = run_oracle(dict(s, empty_ray=reading) if reading else s, p, img, cam, 1, 16, poses, **kw)
+        _compare(g, o, TOL["small"])
+        empty = ~np.isfinite(o["z_trans"])
+        assert empty.mean() > 0.5
+        want = s["far"] - s["near"] if mode else s["tau"]
+        assert np.all(g["F"][empty] == np.float32(want))
+    with pytest.raises(LocError):
+        c.loc_set_empty_ray_uncertainty(2)
+
+
 def test_tau_dominant_reduces_to_eq4(torch_dev):
     # tau >= far - near: F = tau on every ray, so the normalised weights equal
     # normalised (B / sum_j E_j)^4 computed from the GPU's own E

@@ -303,6 +303,31 @@ def test_quantile_special_cases():
     zts, zos = rd.ray_quantiles(t, sigs, logTs, far, alpha)
     assert alpha < As < 1 - alpha and zos == far
     assert abs(rd.uncertainty(zts, zos, tau) - (far - zts)) < 1e-15
+    # the other reading of the empty set: F = far - near for the empty ray
+    # only; opaque and semi-transparent rays keep their gap
+    assert rd.uncertainty(zt0, zo0, tau, far - near) == far - near
+    assert rd.uncertainty(zt, zo, tau, far - near) == tau
+    assert abs(rd.uncertainty(zts, zos, tau, far - near) - (far - zts)) < 1e-15
+
+
+def test_empty_ray_reading_through_the_update():
+    # a map with density ~0 everywhere (density bias -40): every ray is
+    # empty, F = tau under the default reading and far - near under "span",
+    # and the weights follow Eq. 6 with the constant F (the same weights)
+    s = synth.spec("small", tau=0.1)
+    flat = []
+    for n, (_, o, i) in enumerate(rd.layer_shapes(s)):
+        flat.append(np.zeros(o * i))
+        flat.append(np.full(o, -40.0) if n == s["n_layers"] else np.zeros(o))
+    flat = np.concatenate(flat).astype(np.float32)
+    cam = synth.camera("small")
+    poses = synth.particles("small", 4, N=3)
+    img = synth.observation("small", 4)
+    a = mcl.update_particles(s, flat, img, cam, 1, 5, poses, seed=1, it=0)
+    b = mcl.update_particles(dict(s, empty_ray="span"), flat, img, cam, 1, 5, poses, seed=1, it=0)
+    assert np.all(a["F"] == 0.1) and np.all(b["F"] == s["far"] - s["near"])
+    assert np.allclose(a["weight"], b["weight"], rtol=0, atol=1e-15)
+    assert np.allclose(b["loglik"] - a["loglik"], -4 * math.log((s["far"] - s["near"]) / 0.1), atol=1e-12)
 
 
 def test_crossing_densities_and_first_order_conditioning():
