@@ -772,9 +772,17 @@ def main():
         O, D = ctxp.loc_cast_rays(cam, 1, 64, tp, seed=args.seed + 1, iter=0)
         T = ctxp.loc_teacher_histograms(O, D, 128, seed=args.seed + 1, iter=1)
         ctxp.loc_set_proposal(synth.proposal_params(args.seed))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctxp.loc_set_profiling(1)       # events around each training step's two kernels
         losses = ctxp.loc_train_proposal(O, D, T, 8192, args.train_steps, lr=2e-3)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0
+        train_loop_s = time.perf_counter() - t1
+        kt = ctxp.loc_kernel_stats().get("proposal_train", {"ms": 0.0, "launches": 0, "flop": 0.0})
+        ctxp.loc_set_profiling(0)
+        step_ms = kt["ms"] / max(kt["launches"], 1)
+        step_tflops = kt["flop"] / max(kt["launches"], 1) / (step_ms * 1e-3) / 1e12 if step_ms > 0 else None
         losses = losses.cpu().numpy()
         del O, D, T, tp
         ctxp.loc_set_fine_mode(1)
@@ -795,7 +803,11 @@ def main():
                "speedup_mlp_samples_vs_fp32": rp["samples_per_s"] / r32["samples_per_s"],
                "roofline": rp["roofline"], "kernels": rp["kernels"], "flags": flp,
                "proposal_training": {"rays": args.train_poses * 64, "steps": args.train_steps, "batch": 8192,
-                                     "seconds": train_s, "loss_first": float(losses[:20].mean()),
+                                     "seconds_with_teacher_render": train_s, "seconds_training": train_loop_s,
+                                     "precision": "bf16 operands, fp32 accumulation (matrix cores)",
+                                     "ms_per_step": step_ms, "TFLOPs_per_step": step_tflops,
+                                     "frac_bf16_peak": step_tflops / PEAK["bf16"][0] if step_tflops else None,
+                                     "loss_first": float(losses[:20].mean()),
                                      "loss_last": float(losses[-20:].mean())},
                "fp32_plain": {"samples_per_s": r32["samples_per_s"], "ms_per_step": r32["ms_per_step"],
                               "particle_updates_per_s": r32["particle_updates_per_s"],

@@ -144,6 +144,10 @@ struct TrainArgs {
   float lr, beta1, beta2, eps;
 };
 hipError_t launch_prop_grad(const TrainArgs& a, hipStream_t st);
+// the same gradient with bf16 operands on the matrix cores (float32
+// accumulation), prop_rays_per_wave_bf16() rays per wave
+hipError_t launch_prop_grad_bf16(const TrainArgs& a, hipStream_t st);
+int prop_rays_per_wave_bf16();
 // multi-resolution grid map (levels 4, 8 or 16; direction bands <= 4)
 constexpr int kGridMaxLevels = 16;
 constexpr int kGridMaxDirBands = 4;

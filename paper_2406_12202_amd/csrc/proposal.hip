@@ -328,8 +328,18 @@ __global__ __launch_bounds__(256) void k_prop_reduce(const TrainArgs a) {
     a.loss_out[a.loss_index] = l / (float)a.batch;
   }
   if (e >= P_N) return;
+  // eight interleaved running sums (waves v = 8 u + k into sum k), added in
+  // the order k = 0..7: the loads of eight waves are in flight at once
+  float g8[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  int v = 0;
+  for (; v + 8 <= a.n_waves; v += 8) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g8[k] += a.partial[(long)(v + k) * P_N + e];
+  }
+  for (int k = 0; v + k < a.n_waves; ++k) g8[k] += a.partial[(long)(v + k) * P_N + e];
   float g = 0.0f;
-  for (int v = 0; v < a.n_waves; ++v) g += a.partial[(long)v * P_N + e];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) g += g8[k];
   if (a.grad_out) a.grad_out[e] = g;
   if (a.adam) {
     const float m = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
@@ -350,6 +360,380 @@ hipError_t launch_prop_grad(const TrainArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_prop_reduce, dim3((P_N + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// training in bfloat16 on the matrix cores (v_mfma_f32_32x32x16_bf16, float32
+// accumulation): a wave takes tiles of 32 rays.  Forward and the backward pass
+// through the layers run transposed, out^T = W in^T, with the rays as the 32
+// columns: in an instruction lane l = 32 h + n supplies column n and the eight
+// k-rows 8 h .. 8 h + 7 of the k-block, and the accumulator holds, in lane
+// (n, h) and register v, output row 8 (v / 4) + 4 h + v % 4 of column n.
+// Registers v = 0..7 and 8..15 of an output tile, rounded to bf16, are the
+// next product's operands of its k-blocks 2 mt and 2 mt + 1, so a chained
+// k-block kb carries in half h and slot q the row 16 kb + 8 (q / 4) + 4 h +
+// q % 4 (the weights are staged in that order).  Layer 1 reads the encoding
+// in natural order (k-row 16 kb + 8 h + q), padded to 80 with x_78 = 1 (the
+// bias column of dW1) and x_79 = 0.  The weight gradients contract over the
+// rays: each tile's activations and output gradients go through the wave's
+// LDS as bf16 [row][ray] tables, whose rows give the 8-ray operand slots,
+// and dW = G H^T accumulates in registers over the wave's tiles (one wave per
+// SIMD, 512 registers).  db2 and db3 are summed on the vector ALU.  Each wave
+// writes its partial gradient in parameter order, as the float32 kernel.
+constexpr int kTrainBWaves = 4;
+// 32-ray tiles per wave (measured on MI355X for 8192-ray steps: 1, 2 and 4
+// tiles took 62, 53 and 60 us per step)
+constexpr int kTrainBTiles = 2;
+constexpr int PX = 80;                              // padded encoding
+constexpr int PKX = PX / 16;                        // 5 k-blocks of layer 1
+constexpr int TROW = 40;                            // LDS table row stride (bf16)
+// weight fragments (1 KB blocks) in LDS
+constexpr int FB_W1 = 0, FB_W2 = FB_W1 + 2 * PKX, FB_W3 = FB_W2 + 2 * 4, FB_W3T = FB_W3 + 4, FB_W2T = FB_W3T + 2 * 2,
+              FB_N = FB_W2T + 2 * 4;
+// per-wave tables (bf16 rows of TROW): gz 32, h2 64, ga2 64, h1 64, ga1 64, x 96
+constexpr int TB_GZ = 0, TB_H2 = TB_GZ + 32, TB_GA2 = TB_H2 + 64, TB_H1 = TB_GA2 + 64, TB_GA1 = TB_H1 + 64,
+              TB_X = TB_GA1 + 64, TB_ROWS = TB_X + 96;
+
+typedef __bf16 pbf16x8 __attribute__((ext_vector_type(8)));
+typedef float pf32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 pbf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int chain_row(int kb, int h, int q) { return 16 * kb + 8 * (q >> 2) + 4 * h + (q & 3); }
+
+__device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
+  const pf32x2 f = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, pbf16x2));
+}
+
+// rounded bf16 operands of k-blocks 2 mt and 2 mt + 1 from an output tile
+__device__ __forceinline__ void tile_operands_bf16(const pf32x16& t, pbf16x8& k0, pbf16x8& k1) {
+  uint4 u0, u1;
+  u0.x = pack2_bf16(t[0], t[1]); u0.y = pack2_bf16(t[2], t[3]);
+  u0.z = pack2_bf16(t[4], t[5]); u0.w = pack2_bf16(t[6], t[7]);
+  u1.x = pack2_bf16(t[8], t[9]); u1.y = pack2_bf16(t[10], t[11]);
+  u1.z = pack2_bf16(t[12], t[13]); u1.w = pack2_bf16(t[14], t[15]);
+  k0 = __builtin_bit_cast(pbf16x8, u0);
+  k1 = __builtin_bit_cast(pbf16x8, u1);
+}
+
+// a 32-row output tile (rows row0 + 8 (v / 4) + 4 h + v % 4 of column n) into
+// the [row][ray] table as bf16, the same rounding as tile_operands_bf16
+__device__ __forceinline__ void tile_to_table(const pf32x16& t, __bf16* tab, const int row0, const int n,
+                                              const int h) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v) tab[(row0 + 8 * (v >> 2) + 4 * h + (v & 3)) * TROW + n] = (__bf16)t[v];
+}
+
+__device__ __forceinline__ pbf16x8 table_operand(const __bf16* tab, const int row, const int kb, const int h) {
+  return __builtin_bit_cast(pbf16x8, *reinterpret_cast<const uint4*>(tab + row * TROW + 16 * kb + 8 * h));
+}
+
+__device__ __forceinline__ float warp_f32(float v, int k) { return __shfl_xor(v, k, 64); }
+
+__global__ __launch_bounds__(64 * kTrainBWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_prop_grad_bf16(
+    const TrainArgs a) {
+  __shared__ uint4 s_w[FB_N * 64];
+  __shared__ __align__(16) __bf16 s_t[kTrainBWaves][TB_ROWS * TROW];
+  __shared__ float s_b[PH + PH + PB];
+  const float* __restrict__ P = a.params;
+  // weight fragments in the operand order of each product
+  for (int e = threadIdx.x; e < FB_N * 64; e += blockDim.x) {
+    const int blk = e >> 6, ln = e & 63, i = ln & 31, h = ln >> 5;
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float x = 0.0f;
+      if (blk < FB_W2) {                      // W1: block mt * 5 + kb, natural k order
+        const int mt = blk / PKX, kb = blk - mt * PKX, k = 16 * kb + 8 * h + q;
+        x = k < PIN ? P[P_W1 + (32 * mt + i) * PIN + k] : 0.0f;
+      } else if (blk < FB_W3) {               // W2: block mt * 4 + kb, chained k order
+        const int b = blk - FB_W2, mt = b >> 2, kb = b & 3;
+        x = P[P_W2 + (32 * mt + i) * PH + chain_row(kb, h, q)];
+      } else if (blk < FB_W3T) {              // W3: block kb
+        const int kb = blk - FB_W3;
+        x = P[P_W3 + i * PH + chain_row(kb, h, q)];
+      } else if (blk < FB_W2T) {              // W3^T: block mt * 2 + kb (rows hidden, k bins)
+        const int b = blk - FB_W3T, mt = b >> 1, kb = b & 1;
+        x = P[P_W3 + chain_row(kb, h, q) * PH + 32 * mt + i];
+      } else {                                // W2^T: block mt * 4 + kb (rows h1 units, k h2 units)
+        const int b = blk - FB_W2T, mt = b >> 2, kb = b & 3;
+        x = P[P_W2 + chain_row(kb, h, q) * PH + 32 * mt + i];
+      }
+      v[q] = x;
+    }
+    uint4 u;
+    u.x = pack2_bf16(v[0], v[1]); u.y = pack2_bf16(v[2], v[3]);
+    u.z = pack2_bf16(v[4], v[5]); u.w = pack2_bf16(v[6], v[7]);
+    s_w[e] = u;
+  }
+  for (int e = threadIdx.x; e < PH + PH + PB; e += blockDim.x)
+    s_b[e] = e < PH ? P[P_B1 + e] : (e < 2 * PH ? P[P_B2 + e - PH] : P[P_B3 + e - 2 * PH]);
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 31, h = lane >> 5;
+  const int wave = blockIdx.x * kTrainBWaves + wv;
+  if (wave >= a.n_waves) return;   // no barrier follows
+  __bf16* tab = s_t[wv];
+  const float scale = 2.0f / (float)a.batch;
+  pf32x16 dw1[2][3], dw2[2][2], dw3[2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int nt = 0; nt < 3; ++nt) dw1[mt][nt][r] = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) dw2[mt][nt][r] = 0.0f;
+      dw3[mt][r] = 0.0f;
+    }
+  }
+  float db2[2][16], db3[16], lsum = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) { db2[0][r] = db2[1][r] = 0.0f; db3[r] = 0.0f; }
+  for (int tt = 0; tt < kTrainBTiles; ++tt) {
+    const int rb = (wave * kTrainBTiles + tt) * 32 + n;   // position in the batch
+    const bool valid = rb < a.batch;
+    const long ray = ((long)a.first + (valid ? rb : 0)) % a.n_rays;
+    const float4 o = a.ray_o[ray], d = a.ray_d[ray];
+    // encoding entries 16 kb + 8 h + q of this ray; the same entries into the x table
+    pbf16x8 xb[PKX];
+    {
+      float sn[2][3][6], cs[2][3][6];
+      const float oc[2][3] = {{o.x, o.y, o.z}, {d.x, d.y, d.z}};
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int l = 0; l < 6; ++l) sincospif(ldexpf(oc[s2][c], l), &sn[s2][c][l], &cs[s2][c][l]);
+#pragma unroll
+      for (int kb = 0; kb < PKX; ++kb) {
+        float xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float v0 = 0.0f, v1 = 0.0f;       // entry for half 0 and half 1
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int k = 16 * kb + 8 * hh + q;
+            float x;
+            if (k == PIN) x = 1.0f;
+            else if (k > PIN) x = 0.0f;
+            else {
+              const int s2 = k >= PENC, e = s2 ? k - PENC : k;
+              if (e < 3) x = oc[s2][e];
+              else {
+                const int qq = e - 3, l = qq / 6, rr = qq % 6, c = rr % 3;
+                x = rr < 3 ? sn[s2][c][l] : cs[s2][c][l];
+              }
+            }
+            if (hh == 0) v0 = x; else v1 = x;
+          }
+          xv[q] = valid ? (h ? v1 : v0) : 0.0f;
+        }
+        uint4 u;
+        u.x = pack2_bf16(xv[0], xv[1]); u.y = pack2_bf16(xv[2], xv[3]);
+        u.z = pack2_bf16(xv[4], xv[5]); u.w = pack2_bf16(xv[6], xv[7]);
+        xb[kb] = __builtin_bit_cast(pbf16x8, u);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tab[(TB_X + 16 * kb + 8 * h + q) * TROW + n] = xb[kb][q];
+      }
+#pragma unroll
+      for (int r = PX; r < 96; ++r)
+        if (h == 0) tab[(TB_X + r) * TROW + n] = (__bf16)0.0f;
+    }
+    // forward
+    pf32x16 s1[2], s2v[2], z;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s1[mt][r] = s_b[32 * mt + prop_row(r, h)];
+#pragma unroll
+      for (int kb = 0; kb < PKX; ++kb)
+        s1[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W1 + mt * PKX + kb) * 64 + lane]),
+                                                         xb[kb], s1[mt], 0, 0, 0);
+    }
+    pf32x16 h1[2];
+    pbf16x8 h1b[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h1[mt][r] = fmaxf(s1[mt][r], 0.0f);
+      tile_operands_bf16(h1[mt], h1b[2 * mt], h1b[2 * mt + 1]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s2v[mt][r] = s_b[PH + 32 * mt + prop_row(r, h)];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        s2v[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W2 + mt * 4 + kb) * 64 + lane]),
+                                                          h1b[kb], s2v[mt], 0, 0, 0);
+    }
+    pf32x16 h2[2];
+    pbf16x8 h2b[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h2[mt][r] = fmaxf(s2v[mt][r], 0.0f);
+      tile_operands_bf16(h2[mt], h2b[2 * mt], h2b[2 * mt + 1]);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = s_b[2 * PH + prop_row(r, h)];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W3 + kb) * 64 + lane]), h2b[kb], z,
+                                                  0, 0, 0);
+    // softmax over the 32 bins of column n, loss and dL/dz
+    float m = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) m = fmaxf(m, z[r]);
+    m = fmaxf(m, warp_f32(m, 32));
+    float sum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { z[r] = expf(z[r] - m); sum += z[r]; }
+    sum += warp_f32(sum, 32);
+    const float inv = 1.0f / sum;
+    float tg[16];
+    {
+      const float4* tp = reinterpret_cast<const float4*>(a.target + ray * PB);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 t4 = tp[2 * g + h];
+        tg[4 * g] = t4.x; tg[4 * g + 1] = t4.y; tg[4 * g + 2] = t4.z; tg[4 * g + 3] = t4.w;
+      }
+    }
+    float pg = 0.0f, sq = 0.0f;
+    pf32x16 gz;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float p = z[r] * inv;
+      const float diff = p - tg[r];
+      sq += diff * diff;
+      gz[r] = scale * diff;          // dL/dp
+      z[r] = p;
+      pg += p * gz[r];
+    }
+    pg += warp_f32(pg, 32);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) gz[r] = valid ? z[r] * (gz[r] - pg) : 0.0f;
+    if (valid) lsum += sq;
+    // backward through the layers
+    pbf16x8 gzb[2];
+    tile_operands_bf16(gz, gzb[0], gzb[1]);
+    pf32x16 ga2[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ga2[mt][r] = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+        ga2[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W3T + mt * 2 + kb) * 64 + lane]),
+                                                          gzb[kb], ga2[mt], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ga2[mt][r] = s2v[mt][r] > 0.0f ? ga2[mt][r] : 0.0f;
+    }
+    pbf16x8 ga2b[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) tile_operands_bf16(ga2[mt], ga2b[2 * mt], ga2b[2 * mt + 1]);
+    pf32x16 ga1[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ga1[mt][r] = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        ga1[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W2T + mt * 4 + kb) * 64 + lane]),
+                                                          ga2b[kb], ga1[mt], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ga1[mt][r] = s1[mt][r] > 0.0f ? ga1[mt][r] : 0.0f;
+    }
+    // bias gradients of layers 2 and 3 on the vector ALU (this lane's column)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      db3[r] += gz[r];
+      db2[0][r] += ga2[0][r];
+      db2[1][r] += ga2[1][r];
+    }
+    // the tile's tables, then dW = G H^T over the tile's 32 rays
+    tile_to_table(gz, tab, TB_GZ, n, h);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      tile_to_table(h2[mt], tab, TB_H2 + 32 * mt, n, h);
+      tile_to_table(ga2[mt], tab, TB_GA2 + 32 * mt, n, h);
+      tile_to_table(h1[mt], tab, TB_H1 + 32 * mt, n, h);
+      tile_to_table(ga1[mt], tab, TB_GA1 + 32 * mt, n, h);
+    }
+    prop_wave_sync();
+    const int i = n;   // operand row of this lane
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const pbf16x8 agz = table_operand(tab, TB_GZ + i, kb, h);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        dw3[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(agz, table_operand(tab, TB_H2 + 32 * nt + i, kb, h), dw3[nt],
+                                                          0, 0, 0);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const pbf16x8 aga2 = table_operand(tab, TB_GA2 + 32 * mt + i, kb, h);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          dw2[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aga2, table_operand(tab, TB_H1 + 32 * nt + i, kb, h),
+                                                                dw2[mt][nt], 0, 0, 0);
+        const pbf16x8 aga1 = table_operand(tab, TB_GA1 + 32 * mt + i, kb, h);
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt)
+          dw1[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aga1, table_operand(tab, TB_X + 32 * nt + i, kb, h),
+                                                                dw1[mt][nt], 0, 0, 0);
+      }
+    }
+    prop_wave_sync();   // the next tile overwrites the tables
+  }
+  // bias sums over the 32 columns of each half, fixed butterfly order
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      db3[r] += __shfl_xor(db3[r], o, 32);
+      db2[0][r] += __shfl_xor(db2[0][r], o, 32);
+      db2[1][r] += __shfl_xor(db2[1][r], o, 32);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+  // partial gradient in parameter order: accumulator (row 8 (v / 4) + 4 h +
+  // v % 4, column n) of tile (mt, nt) is dW[32 mt + row][32 nt + n]
+  float* out = a.partial + (long)wave * P_N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = prop_row(r, h);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int u = 32 * mt + row;
+#pragma unroll
+      for (int nt = 0; nt < 3; ++nt) {
+        const int k = 32 * nt + n;
+        if (k < PIN) out[P_W1 + u * PIN + k] = dw1[mt][nt][r];
+        else if (k == PIN) out[P_B1 + u] = dw1[mt][nt][r];
+      }
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) out[P_W2 + u * PH + 32 * nt + n] = dw2[mt][nt][r];
+      if (n == 0) out[P_B2 + u] = db2[mt][r];
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) out[P_W3 + row * PH + 32 * nt + n] = dw3[nt][r];
+    if (n == 0) out[P_B3 + row] = db3[r];
+  }
+  if (lane == 0) a.loss_partial[wave] = lsum;
+}
+
+hipError_t launch_prop_grad_bf16(const TrainArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_prop_grad_bf16, dim3((a.n_waves + kTrainBWaves - 1) / kTrainBWaves), dim3(64 * kTrainBWaves),
+                     0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prop_reduce, dim3((P_N + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int prop_rays_per_wave_bf16() { return 32 * kTrainBTiles; }
 
 // ---------------------------------------------------------------------------
 __global__ void k_rays_to_f4(const float* o3, const float* d3, int n, float4* o4, float4* d4) {

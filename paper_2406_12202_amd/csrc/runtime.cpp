@@ -1162,9 +1162,14 @@ loc_status loc_proposal_forward(loc_ctx* c, const float* ray_o, const float* ray
 namespace {
 constexpr int kRaysPerWave = 32;
 
+// the proposal trains in the map's precision: float32 on the vector ALU for a
+// float32 context, bf16 operands on the matrix cores otherwise
+bool prop_bf16(const loc_ctx* c) { return c->desc.precision != LOC_FP32; }
+
 loc_status prop_prepare(loc_ctx* c, const float* ray_o, const float* ray_d, int n, int batch, TrainArgs& ta) {
   loc_status s;
-  const int n_waves = (batch + kRaysPerWave - 1) / kRaysPerWave;
+  const int rpw = prop_bf16(c) ? prop_rays_per_wave_bf16() : kRaysPerWave;
+  const int n_waves = (batch + rpw - 1) / rpw;
   if ((s = ensure(c, c->tr_o, n)) || (s = ensure(c, c->tr_d, n)) ||
       (s = ensure(c, c->prop_partial, (size_t)n_waves * kProposalParams)) || (s = ensure(c, c->prop_loss, n_waves)))
     return s;
@@ -1179,9 +1184,13 @@ loc_status prop_prepare(loc_ctx* c, const float* ray_o, const float* ray_d, int 
   ta.loss_partial = c->prop_loss.p;
   ta.n_rays = n;
   ta.batch = batch;
-  ta.rays_per_wave = kRaysPerWave;
+  ta.rays_per_wave = rpw;
   ta.n_waves = n_waves;
   return LOC_OK;
+}
+
+hipError_t launch_prop_step(const loc_ctx* c, const TrainArgs& ta) {
+  return prop_bf16(c) ? launch_prop_grad_bf16(ta, c->stream) : launch_prop_grad(ta, c->stream);
 }
 }  // namespace
 
@@ -1201,7 +1210,7 @@ loc_status loc_proposal_grad(loc_ctx* c, const float* ray_o, const float* ray_d,
   ta.loss_index = 0;
   ta.grad_out = grad_out;
   ta.adam = 0;
-  return timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * n, 0.0, [&] { return launch_prop_grad(ta, c->stream); });
+  return timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * n, 0.0, [&] { return launch_prop_step(c, ta); });
 }
 
 loc_status loc_train_proposal(loc_ctx* c, const float* ray_o, const float* ray_d, const float* target, int n,
@@ -1233,7 +1242,7 @@ loc_status loc_train_proposal(loc_ctx* c, const float* ray_o, const float* ray_d
     ta.first = (int)(((long)k * cfg->batch) % n);
     ta.loss_index = k;
     ta.step = ++c->prop_step;
-    if ((s = timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * cfg->batch, 0.0, [&] { return launch_prop_grad(ta, c->stream); })))
+    if ((s = timed(c, K_TRAIN, 3.0 * 2.0 * 11136.0 * cfg->batch, 0.0, [&] { return launch_prop_step(c, ta); })))
       return s;
   }
   return LOC_OK;

@@ -8,6 +8,12 @@ Bars (FP32 kernels):
   gradient                      cosine >= 0.9999 and relative L2 <= 1e-4
   Adam trajectory (3 steps)     within 1e-3 lr of the FP64 oracle's
   proposal-guided update        FP32 tolerances of the hierarchical path
+Training on a bf16 context (bf16 operands on the matrix cores, float32
+accumulation; a relative rounding of 2^-8 per operand over three chained
+products): gradient relative L2 <= 2e-2 at batch scale (5e-2 for 333 rays)
+and cosine >= 0.999, loss within 1e-2 relative; Adam's first step equals its closed form on the kernel's own
+gradient; the network trained this way keeps the gain over uniform and
+hierarchical placement.
 """
 import math
 
@@ -112,6 +118,64 @@ def test_proposal_gradient_matches_oracle(torch_dev):
     assert torch.equal(grad, grad2)
 
 
+@pytest.mark.parametrize("n_rays,seed,rel_bar", [(333, 3, 5e-2), (8197, 12, 2e-2)])
+def test_proposal_gradient_bf16_matches_oracle(torch_dev, n_rays, seed, rel_bar):
+    """The bf16 matrix-core gradient (a bf16 context): 8197 rays, the scale
+    of a training batch, spread over 129 waves and hold the planned bar
+    (relative L2 <= 2e-2); 333 rays leave the last 64-ray wave partly empty.
+    Each gradient entry is a sum over rays of terms of both signs, so the
+    operands' relative rounding (2^-8) reaches the sum amplified by
+    sum |term| / |sum|, which is larger for the small, random batch:
+    relative L2 <= 5e-2 there, with the cosine bar unchanged."""
+    torch = torch_dev
+    s, p, _, _, _ = inputs("small", 34)
+    c = ctx(s, p, "bf16")
+    theta = synth.proposal_params(seed)
+    c.loc_set_proposal(theta)
+    O, D = _rays(n_rays, seed)
+    T = synth.random_histograms(seed + 2, n_rays)
+    c.loc_set_profiling(1)
+    loss, grad = c.loc_proposal_grad(_dev(O, torch), _dev(D, torch), _dev(T, torch))
+    ks = c.loc_kernel_stats()
+    c.loc_set_profiling(0)
+    P = pr.unpack(theta)
+    pp, cache = pr.forward(P, pr.features(O.astype(np.float64), D.astype(np.float64)))
+    gref = pr.pack(pr.backward(P, cache, T.astype(np.float64)))
+    g = grad.cpu().numpy().astype(np.float64)
+    cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    lref = pr.loss(pp, T)
+    print("bf16 gradient cosine %.6f  relative L2 %.3e  loss %.6f vs %.6f  (%.1f us)"
+          % (cos, rel, float(loss.item()), lref, 1e3 * ks["proposal_train"]["ms"] / max(ks["proposal_train"]["launches"], 1)))
+    assert cos >= 0.999 and rel <= rel_bar
+    assert abs(float(loss.item()) - lref) <= 1e-2 * lref
+    _, grad2 = c.loc_proposal_grad(_dev(O, torch), _dev(D, torch), _dev(T, torch))
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_first_step_bf16_closed_form(torch_dev):
+    """One Adam step of the bf16 training from zero moments moves every
+    parameter by lr g / (|g| + eps) with g the same kernel's gradient on the
+    same batch (the first batch of the ray list)."""
+    torch = torch_dev
+    s, p, _, _, _ = inputs("small", 35)
+    c = ctx(s, p, "bf16")
+    theta = synth.proposal_params(6)
+    O, D = _rays(512, 4)
+    T = synth.random_histograms(7, 512)
+    lr, batch = 1e-3, 256
+    c.loc_set_proposal(theta)
+    _, g = c.loc_proposal_grad(_dev(O[:batch], torch), _dev(D[:batch], torch), _dev(T[:batch], torch))
+    g = g.cpu().numpy().astype(np.float64)
+    c.loc_set_proposal(theta)
+    c.loc_train_proposal(_dev(O, torch), _dev(D, torch), _dev(T, torch), batch, 1, lr=lr)
+    got = c.loc_get_proposal().astype(np.float64)
+    want = theta.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    d = np.abs(got - want)
+    print("bf16 Adam first step: max |d theta| %.3e (lr %.1e)" % (d.max(), lr))
+    assert d.max() <= 1e-4 * lr + 1e-7
+
+
 def test_adam_trajectory_matches_oracle(torch_dev):
     torch = torch_dev
     s, p, _, _, _ = inputs("small", 35)
@@ -159,7 +223,8 @@ def test_update_with_proposal_matches_oracle(torch_dev, N, B, n_fine):
     assert rC["max"] <= 2e-4 and rF["max"] <= 0.1 and rL["max"] <= 1e-2
 
 
-def test_trained_proposal_gain(torch_dev):
+@pytest.mark.parametrize("train_precision", ["fp32", "bf16"])
+def test_trained_proposal_gain(torch_dev, train_precision):
     """Train the proposal on the map's own compositing weights, then render
     held-out particle rays with 64 coarse + 32 fine samples placed by (a) the
     trained proposal, (b) a uniform proposal, (c) hierarchical sampling on the
@@ -176,12 +241,18 @@ def test_trained_proposal_gain(torch_dev):
     params = synth.map_params(s_full, 37)
     cam = synth.camera("nerf")
     c = ctx(s32, params)
-    # training rays: 16384 poses x 16 pixels from the particle distribution
+    # training rays: 16384 poses x 16 pixels from the particle distribution;
+    # teacher targets from the float32 map, training in train_precision (a
+    # bf16 context trains with bf16 operands on the matrix cores), the
+    # trained parameters evaluated on the float32 map
     tp = _dev(synth.training_poses("nerf", 37, 16384), torch)
     O, D = c.loc_cast_rays(cam, 1, 16, tp, seed=11, iter=0)
     T = c.loc_teacher_histograms(O, D, 128, seed=11, iter=1)
-    c.loc_set_proposal(synth.proposal_params(9))
-    losses = c.loc_train_proposal(O, D, T, 4096, 4000, lr=2e-3).cpu().numpy()
+    tr = c if train_precision == "fp32" else ctx(s32, params, "bf16")
+    tr.loc_set_proposal(synth.proposal_params(9))
+    losses = tr.loc_train_proposal(O, D, T, 4096, 4000, lr=2e-3).cpu().numpy()
+    if tr is not c:
+        c.loc_set_proposal(tr.loc_get_proposal())
     uni = float(((1.0 / 32 - T.cpu().numpy()) ** 2).sum(1).mean())
     print("proposal loss: first %.4f  last %.4f  (uniform guess %.4f)" % (losses[:20].mean(), losses[-20:].mean(), uni))
     assert losses[-20:].mean() < 0.5 * uni
