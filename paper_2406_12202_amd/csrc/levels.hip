@@ -47,6 +47,22 @@ hipError_t launch_level_predict(const LevelKey* key, const double* pose_in, doub
   return hipGetLastError();
 }
 
+// the call's key written for the later kernels, and the first level's
+// prediction from the same values (passed by value)
+__global__ __launch_bounds__(256) void k_level_begin(LevelKey* key, const LevelKey v, const double* pose_in,
+                                                     double* pose_out, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *key = v;
+  if (i >= N) return;
+  predict_pose(pose_in + (long)i * 12, pose_out + (long)i * 12, v.motion, v.sigma_t, v.sigma_r, v.seed, v.iter, i);
+}
+
+hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* pose_in, double* pose_out, int N,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_level_begin, dim3((N + 255) / 256), dim3(256), 0, st, key, v, pose_in, pose_out, N);
+  return hipGetLastError();
+}
+
 // one layer with weights resident in LDS: y = act(b + W x), MTO output tiles
 template <int NTL, int MTO, int KB1, int NX1, bool X1_LDS, int NY>
 __device__ __forceinline__ void dense_res(const uint4* w, const float* bl, const bool relu,

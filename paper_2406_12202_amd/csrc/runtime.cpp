@@ -1415,18 +1415,24 @@ LevelRayArgs level_ray_args(const loc_ctx* c, const LevelCall& q, int L) {
   return a;
 }
 
-// the level sequence (everything after the key upload) on stream st; with
-// `prof`, every launch is timed
-loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof) {
+// the level sequence on stream st; with `prof`, every launch is timed.  With
+// kv (eager calls) the first kernel writes the call's key and predicts from
+// it; without (a captured graph, replayed after upload_key) it reads the key
+loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof, const LevelKey* kv) {
   auto run = [&](int kid, double flop, double bytes, auto fn) -> loc_status {
     if (prof) return timed(c, kid, flop, bytes, fn);
     hipError_t e = fn();
     return e == hipSuccess ? LOC_OK : fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
   };
   loc_status s;
-  if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
-               [&] { return launch_level_predict(c->key, q.pose_in, c->lv[0].pose.p, q.N, st); })))
+  if (kv) {
+    if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
+                 [&] { return launch_level_begin(c->key, *kv, q.pose_in, c->lv[0].pose.p, q.N, st); })))
+      return s;
+  } else if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
+                      [&] { return launch_level_predict(c->key, q.pose_in, c->lv[0].pose.p, q.N, st); }))) {
     return s;
+  }
   for (int L = 0; L < q.n_levels; ++L) {
     auto& lv = c->lv[L];
     const LevelRayArgs ra = level_ray_args(c, q, L);
@@ -1546,15 +1552,19 @@ loc_status prepare_levels(loc_ctx* c, const float* image, const loc_camera* cam,
   return LOC_OK;
 }
 
-loc_status upload_key(loc_ctx* c, const double* motion, double sigma_t, double sigma_r, uint64_t seed,
-                      uint64_t iter) {
+loc_status make_key(loc_ctx* c, const double* motion, double sigma_t, double sigma_r, uint64_t seed, uint64_t iter,
+                    LevelKey& kv) {
   if (!(sigma_t >= 0.0) || !(sigma_r >= 0.0)) return fail(c, LOC_E_ARG, "negative noise scale");
-  LevelKey kv{};
+  kv = LevelKey{};
   kv.seed = seed;
   kv.iter = iter;
   for (int qd = 0; qd < 12; ++qd) kv.motion[qd] = motion ? motion[qd] : ((qd % 5 == 0) ? 1.0 : 0.0);
   kv.sigma_t = sigma_t;
   kv.sigma_r = sigma_r;
+  return LOC_OK;
+}
+
+loc_status upload_key(loc_ctx* c, const LevelKey& kv) {
   return timed(c, K_LV_KEY, 0, sizeof(LevelKey), [&] { return launch_set_key(c->key, kv, c->stream); });
 }
 
@@ -1575,14 +1585,16 @@ loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* c
     hipError_t pe = hipGetLastError();
     if (pe != hipSuccess) return fail(c, LOC_E_HIP, "pending HIP error: %s", hipGetErrorString(pe));
   }
-  if ((s = upload_key(c, motion, sigma_t, sigma_r, seed, iter))) return s;
-  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof != 0);
+  LevelKey kv;
+  if ((s = make_key(c, motion, sigma_t, sigma_r, seed, iter, kv))) return s;
+  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof != 0, &kv);
+  if ((s = upload_key(c, kv))) return s;
   std::vector<double> sig = level_signature(c, q);
   if (!c->gexec || sig != c->graph_sig) {
     drop_graph(c);
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    loc_status cs = enqueue_levels(c, q, c->cap_stream, false);
+    loc_status cs = enqueue_levels(c, q, c->cap_stream, false, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (cs) { if (g) hipGraphDestroy(g); return cs; }
@@ -1684,8 +1696,9 @@ loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera*
   for (int L = 0; L < n_levels; ++L) c->lv[L].ntl = c->lv[L].waves = c->lv[L].blocks = 0;
   const int prof = c->prof;
   c->prof = 0;
-  s = upload_key(c, nullptr, 0.0, 0.0, 12345, 0);
-  if (!s) s = enqueue_levels(c, q, c->stream, false);
+  LevelKey kv;
+  s = make_key(c, nullptr, 0.0, 0.0, 12345, 0, kv);
+  if (!s) s = enqueue_levels(c, q, c->stream, false, &kv);
   // cached choices
   std::vector<std::string> cache_lines;
   if (cache_path) {
