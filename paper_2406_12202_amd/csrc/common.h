@@ -64,20 +64,27 @@ __host__ __device__ inline double unit_open(uint32_t w) { return ((double)w + 0.
 // ---------------------------------------------------------------- camera rays
 // Ray of pixel (u, v) for a camera-to-world pose P (3 x 4, row-major): OpenGL
 // camera looking along -z, pixel centres at +1/2 (Eq. 4's r(p, x) with
-// intrinsics K); the rotation is applied in float64 with explicit fused
-// multiply-adds (so every kernel that forms a ray gets the same bits) and the
-// unit direction is rounded once to float32.
+// intrinsics K).  Float32 throughout: the pose and the intrinsics are rounded
+// to float32 once, the camera-frame direction is formed and rotated with
+// explicit fused multiply-adds (so every kernel that forms a ray gets the
+// same bits) and normalised.  Float64 stays with the poses themselves.
 __device__ __forceinline__ void camera_ray(const double* P, int u, int v, double fx, double fy, double cx, double cy,
                                            float (&o)[3], float (&d)[3]) {
-  const double dc0 = ((double)u + 0.5 - cx) / fx;
-  const double dc1 = -((double)v + 0.5 - cy) / fy;
-  double d0 = fma(P[0], dc0, fma(P[1], dc1, -P[2]));
-  double d1 = fma(P[4], dc0, fma(P[5], dc1, -P[6]));
-  double d2 = fma(P[8], dc0, fma(P[9], dc1, -P[10]));
-  const double inv = 1.0 / sqrt(fma(d0, d0, fma(d1, d1, d2 * d2)));
-  d0 *= inv; d1 *= inv; d2 *= inv;
+  const float dc0 = ((float)u + 0.5f - (float)cx) / (float)fx;
+  const float dc1 = -(((float)v + 0.5f - (float)cy) / (float)fy);
+  float r[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[3 * k] = (float)P[4 * k];
+    r[3 * k + 1] = (float)P[4 * k + 1];
+    r[3 * k + 2] = (float)P[4 * k + 2];
+  }
+  float d0 = fmaf(r[0], dc0, fmaf(r[1], dc1, -r[2]));
+  float d1 = fmaf(r[3], dc0, fmaf(r[4], dc1, -r[5]));
+  float d2 = fmaf(r[6], dc0, fmaf(r[7], dc1, -r[8]));
+  const float inv = 1.0f / sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
   o[0] = (float)P[3]; o[1] = (float)P[7]; o[2] = (float)P[11];
-  d[0] = (float)d0; d[1] = (float)d1; d[2] = (float)d2;
+  d[0] = d0 * inv; d[1] = d1 * inv; d[2] = d2 * inv;
 }
 
 // ---------------------------------------------------------------- wave primitives

@@ -96,9 +96,9 @@ __device__ __forceinline__ void dense_res(const uint4* w, const float* bl, const
 }
 
 // per-lane set-up of ray r as k_raygen computes it: query pixel p_j, the
-// unit direction through it (rotation in float64, one rounding to float32),
+// unit direction through it (camera_ray, float32),
 // the origin, and the S x S box average of the observation (row-major sum in
-// float64); S is the level factor
+// float32, as k_raygen); S is the level factor
 constexpr int kRayBatch = 8;   // rays set up per wave at once (one per lane)
 
 struct RaySetup {
@@ -116,7 +116,7 @@ __device__ __forceinline__ void ray_setup(const LevelRayArgs& a, uint64_t seed, 
   const uint32_t p = (uint32_t)(((uint64_t)w * npix) >> 32);
   const int u = (int)(p % (uint32_t)a.Wl), v = (int)(p / (uint32_t)a.Wl);
   camera_ray(a.pose + (long)i * 12, u, v, a.fx, a.fy, a.cx, a.cy, rs.o, rs.d);
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
   for (int yy = 0; yy < S; ++yy) {
     const float* row = a.image + ((long)(v * S + yy) * a.W_full + (long)u * S) * 3;
@@ -126,8 +126,8 @@ __device__ __forceinline__ void ray_setup(const LevelRayArgs& a, uint64_t seed, 
 #pragma unroll
     for (int xx = 0; xx < S; ++xx) { c0 += px[3 * xx]; c1 += px[3 * xx + 1]; c2 += px[3 * xx + 2]; }
   }
-  const double sc = 1.0 / ((double)S * S);
-  rs.obs[0] = (float)(c0 * sc); rs.obs[1] = (float)(c1 * sc); rs.obs[2] = (float)(c2 * sc);
+  const float sc = 1.0f / (float)(S * S);
+  rs.obs[0] = c0 * sc; rs.obs[1] = c1 * sc; rs.obs[2] = c2 * sc;
 }
 
 // segmented wave primitives over the two 32-lane halves (for lanes of half 0

@@ -8,8 +8,9 @@ namespace fl {
 // ---------------------------------------------------------------------------
 // ray generation: query pixel p_j at level R, its box-averaged observation and
 // the camera ray of particle i through it (Eq. 4's r(p, x) with intrinsics R K;
-// OpenGL camera, pixel centres at +1/2).  One thread per ray; the rotation is
-// applied in float64 and the unit direction rounded once to float32.
+// OpenGL camera, pixel centres at +1/2).  One thread per ray, float32 (the
+// pose rounded once; camera_ray); the box average sums the s x s block row by
+// row in float32.
 __global__ __launch_bounds__(256) void k_raygen(const RaygenArgs a) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.N * a.B) return;
@@ -24,15 +25,15 @@ __global__ __launch_bounds__(256) void k_raygen(const RaygenArgs a) {
   a.ray_d[r] = make_float4(d[0], d[1], d[2], 0.0f);
   if (!a.image) return;
   // downscale(I_t, R_t): mean of the s x s block behind level pixel (u, v)
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
   for (int yy = 0; yy < a.s; ++yy) {
     const float* row = a.image + ((long)(v * a.s + yy) * a.W_full + (long)u * a.s) * 3;
     for (int xx = 0; xx < a.s; ++xx) {
       c0 += row[3 * xx + 0]; c1 += row[3 * xx + 1]; c2 += row[3 * xx + 2];
     }
   }
-  const double sc = 1.0 / ((double)a.s * a.s);
-  a.obs[r] = make_float4((float)(c0 * sc), (float)(c1 * sc), (float)(c2 * sc), 0.0f);
+  const float sc = 1.0f / (float)(a.s * a.s);   // a power of two: exact
+  a.obs[r] = make_float4(c0 * sc, c1 * sc, c2 * sc, 0.0f);
 }
 
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st) {

@@ -22,9 +22,13 @@ float32 accumulation, float32 compositing) against two oracles.
                            renormalised over the subset on both sides
 2. The BF16-configuration oracle (the same roundings, float64 sums), which
    must agree far more closely: what remains is float32 accumulation order
-   and the kernels' float32 positions and encodings, which move some of the
-   highest-band encoding values across a bf16 rounding boundary.
-     C, A: p99 <= 4e-3, max <= 1e-2; F: p99 <= 2e-2; l: <= 1e-2; w: <= 2e-3
+   and the kernels' float32 rays, positions and encodings, which move some of
+   the highest-band encoding values across a bf16 rounding boundary.
+     C, A: p99 <= 4e-3, max <= 1e-2; l: <= 1e-2; w: <= 2e-3
+     F: the conditioning bound above with a relative optical-depth error of
+        0.02 instead of 0.1, median <= 1e-3 (a flat bar on F does not hold
+        at crossings where the density is small: one bf16 step of an
+        encoding moves such a crossing by centimetres)
 Structural mistakes (a missing k-block, a permuted feature) move colours by
 O(0.1 - 1) and fail both.
 """
@@ -47,13 +51,28 @@ def torch_dev():
 
 EPS_TAU = 0.1
 FP64_BARS = dict(C_P99=2e-2, A_P99=2e-2, F_P50=2e-3, L_MAX=0.1, W_MAX=5e-3)
-FIDELITY_BARS = dict(C_P99=4e-3, C_MAX=1e-2, F_P99=2e-2, L_MAX=1e-2, W_MAX=2e-3)
+FIDELITY_BARS = dict(C_P99=4e-3, C_MAX=1e-2, F_P50=1e-3, L_MAX=1e-2, W_MAX=2e-3)
+EPS_TAU_BF16 = 0.02
 
 
 def _subset_weights(ll):
     ll = np.asarray(ll, dtype=np.float64)
     e = np.exp(ll - ll.max())
     return e / e.sum()
+
+
+def _check_F(gF, o, alpha, eps):
+    """F = z_opaque - z_trans (Eq. 5) against the oracle's, ray by ray, within
+    what a relative optical-depth error eps moves it: a crossing where the
+    density is sigma moves by |log level| eps / sigma, so the bound is
+    eps (|log(1 - alpha)| / sigma_trans + |log alpha| / sigma_opaque) + 2e-3."""
+    kt = np.where(np.isnan(o["sig_trans"]), 0.0, abs(math.log1p(-alpha)) / o["sig_trans"])
+    ko = np.where(np.isnan(o["sig_opaque"]), 0.0, abs(math.log(alpha)) / o["sig_opaque"])
+    bound = eps * (kt + ko) + 2e-3
+    dF = np.abs(gF - o["F"])
+    inside = (dF <= bound).mean()
+    print("F within conditioning bound (eps %.2g): %.4f of %d rays" % (eps, inside, dF.size))
+    assert inside >= 0.99 or (dF.size < 100 and (dF > bound).sum() <= 1)
 
 
 def _check(g, o, alpha=0.05, subset=None, o16=None):
@@ -74,14 +93,7 @@ def _check(g, o, alpha=0.05, subset=None, o16=None):
     a_in = (np.abs(g["A"][idx] - o["A"]) <= a_bound).mean()
     print("A within optical-depth bound: %.4f" % a_in)
     assert a_in >= 0.99
-    # conditioning-aware bound on F
-    kt = np.where(np.isnan(o["sig_trans"]), 0.0, abs(math.log1p(-alpha)) / o["sig_trans"])
-    ko = np.where(np.isnan(o["sig_opaque"]), 0.0, abs(math.log(alpha)) / o["sig_opaque"])
-    bound = EPS_TAU * (kt + ko) + 2e-3
-    dF = np.abs(g["F"][idx] - o["F"])
-    inside = (dF <= bound).mean()
-    print("F within conditioning bound: %.4f of %d rays" % (inside, dF.size))
-    assert inside >= 0.99 or (dF.size < 100 and (dF > bound).sum() <= 1)
+    _check_F(g["F"][idx], o, alpha, EPS_TAU)
     assert rF["p50"] <= FP64_BARS["F_P50"]
     # log-likelihood: GPU-internal consistency and the bar against the oracle
     EFg = (g["E"][idx] * g["F"][idx]).astype(np.float64)
@@ -100,7 +112,8 @@ def _check(g, o, alpha=0.05, subset=None, o16=None):
         print("weight     max=%.3e" % fw)
         for r in (fC, fA):
             assert r["p99"] <= FIDELITY_BARS["C_P99"] and r["max"] <= FIDELITY_BARS["C_MAX"]
-        assert fF["p99"] <= FIDELITY_BARS["F_P99"]
+        _check_F(g["F"][idx], o16, alpha, EPS_TAU_BF16)
+        assert fF["p50"] <= FIDELITY_BARS["F_P50"]
         assert fL["max"] <= FIDELITY_BARS["L_MAX"] and fw <= FIDELITY_BARS["W_MAX"]
 
 

@@ -2,7 +2,9 @@
 against the FP64 oracle, and the gain test of the trained network.
 
 Bars (FP32 kernels):
-  rays (loc_cast_rays)          |d| and |o| within 2e-7 / 1e-6 of the oracle
+  rays (loc_cast_rays)          |d| and |o| within 5e-7 / 1e-6 of the oracle (the
+                                direction formed in float32 from the rounded pose:
+                                about seven float32 roundings of unit size)
   teacher histograms            99.5% of bins within 1e-4, rows sum to 1
   forward probabilities         within 2e-6
   gradient                      cosine >= 0.9999 and relative L2 <= 1e-4
@@ -58,7 +60,7 @@ def test_cast_rays_match_oracle(torch_dev):
         rays = mcl.particle_rays(poses[i], pix, W // 2, (fx / 2, fy / 2, cx / 2, cy / 2))
         for j, (ro, rd_) in enumerate(rays):
             assert np.abs(o[i * 8 + j] - ro).max() <= 1e-6
-            assert np.abs(d[i * 8 + j] - rd_).max() <= 2e-7
+            assert np.abs(d[i * 8 + j] - rd_).max() <= 5e-7
 
 
 @pytest.mark.parametrize("n_rays", [24, 23])
