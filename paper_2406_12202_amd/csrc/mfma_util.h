@@ -73,6 +73,24 @@ __device__ __forceinline__ void posenc_b(const float p0, const float p1, const f
   for (int kb = 0; kb < KB; ++kb) out[kb] = h ? both[1][kb] : both[0][kb];
 }
 
+// raw buffer resource over n_bytes at p (stride 0, 32-bit data format):
+// reads past n_bytes return zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, const int n_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n_bytes, 0x00020000);
+}
+
+// the direct loads of issue_blocks through the buffer path (buffer_load ...
+// lds): while loads of this form are in flight the compiler still counts
+// outstanding LDS reads one by one, whereas with the global form in flight
+// it waits for all of them at every use
+template <int WAVES>
+__device__ __forceinline__ void issue_blocks_buf(const __amdgpu_buffer_rsrc_t r, const long base, const int nkb,
+                                                 uint4* slot, const int wv, const int lane) {
+  for (int b = wv; b < nkb; b += WAVES)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)(slot + b * 64), 16,
+                                             (unsigned)(((base + b) * 64 + lane) * 16), 0, 0, 0);
+}
+
 // issue the direct loads of nkb consecutive 1 KB units into an LDS slot;
 // wave wv takes units wv, wv + WAVES, ...
 template <int WAVES>

@@ -94,10 +94,13 @@ __device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const flo
       uint4* nxt = ((mt / MPC) & 1) ? slot0 : slot1;
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      // buffer-path loads: with the global form in flight the compiler waits
+      // for all outstanding LDS reads at every use
+      const __amdgpu_buffer_rsrc_t wr = raw_rsrc(wb, (int)(S::UNITS * 1024));
       if (mt + MPC < MTO)
-        issue_blocks<WAVES>(wb, base + (long)(mt + MPC) * u_tot, MPC * u_tot, nxt, wv, lane);
+        issue_blocks_buf<WAVES>(wr, base + (long)(mt + MPC) * u_tot, MPC * u_tot, nxt, wv, lane);
       else if (l + 1 < S::NL)
-        issue_blocks<WAVES>(wb, S::unit_base(l + 1), MPC * S::layer_units(l + 1), nxt, wv, lane);
+        issue_blocks_buf<WAVES>(wr, S::unit_base(l + 1), MPC * S::layer_units(l + 1), nxt, wv, lane);
     }
     const uint4* cur = grp + (mt % MPC) * u_tot * 64;
     f32x16 binit;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
-  issue_blocks<WAVES>(wb, 0, MPC * S::layer_units(0), slot0, wv, lane);
+  issue_blocks_buf<WAVES>(raw_rsrc(wb, (int)(S::UNITS * 1024)), 0, MPC * S::layer_units(0), slot0, wv, lane);
   for (int i = threadIdx.x; i < S::BIASES / 4; i += THREADS) s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
   for (int i = threadIdx.x; i < S::HEADS / 4; i += THREADS) s_heads[i] = reinterpret_cast<const float4*>(a.heads)[i];
 
