@@ -19,9 +19,19 @@ hipError_t launch_predict(const PredictArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// a set that fits is read once into LDS, so the passes over it do not wait
+// on memory (the arithmetic is the same either way)
 __global__ __launch_bounds__(kRedThreads) void k_normalize(const double* ll, double* w, int N, int* flags) {
-  __shared__ double s[kRedThreads];
-  normalize_block(ll, w, N, flags, s);
+  __shared__ double s[kRedThreads / 64];
+  __shared__ double s_l[kPrefixLds], s_w[kPrefixLds];
+  if (N <= kPrefixLds) {
+    for (int i = threadIdx.x; i < N; i += kRedThreads) s_l[i] = ll[i];
+    __syncthreads();
+    normalize_block(s_l, s_w, N, flags, s);
+    for (int i = threadIdx.x; i < N; i += kRedThreads) w[i] = s_w[i];
+  } else {
+    normalize_block(ll, w, N, flags, s);
+  }
 }
 
 hipError_t launch_normalize(const double* loglik, double* weight, int N, int* flags, hipStream_t st) {
@@ -32,9 +42,17 @@ hipError_t launch_normalize(const double* loglik, double* weight, int N, int* fl
 __global__ __launch_bounds__(kRedThreads) void k_resample(const double* weight, int n_in, int n_out,
                                                           uint64_t seed, uint64_t iter, u64* prefix,
                                                           int32_t* idx, int* flags) {
-  __shared__ double s_max[kRedThreads];
-  __shared__ u64 s_sum[kRedThreads];
-  resample_block(weight, n_in, n_out, seed, iter, prefix, idx, flags, s_max, s_sum);
+  __shared__ double s_max[kRedThreads / 64];
+  __shared__ u64 s_sum[kRedThreads / 64];
+  __shared__ u64 s_prefix[kPrefixLds];
+  __shared__ double s_w[kPrefixLds];
+  if (n_in <= kPrefixLds) {
+    for (int i = threadIdx.x; i < n_in; i += kRedThreads) s_w[i] = weight[i];
+    __syncthreads();
+    resample_block(s_w, n_in, n_out, seed, iter, prefix, idx, flags, s_max, s_sum, s_prefix);
+  } else {
+    resample_block(weight, n_in, n_out, seed, iter, prefix, idx, flags, s_max, s_sum, s_prefix);
+  }
 }
 
 hipError_t launch_resample(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,

@@ -76,10 +76,79 @@ __device__ __forceinline__ void predict_pose(const double* __restrict__ xin, dou
 }
 
 // ---------------------------------------------------------------------------
-// w_i = exp(l_i - m) / sum_k exp(l_k - m), m = max over finite l (Eq. 3).
-// Fixed strided assignment and a fixed tree: deterministic sums.
+// Workgroup reductions and scans.  Within a 64-lane wave: an inclusive scan
+// by DPP lane moves (row shifts by 1, 2, 4, 8, then the row broadcasts of
+// lanes 15 and 31), a few cycles per step where a shuffle through LDS takes
+// a hundred; lane 63 ends with the wave total.  The wave totals meet in LDS
+// and are combined the same way in every wave.  The order is fixed, so the
+// results are deterministic; two barriers per workgroup reduction.
 constexpr int kRedThreads = 1024;
 
+// an 8-byte value moved by DPP control CTRL (row mask RM); `fill` where the
+// control has no source lane or the row is masked off
+template <int CTRL, int RM, class T>
+__device__ __forceinline__ T dpp_move(const T v, const T fill) {
+  static_assert(sizeof(T) == 8, "8-byte values");
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)u, CTRL, RM, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(u >> 32), CTRL,
+                                                            RM, 0xf, false);
+  return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+}
+
+// inclusive scan over the 64 lanes of a wave with the associative op, whose
+// identity is `id`
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan(T v, const T id, Op op) {
+  v = op(v, dpp_move<0x111, 0xf>(v, id));   // row_shr:1
+  v = op(v, dpp_move<0x112, 0xf>(v, id));   // row_shr:2
+  v = op(v, dpp_move<0x114, 0xf>(v, id));   // row_shr:4
+  v = op(v, dpp_move<0x118, 0xf>(v, id));   // row_shr:8
+  v = op(v, dpp_move<0x142, 0xa>(v, id));   // row_bcast:15 into rows 1 and 3
+  v = op(v, dpp_move<0x143, 0xc>(v, id));   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T lane_value(const T v, const int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+}
+
+struct OpAdd {
+  __device__ double operator()(const double a, const double b) const { return a + b; }
+};
+struct OpMax {
+  __device__ double operator()(const double a, const double b) const { return fmax(a, b); }
+};
+struct OpAddU64 {
+  __device__ unsigned long long operator()(const unsigned long long a, const unsigned long long b) const {
+    return a + b;
+  }
+};
+
+// s: one value per wave of the workgroup (LDS); every thread gets the result
+template <class Op>
+__device__ __forceinline__ double block_reduce(double v, const double id, Op op, double* s) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = lane_value(wave_scan(v, id, op), 63);
+  if (lane == 0) s[w] = v;
+  __syncthreads();
+  const double t = lane_value(wave_scan(lane < nw ? s[lane] : id, id, op), 63);
+  __syncthreads();
+  return t;
+}
+__device__ __forceinline__ double block_sum(const double v, double* s) { return block_reduce(v, 0.0, OpAdd{}, s); }
+__device__ __forceinline__ double block_max(const double v, double* s) {
+  return block_reduce(v, -INFINITY, OpMax{}, s);
+}
+__device__ __forceinline__ double wave_sum(const double v) { return lane_value(wave_scan(v, 0.0, OpAdd{}), 63); }
+
+// w_i = exp(l_i - m) / sum_k exp(l_k - m), m = max over finite l (Eq. 3).
+// Fixed strided assignment and fixed reduction order: deterministic sums.
 __device__ inline void normalize_block(const double* ll, double* w, int N, int* flags, double* s) {
   const int tid = threadIdx.x;
   double m = -INFINITY;
@@ -87,27 +156,14 @@ __device__ inline void normalize_block(const double* ll, double* w, int N, int* 
     const double v = ll[i];
     if (isfinite(v)) m = fmax(m, v);
   }
-  s[tid] = m;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s[tid] = fmax(s[tid], s[tid + o]);
-    __syncthreads();
-  }
-  m = s[0];
-  __syncthreads();
+  m = block_max(m, s);
   const bool none = !(m > -INFINITY);
   double acc = 0.0;
   for (int i = tid; i < N; i += kRedThreads) {
     const double v = ll[i];
     if (!none && isfinite(v)) acc += exp(v - m);
   }
-  s[tid] = acc;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s[tid] += s[tid + o];
-    __syncthreads();
-  }
-  const double tot = s[0];
+  const double tot = block_sum(acc, s);
   for (int i = tid; i < N; i += kRedThreads) {
     const double v = ll[i];
     w[i] = (!none && isfinite(v)) ? exp(v - m) / tot : 0.0;
@@ -138,39 +194,53 @@ __device__ inline u64 resample_threshold(u64 a, u64 Q, u64 n) {
   return q;
 }
 
-// idx[k] = -1 for every k and flag 2 when all weights are zero
+// lower bound min{i : P_i > th} over the inclusive prefix P[0 .. n)
+template <class P>
+__device__ inline int prefix_search(const P* prefix, const int n, const u64 th) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] > th) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// inclusive prefix of the integer weights kept in LDS up to this many
+// entries (the searches then read LDS), in the global array beyond
+constexpr int kPrefixLds = 4096;
+
+// idx[k] = -1 for every k and flag 2 when all weights are zero.  s_max: one
+// double per wave; s_sum: one u64 per wave; s_prefix: kPrefixLds u64 (LDS).
 __device__ inline void resample_block(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
-                                      u64* prefix, int32_t* idx, int* flags, double* s_max, u64* s_sum) {
-  const int tid = threadIdx.x;
+                                      u64* prefix, int32_t* idx, int* flags, double* s_max, u64* s_sum,
+                                      u64* s_prefix) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double m = 0.0;
   for (int i = tid; i < n_in; i += kRedThreads) m = fmax(m, clean_weight(weight[i]));
-  s_max[tid] = m;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s_max[tid] = fmax(s_max[tid], s_max[tid + o]);
-    __syncthreads();
-  }
-  const double wmax = s_max[0];
-  // contiguous chunk per thread: local sums, block inclusive scan, local prefixes
+  const double wmax = block_max(m, s_max);
+  // contiguous chunk per thread: local sums, workgroup inclusive scan (waves
+  // by shuffles, then the wave totals), local prefixes
   const int chunk = (n_in + kRedThreads - 1) / kRedThreads;
   const int b0 = min(tid * chunk, n_in), b1 = min(b0 + chunk, n_in);
   u64 local = 0;
   if (wmax > 0.0)
     for (int i = b0; i < b1; ++i) local += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
-  s_sum[tid] = local;
+  const u64 incl = wave_scan(local, (u64)0, OpAddU64{});
+  if (lane == 63) s_sum[w] = incl;
   __syncthreads();
-  for (int o = 1; o < kRedThreads; o <<= 1) {     // Hillis-Steele inclusive scan
-    const u64 v = (tid >= o) ? s_sum[tid - o] : 0;
-    __syncthreads();
-    s_sum[tid] += v;
-    __syncthreads();
+  u64 before = 0, Q = 0;
+  for (int v = 0; v < kRedThreads / 64; ++v) {
+    const u64 t = s_sum[v];
+    if (v < w) before += t;
+    Q += t;
   }
-  const u64 Q = s_sum[kRedThreads - 1];
-  u64 run = s_sum[tid] - local;
+  const bool in_lds = n_in <= kPrefixLds;
+  u64 run = before + incl - local;
   if (wmax > 0.0)
     for (int i = b0; i < b1; ++i) {
       run += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
-      prefix[i] = run;
+      if (in_lds) s_prefix[i] = run;
+      else prefix[i] = run;
     }
   __threadfence_block();
   __syncthreads();
@@ -181,12 +251,7 @@ __device__ inline void resample_block(const double* weight, int n_in, int n_out,
     const u64 r0 = draw(seed, iter, kStreamResample, 0, 0, 0).x;
     for (int k = tid; k < n_out; k += kRedThreads) {
       const u64 th = resample_threshold(((u64)k << 32) + r0, Q, (u64)n_out);
-      int lo = 0, hi = n_in - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] > th) hi = mid; else lo = mid + 1;
-      }
-      idx[k] = lo;
+      idx[k] = in_lds ? prefix_search(s_prefix, n_in, th) : prefix_search(prefix, n_in, th);
     }
   }
   __threadfence_block();
@@ -241,7 +306,7 @@ __device__ inline void sym3_min_eigvec(const double* Ain, double* v) {
 
 constexpr int kEstThreads = 256;
 
-// threads 0 .. kEstThreads-1 of the workgroup accumulate; s: kEstThreads x 13 doubles
+// threads 0 .. kEstThreads-1 of the workgroup accumulate; s: at least 4 x 13 doubles
 __device__ inline void pose_estimate_block(const double* pose, const double* w, int N, double* est, int* flags,
                                            double (*s)[13]) {
   const int tid = threadIdx.x;
@@ -257,15 +322,14 @@ __device__ inline void pose_estimate_block(const double* pose, const double* w, 
       }
       acc[12] += wi;
     }
-    for (int q = 0; q < 13; ++q) s[tid][q] = acc[q];
+    for (int q = 0; q < 13; ++q) acc[q] = wave_sum(acc[q]);
+    if ((tid & 63) == 0)
+      for (int q = 0; q < 13; ++q) s[tid >> 6][q] = acc[q];
   }
   __syncthreads();
-  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
-    if (tid < o)
-      for (int q = 0; q < 13; ++q) s[tid][q] += s[tid + o][q];
-    __syncthreads();
-  }
   if (tid == 0) {
+    static_assert(kEstThreads == 256, "four wave totals");
+    for (int q = 0; q < 13; ++q) s[0][q] = (s[0][q] + s[1][q]) + (s[2][q] + s[3][q]);
     const double W = s[0][12];
     bool done = false;
     if (!(W > 0.0)) {
@@ -287,7 +351,7 @@ __device__ inline void pose_estimate_block(const double* pose, const double* w, 
       // scaling: Q <- (g Q + Q^{-T} / g) / 2, g = |det Q|^(-1/3)
       for (int it = 0; it < 60; ++it) {
         const double d = mat3_det(Q);
-        const double g = pow(fabs(d), -1.0 / 3.0);
+        const double g = rcbrt(fabs(d));
         double C[9];   // cofactor matrix: Q^{-T} = C / det Q
         C[0] = Q[4] * Q[8] - Q[5] * Q[7]; C[1] = Q[5] * Q[6] - Q[3] * Q[8]; C[2] = Q[3] * Q[7] - Q[4] * Q[6];
         C[3] = Q[2] * Q[7] - Q[1] * Q[8]; C[4] = Q[0] * Q[8] - Q[2] * Q[6]; C[5] = Q[1] * Q[6] - Q[0] * Q[7];
@@ -330,7 +394,7 @@ __device__ inline void pose_estimate_block(const double* pose, const double* w, 
 // spread of a weighted particle set: sum_i w_i |t_i - t_bar|^2 / sum_i w_i
 // (trace of the weighted covariance of the positions; w <= 0 or non-finite
 // counts as 0; NaN without weight); two fixed-order passes over kEstThreads
-// threads; s: kEstThreads x 4 doubles
+// threads; s: at least 4 x 4 doubles
 __device__ inline void position_variance_block(const double* pose, const double* w, int N, double* var,
                                                double (*s)[4]) {
   const int tid = threadIdx.x;
@@ -341,16 +405,15 @@ __device__ inline void position_variance_block(const double* pose, const double*
       for (int r = 0; r < 3; ++r) acc[r] += wi * pose[(long)i * 12 + 4 * r + 3];
       acc[3] += wi;
     }
-    for (int q = 0; q < 4; ++q) s[tid][q] = acc[q];
+    for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+    if ((tid & 63) == 0)
+      for (int q = 0; q < 4; ++q) s[tid >> 6][q] = acc[q];
   }
   __syncthreads();
-  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
-    if (tid < o)
-      for (int q = 0; q < 4; ++q) s[tid][q] += s[tid + o][q];
-    __syncthreads();
-  }
-  const double W = s[0][3];
-  const double tb[3] = {s[0][0] / W, s[0][1] / W, s[0][2] / W};
+  double tot[4];
+  for (int q = 0; q < 4; ++q) tot[q] = (s[0][q] + s[1][q]) + (s[2][q] + s[3][q]);
+  const double W = tot[3];
+  const double tb[3] = {tot[0] / W, tot[1] / W, tot[2] / W};
   __syncthreads();
   if (tid < kEstThreads) {
     double v = 0.0;
@@ -363,14 +426,11 @@ __device__ inline void position_variance_block(const double* pose, const double*
       }
       v += wi * d2;
     }
-    s[tid][0] = v;
+    v = wave_sum(v);
+    if ((tid & 63) == 0) s[tid >> 6][0] = v;
   }
   __syncthreads();
-  for (int o = kEstThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s[tid][0] += s[tid + o][0];
-    __syncthreads();
-  }
-  if (tid == 0) *var = W > 0.0 ? s[0][0] / W : NAN;
+  if (tid == 0) *var = W > 0.0 ? ((s[0][0] + s[1][0]) + (s[2][0] + s[3][0])) / W : NAN;
   __threadfence_block();
   __syncthreads();
 }

@@ -419,58 +419,67 @@ hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishArgs a) {
-  __shared__ double s_d[kEstThreads * 13];   // >= kRedThreads doubles; reused by every phase
-  __shared__ u64 s_u[kRedThreads];
-  __shared__ double s_stat[2];
+// Rejection (mean F above mean + one standard deviation, Sec. III-C),
+// normalisation, read-out and the draw of one level on the particles' l and
+// mean F (L, W: LDS copies for small sets, else the global arrays; W holds
+// the weights on return).
+__device__ __forceinline__ void level_weigh_and_draw(const LevelFinishArgs& a, double* L, double* W, double* s_d,
+                                                     u64* s_u, u64* s_prefix, const uint64_t seed,
+                                                     const uint64_t iter) {
   const int tid = threadIdx.x;
-  const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
-  // scores, mean F (in weight[]) come from k_level_scores
   if (a.reject) {
     // mean and population standard deviation of the mean F over particles
     // with finite mean F and finite l; particles above mean + std get -inf
     double cnt = 0.0, sum = 0.0;
     for (int i = tid; i < a.N; i += kRedThreads) {
-      const double U = a.weight[i];
-      if (isfinite(U) && isfinite(a.loglik[i])) { cnt += 1.0; sum += U; }
+      const double U = W[i];
+      if (isfinite(U) && isfinite(L[i])) { cnt += 1.0; sum += U; }
     }
-    s_d[tid] = sum;
-    s_u[tid] = (u64)cnt;
-    __syncthreads();
-    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-      if (tid < o) { s_d[tid] += s_d[tid + o]; s_u[tid] += s_u[tid + o]; }
-      __syncthreads();
-    }
-    if (tid == 0) s_stat[0] = s_u[0] > 0 ? s_d[0] / (double)s_u[0] : 0.0;
-    __syncthreads();
-    const double mu = s_stat[0];
-    const double n_ok = (double)s_u[0];
-    __syncthreads();
+    const double n_ok = block_sum(cnt, s_d);
+    const double mu = n_ok > 0.0 ? block_sum(sum, s_d) / n_ok : 0.0;
     double ss = 0.0;
     for (int i = tid; i < a.N; i += kRedThreads) {
-      const double U = a.weight[i];
-      if (isfinite(U) && isfinite(a.loglik[i])) ss += (U - mu) * (U - mu);
+      const double U = W[i];
+      if (isfinite(U) && isfinite(L[i])) ss += (U - mu) * (U - mu);
     }
-    s_d[tid] = ss;
-    __syncthreads();
-    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-      if (tid < o) s_d[tid] += s_d[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) s_stat[1] = n_ok > 0.0 ? sqrt(s_d[0] / n_ok) : 0.0;
-    __syncthreads();
-    const double thr = mu + s_stat[1];
+    const double sd = block_sum(ss, s_d);
+    const double thr = mu + (n_ok > 0.0 ? sqrt(sd / n_ok) : 0.0);
     for (int i = tid; i < a.N; i += kRedThreads) {
-      const double U = a.weight[i];
-      const bool ok = isfinite(U) && isfinite(a.loglik[i]);
-      if (!ok || U > thr) a.loglik[i] = -INFINITY;
+      const double U = W[i];
+      const bool ok = isfinite(U) && isfinite(L[i]);
+      if (!ok || U > thr) L[i] = -INFINITY;
     }
     __threadfence_block();
     __syncthreads();
   }
-  normalize_block(a.loglik, a.weight, a.N, a.flags, s_d);
-  if (a.est) pose_estimate_block(a.pose, a.weight, a.N, a.est, a.flags, reinterpret_cast<double(*)[13]>(s_d));
-  resample_block(a.weight, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u);
+  normalize_block(L, W, a.N, a.flags, s_d);
+  if (a.est) pose_estimate_block(a.pose, W, a.N, a.est, a.flags, reinterpret_cast<double(*)[13]>(s_d));
+  resample_block(W, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u, s_prefix);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishArgs a) {
+  __shared__ double s_d[kEstThreads * 13];   // reused by every phase
+  __shared__ u64 s_u[kRedThreads / 64];
+  __shared__ u64 s_prefix[kPrefixLds];
+  __shared__ double s_l[kPrefixLds], s_w[kPrefixLds];
+  const int tid = threadIdx.x;
+  const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
+  // scores, mean F (in weight[]) come from k_level_scores; a set that fits is
+  // read once into LDS, so the passes over it do not wait on memory
+  if (a.N <= kPrefixLds) {
+    for (int i = tid; i < a.N; i += kRedThreads) {
+      s_l[i] = a.loglik[i];
+      s_w[i] = a.weight[i];
+    }
+    __syncthreads();
+    level_weigh_and_draw(a, s_l, s_w, s_d, s_u, s_prefix, seed, iter);
+    for (int i = tid; i < a.N; i += kRedThreads) {
+      a.loglik[i] = s_l[i];
+      a.weight[i] = s_w[i];
+    }
+  } else {
+    level_weigh_and_draw(a, a.loglik, a.weight, s_d, s_u, s_prefix, seed, iter);
+  }
   // gather the drawn poses; apply the next level's prediction to particle k
   for (int k = tid; k < a.n_out; k += kRedThreads) {
     const int i = a.idx[k];
