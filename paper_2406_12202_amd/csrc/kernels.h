@@ -255,10 +255,10 @@ struct LevelFinishArgs {
   int* flags;
 };
 
-hipError_t launch_set_key(LevelKey* key, const LevelKey& v, hipStream_t st);
-hipError_t launch_level_predict(const LevelKey* key, const double* pose_in, double* pose_out, int N, hipStream_t st);
 hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* pose_in, double* pose_out, int N,
                               hipStream_t st);
+hipError_t set_level_begin_node(hipGraphExec_t ge, hipGraphNode_t node, LevelKey* key, const LevelKey& v,
+                                const double* pose_in, double* pose_out, int N);
 // tile configuration (column tiles per wave, waves per workgroup), grid size
 hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int blocks, hipStream_t st);
 bool level_rays_config_ok(int ntl, int waves);

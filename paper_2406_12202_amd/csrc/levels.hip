@@ -25,28 +25,6 @@ namespace fl {
 using LS = SmallMapB;
 constexpr int kLevelSpr = 32;   // samples per ray on this path
 
-__global__ void k_set_key(LevelKey* key, const LevelKey v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *key = v;
-}
-
-hipError_t launch_set_key(LevelKey* key, const LevelKey& v, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_key, dim3(1), dim3(64), 0, st, key, v);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_level_predict(const LevelKey* key, const double* pose_in, double* pose_out,
-                                                       int N) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  predict_pose(pose_in + (long)i * 12, pose_out + (long)i * 12, key->motion, key->sigma_t, key->sigma_r, key->seed,
-               key->iter, i);
-}
-
-hipError_t launch_level_predict(const LevelKey* key, const double* pose_in, double* pose_out, int N, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_predict, dim3((N + 255) / 256), dim3(256), 0, st, key, pose_in, pose_out, N);
-  return hipGetLastError();
-}
-
 // the call's key written for the later kernels, and the first level's
 // prediction from the same values (passed by value)
 __global__ __launch_bounds__(256) void k_level_begin(LevelKey* key, const LevelKey v, const double* pose_in,
@@ -61,6 +39,25 @@ hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* po
                               hipStream_t st) {
   hipLaunchKernelGGL(k_level_begin, dim3((N + 255) / 256), dim3(256), 0, st, key, v, pose_in, pose_out, N);
   return hipGetLastError();
+}
+
+// the k_level_begin node of an instantiated graph given the next call's key
+// (the node keeps its launch shape; its arguments are copied when set)
+hipError_t set_level_begin_node(hipGraphExec_t ge, hipGraphNode_t node, LevelKey* key, const LevelKey& v,
+                                const double* pose_in, double* pose_out, int N) {
+  hipKernelNodeParams p{};
+  hipError_t e = hipGraphKernelNodeGetParams(node, &p);
+  if (e != hipSuccess) return e;
+  if (p.func != reinterpret_cast<void*>(&k_level_begin)) return hipErrorInvalidValue;
+  LevelKey* k = key;
+  LevelKey vv = v;
+  const double* pi = pose_in;
+  double* po = pose_out;
+  int n = N;
+  void* args[] = {&k, &vv, &pi, &po, &n};
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return hipGraphExecKernelNodeSetParams(ge, node, &p);
 }
 
 // one layer with weights resident in LDS: y = act(b + W x), MTO output tiles

@@ -24,12 +24,12 @@ using namespace fl;
 namespace {
 
 enum KernelId { K_PREDICT, K_RAYGEN, K_MLP_COARSE, K_FINE, K_PROPOSAL, K_MLP_FINE, K_COMPOSITE, K_NORMALIZE,
-                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB, K_LV_KEY,
+                K_RESAMPLE, K_SPLIT, K_RAYS, K_TEACHER, K_TRAIN, K_GATHER, K_ESTIMATE, K_CALIB,
                 K_LV_PREDICT, K_LV_RAYS, K_LV_SCORES, K_LV_FINISH, K_MLP_BOTH, K_VARIANCE, K_MAP_TRAIN, K_COUNT };
 const char* kKernelNames[K_COUNT] = {"predict", "raygen", "mlp_coarse", "fine_placement", "proposal_placement",
                                      "mlp_fine", "composite_score", "normalize", "resample", "ray_outputs",
                                      "ray_format", "teacher_histogram", "proposal_train", "gather_poses",
-                                     "pose_estimate", "fp8_calibration", "level_key", "level_predict",
+                                     "pose_estimate", "fp8_calibration", "level_predict",
                                      "level_rays", "level_scores", "level_finish", "mlp_coarse_fine",
                                      "position_variance", "map_train"};
 
@@ -101,6 +101,7 @@ struct loc_ctx {
   bool graph_mode = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphNode_t begin_node = nullptr;   // the graph's k_level_begin (takes each call's key)
   hipGraphExec_t gexec = nullptr;
   std::vector<double> graph_sig;
   // map training (4x64 map): float32 master weights in canonical order,
@@ -1415,24 +1416,20 @@ LevelRayArgs level_ray_args(const loc_ctx* c, const LevelCall& q, int L) {
   return a;
 }
 
-// the level sequence on stream st; with `prof`, every launch is timed.  With
-// kv (eager calls) the first kernel writes the call's key and predicts from
-// it; without (a captured graph, replayed after upload_key) it reads the key
-loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof, const LevelKey* kv) {
+// the level sequence on stream st; with `prof`, every launch is timed.  The
+// first kernel writes the call's key kv (by value) for the later kernels and
+// predicts the first level from it; a captured graph gets each later call's
+// key on that node (set_level_begin_node)
+loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof, const LevelKey& kv) {
   auto run = [&](int kid, double flop, double bytes, auto fn) -> loc_status {
     if (prof) return timed(c, kid, flop, bytes, fn);
     hipError_t e = fn();
     return e == hipSuccess ? LOC_OK : fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
   };
   loc_status s;
-  if (kv) {
-    if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
-                 [&] { return launch_level_begin(c->key, *kv, q.pose_in, c->lv[0].pose.p, q.N, st); })))
-      return s;
-  } else if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
-                      [&] { return launch_level_predict(c->key, q.pose_in, c->lv[0].pose.p, q.N, st); }))) {
+  if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
+               [&] { return launch_level_begin(c->key, kv, q.pose_in, c->lv[0].pose.p, q.N, st); })))
     return s;
-  }
   for (int L = 0; L < q.n_levels; ++L) {
     auto& lv = c->lv[L];
     const LevelRayArgs ra = level_ray_args(c, q, L);
@@ -1488,6 +1485,7 @@ void drop_graph(loc_ctx* c) {
   if (c->graph) hipGraphDestroy(c->graph);
   c->gexec = nullptr;
   c->graph = nullptr;
+  c->begin_node = nullptr;
   c->graph_sig.clear();
 }
 
@@ -1564,10 +1562,6 @@ loc_status make_key(loc_ctx* c, const double* motion, double sigma_t, double sig
   return LOC_OK;
 }
 
-loc_status upload_key(loc_ctx* c, const LevelKey& kv) {
-  return timed(c, K_LV_KEY, 0, sizeof(LevelKey), [&] { return launch_set_key(c->key, kv, c->stream); });
-}
-
 }  // namespace
 
 extern "C" {
@@ -1587,22 +1581,33 @@ loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* c
   }
   LevelKey kv;
   if ((s = make_key(c, motion, sigma_t, sigma_r, seed, iter, kv))) return s;
-  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof != 0, &kv);
-  if ((s = upload_key(c, kv))) return s;
+  if (!c->graph_mode) return enqueue_levels(c, q, c->stream, c->prof != 0, kv);
+  // graph mode: the same launches captured once per signature; each replay
+  // first hands this call's key to the graph's k_level_begin node
   std::vector<double> sig = level_signature(c, q);
   if (!c->gexec || sig != c->graph_sig) {
     drop_graph(c);
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    loc_status cs = enqueue_levels(c, q, c->cap_stream, false, nullptr);
+    loc_status cs = enqueue_levels(c, q, c->cap_stream, false, kv);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (cs) { if (g) hipGraphDestroy(g); return cs; }
     if (e != hipSuccess) return fail(c, LOC_E_HIP, "graph capture: %s", hipGetErrorString(e));
     c->graph = g;
+    size_t n_roots = 0;
+    e = hipGraphGetRootNodes(c->graph, nullptr, &n_roots);
+    if (e == hipSuccess && n_roots == 1) e = hipGraphGetRootNodes(c->graph, &c->begin_node, &n_roots);
+    if (e != hipSuccess || n_roots != 1) {
+      drop_graph(c);
+      return fail(c, LOC_E_HIP, "graph capture: expected one root node, found %zu", n_roots);
+    }
     e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) { drop_graph(c); return fail(c, LOC_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
     c->graph_sig = sig;
+  } else {
+    hipError_t e = set_level_begin_node(c->gexec, c->begin_node, c->key, kv, q.pose_in, c->lv[0].pose.p, q.N);
+    if (e != hipSuccess) return fail(c, LOC_E_HIP, "graph key update: %s", hipGetErrorString(e));
   }
   HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
   return LOC_OK;
@@ -1698,7 +1703,7 @@ loc_status loc_autotune_levels(loc_ctx* c, const float* image, const loc_camera*
   c->prof = 0;
   LevelKey kv;
   s = make_key(c, nullptr, 0.0, 0.0, 12345, 0, kv);
-  if (!s) s = enqueue_levels(c, q, c->stream, false, &kv);
+  if (!s) s = enqueue_levels(c, q, c->stream, false, kv);
   // cached choices
   std::vector<std::string> cache_lines;
   if (cache_path) {
