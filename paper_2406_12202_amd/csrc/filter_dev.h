@@ -18,10 +18,11 @@ typedef unsigned long long u64;
 // sigma_r^2 I)) (Sec. III-A, prediction step); Exp by Rodrigues' formula and
 // the left Jacobian, Taylor coefficients for |phi| < 1e-4.  Particle i's
 // noise comes from the motion stream keyed (i, 0, 0..1).
-__device__ __forceinline__ void predict_pose(const double* __restrict__ xin, double* __restrict__ xout, const double* O,
-                                    double sigma_t, double sigma_r, uint64_t seed, uint64_t iter, int i) {
-  double x[12];
-  for (int q = 0; q < 12; ++q) x[q] = xin[q];
+// The prediction in two parts: the increment Exp(delta) of particle i (its
+// noise and the exponential map; independent of the pose), and its
+// application x O Exp(delta).
+__device__ __forceinline__ void motion_increment(double sigma_t, double sigma_r, uint64_t seed, uint64_t iter, int i,
+                                                 double (&E)[12]) {
   const u32x4 w0 = draw(seed, iter, kStreamMotion, (uint32_t)i, 0, 0);
   const u32x4 w1 = draw(seed, iter, kStreamMotion, (uint32_t)i, 0, 1);
   const uint32_t ws[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
@@ -50,7 +51,6 @@ __device__ __forceinline__ void predict_pose(const double* __restrict__ xin, dou
   double K2[3][3];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) K2[r][c] = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
-  double E[12];
   for (int r = 0; r < 3; ++r) {
     double tv = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -60,6 +60,12 @@ __device__ __forceinline__ void predict_pose(const double* __restrict__ xin, dou
     }
     E[4 * r + 3] = tv;
   }
+}
+
+__device__ __forceinline__ void apply_increment(const double* __restrict__ xin, const double* O, const double* E,
+                                                double* __restrict__ xout) {
+  double x[12];
+  for (int q = 0; q < 12; ++q) x[q] = xin[q];
   // y = x * O, then y * E
   double y[12], z[12];
   for (int r = 0; r < 3; ++r) {
@@ -73,6 +79,13 @@ __device__ __forceinline__ void predict_pose(const double* __restrict__ xin, dou
     z[4 * r + 3] = y[4 * r + 0] * E[3] + y[4 * r + 1] * E[7] + y[4 * r + 2] * E[11] + y[4 * r + 3];
   }
   for (int q = 0; q < 12; ++q) xout[q] = z[q];
+}
+
+__device__ __forceinline__ void predict_pose(const double* __restrict__ xin, double* __restrict__ xout, const double* O,
+                                             double sigma_t, double sigma_r, uint64_t seed, uint64_t iter, int i) {
+  double E[12];
+  motion_increment(sigma_t, sigma_r, seed, iter, i, E);
+  apply_increment(xin, O, E, xout);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,16 +171,16 @@ __device__ inline void normalize_block(const double* ll, double* w, int N, int* 
   }
   m = block_max(m, s);
   const bool none = !(m > -INFINITY);
+  // exp(l_i - m) kept in w (each thread rereads only its own entries)
   double acc = 0.0;
   for (int i = tid; i < N; i += kRedThreads) {
     const double v = ll[i];
-    if (!none && isfinite(v)) acc += exp(v - m);
+    const double e = (!none && isfinite(v)) ? exp(v - m) : 0.0;
+    w[i] = e;
+    acc += e;
   }
   const double tot = block_sum(acc, s);
-  for (int i = tid; i < N; i += kRedThreads) {
-    const double v = ll[i];
-    w[i] = (!none && isfinite(v)) ? exp(v - m) / tot : 0.0;
-  }
+  for (int i = tid; i < N; i += kRedThreads) w[i] = none ? 0.0 : w[i] / tot;
   if (none && tid == 0) atomicOr(flags, 1);
   __threadfence_block();
   __syncthreads();
@@ -179,8 +192,20 @@ __device__ inline void normalize_block(const double* ll, double* w, int N, int* 
 // theta_k = floor((k 2^32 + r0) Q / (n_out 2^32)), idx_k = min{i : P_i > theta_k}.
 __device__ inline double clean_weight(double w) { return (isfinite(w) && w > 0.0) ? w : 0.0; }
 
-// floor(a * Q / (n 2^32)) for a < 2^63, Q < 2^64, n < 2^31, as 32-bit limbs
-__device__ inline u64 resample_threshold(u64 a, u64 Q, u64 n) {
+// floor(cur / n) for cur < n 2^32, n < 2^31, and the remainder: a float64
+// estimate of the quotient (off by at most one) corrected exactly
+__device__ inline u64 divmod_small(const u64 cur, const u64 n, const double inv_n, u64& r) {
+  u64 q = (u64)((double)cur * inv_n);
+  long long rr = (long long)(cur - q * n);
+  while (rr < 0) { --q; rr += (long long)n; }
+  while (rr >= (long long)n) { ++q; rr -= (long long)n; }
+  r = (u64)rr;
+  return q;
+}
+
+// floor(a * Q / (n 2^32)) for a < 2^63, Q < 2^64, n < 2^31, as 32-bit limbs;
+// inv_n = 1 / n in float64
+__device__ inline u64 resample_threshold(u64 a, u64 Q, u64 n, double inv_n) {
   const u64 lo = a * Q;
   const u64 hi = __umul64hi(a, Q);
   const u64 x2 = hi >> 32, x1 = hi & 0xffffffffull, x0 = lo >> 32;   // (hi:lo) >> 32
@@ -188,8 +213,7 @@ __device__ inline u64 resample_threshold(u64 a, u64 Q, u64 n) {
   const u64 limbs[3] = {x2, x1, x0};
   for (int i = 0; i < 3; ++i) {
     const u64 cur = (r << 32) | limbs[i];
-    q = (q << 32) | (cur / n);
-    r = cur % n;
+    q = (q << 32) | divmod_small(cur, n, inv_n, r);
   }
   return q;
 }
@@ -222,9 +246,16 @@ __device__ inline void resample_block(const double* weight, int n_in, int n_out,
   // by shuffles, then the wave totals), local prefixes
   const int chunk = (n_in + kRedThreads - 1) / kRedThreads;
   const int b0 = min(tid * chunk, n_in), b1 = min(b0 + chunk, n_in);
+  // the integer weights q_i wait in the prefix array until the scan is known
+  const bool in_lds = n_in <= kPrefixLds;
+  u64* P = in_lds ? s_prefix : prefix;
   u64 local = 0;
   if (wmax > 0.0)
-    for (int i = b0; i < b1; ++i) local += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
+    for (int i = b0; i < b1; ++i) {
+      const u64 q = (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
+      P[i] = q;
+      local += q;
+    }
   const u64 incl = wave_scan(local, (u64)0, OpAddU64{});
   if (lane == 63) s_sum[w] = incl;
   __syncthreads();
@@ -234,13 +265,11 @@ __device__ inline void resample_block(const double* weight, int n_in, int n_out,
     if (v < w) before += t;
     Q += t;
   }
-  const bool in_lds = n_in <= kPrefixLds;
   u64 run = before + incl - local;
   if (wmax > 0.0)
     for (int i = b0; i < b1; ++i) {
-      run += (u64)floor(clean_weight(weight[i]) / wmax * 1099511627776.0);
-      if (in_lds) s_prefix[i] = run;
-      else prefix[i] = run;
+      run += P[i];
+      P[i] = run;
     }
   __threadfence_block();
   __syncthreads();
@@ -249,8 +278,9 @@ __device__ inline void resample_block(const double* weight, int n_in, int n_out,
     if (tid == 0) atomicOr(flags, 2);
   } else {
     const u64 r0 = draw(seed, iter, kStreamResample, 0, 0, 0).x;
+    const double inv_n = 1.0 / (double)n_out;
     for (int k = tid; k < n_out; k += kRedThreads) {
-      const u64 th = resample_threshold(((u64)k << 32) + r0, Q, (u64)n_out);
+      const u64 th = resample_threshold(((u64)k << 32) + r0, Q, (u64)n_out, inv_n);
       idx[k] = in_lds ? prefix_search(s_prefix, n_in, th) : prefix_search(prefix, n_in, th);
     }
   }

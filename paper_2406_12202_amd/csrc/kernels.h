@@ -251,6 +251,7 @@ struct LevelFinishArgs {
   int n_out;
   double* next_pose;      // n_out x 12
   int predict_next;       // apply the next level's prediction to the drawn poses
+  double* inc;            // n_out x 12: the next level's motion increments (written by the scores kernel)
   double* est;            // 12: pose read-out of this level's weighted set, or NULL
   int* flags;
 };

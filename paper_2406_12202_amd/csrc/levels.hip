@@ -388,7 +388,19 @@ hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int bloc
 // weight[] for the rejection statistics
 constexpr int kScoreThreads = 256;
 
-__global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a) {
+// Workgroups past the scores compute the next level's motion increments,
+// one per drawn particle k (they depend on k, not on which particle is
+// drawn), so the single-workgroup finish only applies them.
+__global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a, const int score_blocks) {
+  if ((int)blockIdx.x >= score_blocks) {
+    const int k = ((int)blockIdx.x - score_blocks) * kScoreThreads + threadIdx.x;
+    if (k < a.n_out) {
+      double E[12];
+      motion_increment(a.key->sigma_t, a.key->sigma_r, a.key->seed, a.key->iter + (uint64_t)a.level + 1, k, E);
+      for (int q = 0; q < 12; ++q) a.inc[(long)k * 12 + q] = E[q];
+    }
+    return;
+  }
   const int G = particle_group(a.B);
   const int tid = blockIdx.x * kScoreThreads + threadIdx.x;
   const int g = threadIdx.x & (G - 1);
@@ -410,8 +422,10 @@ __global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinis
 
 hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
   const long threads = (long)a.N * particle_group(a.B);
-  hipLaunchKernelGGL(k_level_scores, dim3((unsigned)((threads + kScoreThreads - 1) / kScoreThreads)),
-                     dim3(kScoreThreads), 0, st, a);
+  const int score_blocks = (int)((threads + kScoreThreads - 1) / kScoreThreads);
+  const int inc_blocks = a.predict_next ? (a.n_out + kScoreThreads - 1) / kScoreThreads : 0;
+  hipLaunchKernelGGL(k_level_scores, dim3((unsigned)(score_blocks + inc_blocks)), dim3(kScoreThreads), 0, st, a,
+                     score_blocks);
   return hipGetLastError();
 }
 
@@ -484,7 +498,7 @@ __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishA
     if (i < 0 || i >= a.N) {
       for (int q = 0; q < 12; ++q) out[q] = NAN;
     } else if (a.predict_next) {
-      predict_pose(a.pose + (long)i * 12, out, a.key->motion, a.key->sigma_t, a.key->sigma_r, seed, iter + 1, k);
+      apply_increment(a.pose + (long)i * 12, a.key->motion, a.inc + (long)k * 12, out);
     } else {
       for (int q = 0; q < 12; ++q) out[q] = a.pose[(long)i * 12 + q];
     }

@@ -86,7 +86,7 @@ struct loc_ctx {
   // coarse-to-fine path: per-level buffers, device-side key, tile choices,
   // captured graph of the level sequence
   struct Level {
-    DevBuf<double> pose, loglik, weight;
+    DevBuf<double> pose, loglik, weight, inc;   // inc: the next level's motion increments (n_out x 12)
     DevBuf<float> uncert;
     DevBuf<int32_t> idx;
     DevBuf<float4> rgba;
@@ -767,7 +767,7 @@ void loc_destroy(loc_ctx* c) {
   if (c->lz_host) hipHostFree(c->lz_host);
   for (auto& L : c->lv) {
     hipFree(L.pose.p); hipFree(L.loglik.p); hipFree(L.weight.p); hipFree(L.uncert.p); hipFree(L.idx.p);
-    hipFree(L.rgba.p); hipFree(L.fe.p);
+    hipFree(L.rgba.p); hipFree(L.fe.p); hipFree(L.inc.p);
   }
   hipFree(c->key);
   if (c->gexec) hipGraphExecDestroy(c->gexec);
@@ -1457,6 +1457,7 @@ loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool p
     const bool last = L + 1 == q.n_levels;
     fa.next_pose = last ? q.pose_out : c->lv[L + 1].pose.p;
     fa.predict_next = last ? 0 : 1;
+    fa.inc = lv.inc.p;
     fa.est = last ? q.est_out : nullptr;
     fa.flags = c->flags;
     if ((s = run(K_LV_SCORES, 0, nr * 8.0 + lv.N * 20.0, [&] { return launch_level_scores(fa, st); }))) return s;
@@ -1474,7 +1475,8 @@ std::vector<double> level_signature(const loc_ctx* c, const LevelCall& q) {
     int ntl, waves, blocks;
     level_cfg(c, L, ntl, waves, blocks);
     for (double x : {(double)q.levels[L].inv_R, (double)q.levels[L].B, (double)q.levels[L].n_out, (double)ntl,
-                     (double)waves, (double)blocks, (double)(uintptr_t)c->lv[L].pose.p})
+                     (double)waves, (double)blocks, (double)(uintptr_t)c->lv[L].pose.p,
+                     (double)(uintptr_t)c->lv[L].inc.p})
       v.push_back(x);
   }
   return v;
@@ -1525,7 +1527,8 @@ loc_status prepare_levels(loc_ctx* c, const float* image, const loc_camera* cam,
     loc_status s;
     if ((s = ensure(c, lv.pose, (size_t)n_in * 12)) || (s = ensure(c, lv.loglik, n_in)) ||
         (s = ensure(c, lv.weight, n_in)) || (s = ensure(c, lv.uncert, n_in)) || (s = ensure(c, lv.idx, v.n_out)) ||
-        (s = ensure(c, lv.rgba, (size_t)n_in * v.B)) || (s = ensure(c, lv.fe, (size_t)n_in * v.B)))
+        (s = ensure(c, lv.rgba, (size_t)n_in * v.B)) || (s = ensure(c, lv.fe, (size_t)n_in * v.B)) ||
+        (s = ensure(c, lv.inc, (size_t)v.n_out * 12)))
       return s;
     if (lv.N != n_in || lv.B != v.B || lv.n_out != v.n_out) lv.ntl = lv.waves = lv.blocks = 0;   // retune
     lv.N = n_in;
