@@ -7,7 +7,9 @@
 
 namespace fl {
 
-__global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
+// one wave per workgroup: the float64 prediction is arithmetic-bound, so
+// small workgroups spread a few hundred particles over as many CUs
+__global__ __launch_bounds__(64) void k_predict(const PredictArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.N) return;
   predict_pose(a.pose_in + (long)i * 12, a.pose_out + (long)i * 12, a.motion.m, a.sigma_t, a.sigma_r, a.seed,
@@ -15,7 +17,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
 }
 
 hipError_t launch_predict(const PredictArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_predict, dim3((a.N + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_predict, dim3((a.N + 63) / 64), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 

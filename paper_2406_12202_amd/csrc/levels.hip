@@ -27,7 +27,9 @@ constexpr int kLevelSpr = 32;   // samples per ray on this path
 
 // the call's key written for the later kernels, and the first level's
 // prediction from the same values (passed by value)
-__global__ __launch_bounds__(256) void k_level_begin(LevelKey* key, const LevelKey v, const double* pose_in,
+// one wave per workgroup: the float64 prediction is arithmetic-bound, so
+// small workgroups spread a few hundred particles over as many CUs
+__global__ __launch_bounds__(64) void k_level_begin(LevelKey* key, const LevelKey v, const double* pose_in,
                                                      double* pose_out, int N) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *key = v;
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(256) void k_level_begin(LevelKey* key, const LevelK
 
 hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* pose_in, double* pose_out, int N,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_level_begin, dim3((N + 255) / 256), dim3(256), 0, st, key, v, pose_in, pose_out, N);
+  hipLaunchKernelGGL(k_level_begin, dim3((N + 63) / 64), dim3(64), 0, st, key, v, pose_in, pose_out, N);
   return hipGetLastError();
 }
 
@@ -390,11 +392,13 @@ constexpr int kScoreThreads = 256;
 
 // Workgroups past the scores compute the next level's motion increments,
 // one per drawn particle k (they depend on k, not on which particle is
-// drawn), so the single-workgroup finish only applies them.
+// drawn), so the single-workgroup finish only applies them; one wave of each
+// such workgroup works (64 increments), which spreads the float64
+// arithmetic over more CUs.
 __global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a, const int score_blocks) {
   if ((int)blockIdx.x >= score_blocks) {
-    const int k = ((int)blockIdx.x - score_blocks) * kScoreThreads + threadIdx.x;
-    if (k < a.n_out) {
+    const int k = ((int)blockIdx.x - score_blocks) * 64 + (int)threadIdx.x;
+    if (threadIdx.x < 64 && k < a.n_out) {
       double E[12];
       motion_increment(a.key->sigma_t, a.key->sigma_r, a.key->seed, a.key->iter + (uint64_t)a.level + 1, k, E);
       for (int q = 0; q < 12; ++q) a.inc[(long)k * 12 + q] = E[q];
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinis
 hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
   const long threads = (long)a.N * particle_group(a.B);
   const int score_blocks = (int)((threads + kScoreThreads - 1) / kScoreThreads);
-  const int inc_blocks = a.predict_next ? (a.n_out + kScoreThreads - 1) / kScoreThreads : 0;
+  const int inc_blocks = a.predict_next ? (a.n_out + 63) / 64 : 0;
   hipLaunchKernelGGL(k_level_scores, dim3((unsigned)(score_blocks + inc_blocks)), dim3(kScoreThreads), 0, st, a,
                      score_blocks);
   return hipGetLastError();
