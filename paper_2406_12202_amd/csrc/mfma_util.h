@@ -79,10 +79,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, const 
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n_bytes, 0x00020000);
 }
 
-// the direct loads of issue_blocks through the buffer path (buffer_load ...
+// direct loads of nkb consecutive 1 KB units into an LDS slot, wave wv
+// taking units wv, wv + WAVES, ..., through the buffer path (buffer_load ...
 // lds): while loads of this form are in flight the compiler still counts
-// outstanding LDS reads one by one, whereas with the global form in flight
-// it waits for all of them at every use
+// outstanding LDS reads one by one, whereas with the global form
+// (global_load_lds) in flight it waits for all of them at every use
 template <int WAVES>
 __device__ __forceinline__ void issue_blocks_buf(const __amdgpu_buffer_rsrc_t r, const long base, const int nkb,
                                                  uint4* slot, const int wv, const int lane) {
@@ -91,15 +92,6 @@ __device__ __forceinline__ void issue_blocks_buf(const __amdgpu_buffer_rsrc_t r,
                                              (unsigned)(((base + b) * 64 + lane) * 16), 0, 0, 0);
 }
 
-// issue the direct loads of nkb consecutive 1 KB units into an LDS slot;
-// wave wv takes units wv, wv + WAVES, ...
-template <int WAVES>
-__device__ __forceinline__ void issue_blocks(const uint4* __restrict__ wb, const long base, const int nkb,
-                                             uint4* slot, const int wv, const int lane) {
-  for (int b = wv; b < nkb; b += WAVES)
-    __builtin_amdgcn_global_load_lds((const void*)(wb + (base + b) * 64 + lane),
-                                     (lds_void_t*)(slot + b * 64), 16, 0, 0);
-}
 
 // Sample set-up of one wave's NTL column tiles of 32 samples: depth (given, or
 // stratified with jitter and written out), then gamma(x) and gamma(d) as bf16
