@@ -88,24 +88,73 @@ __device__ __forceinline__ void camera_ray(const double* P, int u, int v, double
 }
 
 // ---------------------------------------------------------------- wave primitives
-__device__ inline float wave_incl_scan(float v, int lane) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const float u = __shfl_up(v, o, kWave);
-    if (lane >= o) v += u;
+// Scans and reductions over a 64-lane wave by DPP lane moves: an inclusive
+// scan is row shifts by 1, 2, 4 and 8 lanes (within 16-lane rows), then the
+// row broadcasts of lane 15 (into rows 1 and 3) and of lane 31 (into rows 2
+// and 3); a few cycles per step where a lane shuffle through LDS takes about
+// a hundred.  After the first five steps each 32-lane half holds the scan of
+// its own lanes; the sixth joins the halves.  The order is fixed, so every
+// result is deterministic.
+
+// a 4- or 8-byte value moved by DPP control CTRL (row mask RM); `fill` where
+// the control has no source lane or the row is masked off
+template <int CTRL, int RM, class T>
+__device__ __forceinline__ T dpp_move(const T v, const T fill) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  if constexpr (sizeof(T) == 4) {
+    const int u = __builtin_bit_cast(int, v), f = __builtin_bit_cast(int, fill);
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(f, u, CTRL, RM, 0xf, false));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)u, CTRL, RM, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(u >> 32),
+                                                              CTRL, RM, 0xf, false);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
   }
+}
+
+// inclusive scan within each 32-lane half, with the associative op whose
+// identity is `id`
+template <class T, class Op>
+__device__ __forceinline__ T half_scan(T v, const T id, Op op) {
+  v = op(v, dpp_move<0x111, 0xf>(v, id));   // row_shr:1
+  v = op(v, dpp_move<0x112, 0xf>(v, id));   // row_shr:2
+  v = op(v, dpp_move<0x114, 0xf>(v, id));   // row_shr:4
+  v = op(v, dpp_move<0x118, 0xf>(v, id));   // row_shr:8
+  v = op(v, dpp_move<0x142, 0xa>(v, id));   // row_bcast:15 into rows 1 and 3
   return v;
 }
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+// inclusive scan over the whole wave
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan(T v, const T id, Op op) {
+  v = half_scan(v, id, op);
+  return op(v, dpp_move<0x143, 0xc>(v, id));   // row_bcast:31 into rows 2 and 3
 }
-__device__ inline int wave_min_int(int v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-  return v;
+
+// the value of lane `lane` (wave-uniform)
+template <class T>
+__device__ __forceinline__ T lane_value(const T v, const int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
 }
+
+struct OpAddF {
+  __device__ float operator()(const float a, const float b) const { return a + b; }
+};
+struct OpMinI {
+  __device__ int operator()(const int a, const int b) const { return min(a, b); }
+};
+
+__device__ inline float wave_incl_scan(float v, int) { return wave_scan(v, 0.0f, OpAddF{}); }
+__device__ inline float wave_sum(float v) { return lane_value(wave_scan(v, 0.0f, OpAddF{}), 63); }
+__device__ inline int wave_min_int(int v) { return lane_value(wave_scan(v, 0x7fffffff, OpMinI{}), 63); }
 
 // Eq. 6's per-particle sums in one fixed order, shared by every kernel that
 // forms them: with G = particle_group(B) lanes per particle, lane g adds

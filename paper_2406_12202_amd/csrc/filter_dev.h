@@ -89,47 +89,12 @@ __device__ __forceinline__ void predict_pose(const double* __restrict__ xin, dou
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup reductions and scans.  Within a 64-lane wave: an inclusive scan
-// by DPP lane moves (row shifts by 1, 2, 4, 8, then the row broadcasts of
-// lanes 15 and 31), a few cycles per step where a shuffle through LDS takes
-// a hundred; lane 63 ends with the wave total.  The wave totals meet in LDS
-// and are combined the same way in every wave.  The order is fixed, so the
-// results are deterministic; two barriers per workgroup reduction.
+// Workgroup reductions and scans.  Within a 64-lane wave: the DPP scan of
+// common.h (wave_scan), lane 63 ending with the wave total.  The wave totals
+// meet in LDS and are combined the same way in every wave.  The order is
+// fixed, so the results are deterministic; two barriers per workgroup
+// reduction.
 constexpr int kRedThreads = 1024;
-
-// an 8-byte value moved by DPP control CTRL (row mask RM); `fill` where the
-// control has no source lane or the row is masked off
-template <int CTRL, int RM, class T>
-__device__ __forceinline__ T dpp_move(const T v, const T fill) {
-  static_assert(sizeof(T) == 8, "8-byte values");
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
-  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)u, CTRL, RM, 0xf, false);
-  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(u >> 32), CTRL,
-                                                            RM, 0xf, false);
-  return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
-}
-
-// inclusive scan over the 64 lanes of a wave with the associative op, whose
-// identity is `id`
-template <class T, class Op>
-__device__ __forceinline__ T wave_scan(T v, const T id, Op op) {
-  v = op(v, dpp_move<0x111, 0xf>(v, id));   // row_shr:1
-  v = op(v, dpp_move<0x112, 0xf>(v, id));   // row_shr:2
-  v = op(v, dpp_move<0x114, 0xf>(v, id));   // row_shr:4
-  v = op(v, dpp_move<0x118, 0xf>(v, id));   // row_shr:8
-  v = op(v, dpp_move<0x142, 0xa>(v, id));   // row_bcast:15 into rows 1 and 3
-  v = op(v, dpp_move<0x143, 0xc>(v, id));   // row_bcast:31 into rows 2 and 3
-  return v;
-}
-
-template <class T>
-__device__ __forceinline__ T lane_value(const T v, const int lane) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
-  return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
-}
 
 struct OpAdd {
   __device__ double operator()(const double a, const double b) const { return a + b; }

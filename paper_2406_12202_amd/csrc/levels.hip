@@ -129,26 +129,20 @@ __device__ __forceinline__ void ray_setup(const LevelRayArgs& a, uint64_t seed, 
   rs.obs[0] = c0 * sc; rs.obs[1] = c1 * sc; rs.obs[2] = c2 * sc;
 }
 
-// segmented wave primitives over the two 32-lane halves (for lanes of half 0
-// they give bitwise the results of the full-wave primitives when lanes 32..63
-// hold zeros, which is how the unfused compositing kernel uses them)
-__device__ __forceinline__ float half_incl_scan(float v, int n) {
-#pragma unroll
-  for (int o = 1; o < 32; o <<= 1) {
-    const float u = __shfl_up(v, o, 32);
-    if (n >= o) v += u;
-  }
-  return v;
+// segmented wave primitives over the two 32-lane halves (DPP scans; for the
+// lanes of either half they give bitwise the results of the full-wave
+// primitives on a wave whose lanes 32..63 hold zeros, which is how the
+// unfused compositing kernel uses them); h: the lane's half
+__device__ __forceinline__ float half_incl_scan(float v, int) { return half_scan(v, 0.0f, OpAddF{}); }
+__device__ __forceinline__ float half_sum(float v, int h) {
+  const float s = half_scan(v, 0.0f, OpAddF{});
+  const float s0 = lane_value(s, 31), s1 = lane_value(s, 63);
+  return h ? s1 : s0;
 }
-__device__ __forceinline__ float half_sum(float v) {
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
-  return v;
-}
-__device__ __forceinline__ int half_min_int(int v) {
-#pragma unroll
-  for (int o = 16; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 32));
-  return v;
+__device__ __forceinline__ int half_min_int(int v, int h) {
+  const int s = half_scan(v, 0x7fffffff, OpMinI{});
+  const int s0 = lane_value(s, 31), s1 = lane_value(s, 63);
+  return h ? s1 : s0;
 }
 
 // Waves per SIMD the ray kernel is compiled for (at most 168 registers, a
@@ -345,9 +339,9 @@ k_level_rays(const LevelRayArgs a) {
       run -= tau;
       if (run <= a.log_trans) ktr = n;
       if (run < a.log_opq) kop = n;
-      cr = half_sum(cr); cg = half_sum(cg); cb = half_sum(cb); accw = half_sum(accw);
-      ktr = half_min_int(ktr);
-      kop = half_min_int(kop);
+      cr = half_sum(cr, h); cg = half_sum(cg, h); cb = half_sum(cb, h); accw = half_sum(accw, h);
+      ktr = half_min_int(ktr, h);
+      kop = half_min_int(kop, h);
       float F = a.empty_F;
       if (ktr < kLevelSpr) {
         const float t_tr = __shfl(tk, ktr, 32), l_tr = __shfl(lt, ktr, 32), s_tr = __shfl(sg, ktr, 32);
