@@ -3,6 +3,9 @@
 // direct global->LDS weight streaming, and the per-tile sample set-up.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -16,6 +19,17 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void_t;
+
+// compile-time loop: fn(std::integral_constant<int, i>) for i = 0 .. N-1,
+// each call inlined with i a constant (register arrays stay registers)
+template <class Fn, int... I>
+__device__ __forceinline__ void static_for_impl(Fn& fn, std::integer_sequence<int, I...>) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  static_for_impl(fn, std::make_integer_sequence<int, N>{});
+}
 
 // bf16 operands of the encoding gamma(p) (pseudo-pair layout of
 // maplayout_bf16.h).  sin and cos of band 0 come from sincospif; band b + 1

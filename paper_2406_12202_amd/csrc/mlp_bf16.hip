@@ -17,9 +17,6 @@
 // weight split into a high and a low bf16 part in two rows of the tile (the
 // density head carries the map's density gain, so its weights keep 16
 // significant bits; the tile has rows to spare).
-#include <type_traits>
-#include <utility>
-
 #include "mfma_util.h"
 #include "maplayout_bf16.h"
 
@@ -57,17 +54,6 @@ __device__ __forceinline__ const uint4* group_begin(ChunkStream& st, const NextG
   if (nx.units > 0) issue_blocks_buf<WAVES>(st.wr, nx.base, nx.units, nxt, st.wv, st.lane);
   ++st.g;
   return cur;
-}
-
-// compile-time loop: fn(std::integral_constant<int, i>) for i = 0 .. N-1,
-// each call inlined with i a constant (register arrays stay registers)
-template <class Fn, int... I>
-__device__ __forceinline__ void static_for_impl(Fn& fn, std::integer_sequence<int, I...>) {
-  (fn(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class Fn>
-__device__ __forceinline__ void static_for(Fn&& fn) {
-  static_for_impl(fn, std::make_integer_sequence<int, N>{});
 }
 
 // accumulator initialised with the 16 biases of lane half h of one tile

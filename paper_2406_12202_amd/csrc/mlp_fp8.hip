@@ -24,26 +24,30 @@ namespace fl {
 
 enum : int { kEpiRelu = 0, kEpiReluSigma = 1, kEpiLinear = 2, kEpiRgb = 3 };
 
+// steps of A fragments read ahead of their MFMAs (dense_f8)
+constexpr int kFp8Depth = 2;
+
 // E4M3 operands of the next layer from one finished output tile (bytes
 // 16 (mt % 2) .. + 15 of k-block mt / 2).  The accumulators already carry the
 // next layer's input scale 2^ea (folded into the MFMA's weight scale, the
 // bias and the encoding weights), so the epilogue is a clamp to [0, 448]
 // (ReLU) or [-448, 448] (the E4M3 range; the conversion returns NaN above it)
-// and the rounding, four values per two conversions.
+// and the rounding, four values per two conversions.  The first conversion of
+// a word keeps the high half of its destination, which the second overwrites,
+// so any register serves there: the first clamped value (no zeroing move).
 template <int NTL, int K8, bool RELU>
 __device__ __forceinline__ void quantize_f8(const f32x16 (&acc)[NTL], const int mt, i32x8 (&y)[NTL][K8]) {
   constexpr float lo = RELU ? 0.0f : -448.0f;
 #pragma unroll
-  for (int nt = 0; nt < NTL; ++nt) {
-    float v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = __builtin_amdgcn_fmed3f(acc[nt][i], lo, 448.0f);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      int d = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w], v[4 * w + 1], 0, false);
-      d = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * w + 2], v[4 * w + 3], d, true);
-      y[nt][mt >> 1][4 * (mt & 1) + w] = d;
-    }
+  for (int q = 0; q < 4 * NTL; ++q) {
+    const int nt = q >> 2, w = q & 3;
+    const float v0 = __builtin_amdgcn_fmed3f(acc[nt][4 * w], lo, 448.0f);
+    const float v1 = __builtin_amdgcn_fmed3f(acc[nt][4 * w + 1], lo, 448.0f);
+    const float v2 = __builtin_amdgcn_fmed3f(acc[nt][4 * w + 2], lo, 448.0f);
+    const float v3 = __builtin_amdgcn_fmed3f(acc[nt][4 * w + 3], lo, 448.0f);
+    const int j = 4 * (mt & 1) + w;
+    const int d = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, __float_as_int(v0), false);
+    y[nt][mt >> 1][j] = __builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, d, true);
   }
 }
 
@@ -73,76 +77,48 @@ __device__ __forceinline__ void head_partial(const f32x16 (&acc)[NTL], const flo
 // alternate between slot0 and slot1 (every layer has an even number of
 // groups).  On entry the loads of this layer's first group are in flight.
 // FIRST: the input layer (bf16 encoding products only).  Otherwise the FP8
-// products with x, then, if use_enc, the bf16 products with the encoding
-// blocks xe ([column tile][k-block][lane], KBE k-blocks).
-template <class S, int NTL, int WAVES, int MPC, int MTO, int KBE, int EPI, bool FIRST>
-__device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const float* bias_lds, const float* head_lds,
-                                         const int l, const bool use_enc, uint4* slot0, uint4* slot1,
+// products with x, then, with ENC, the bf16 products with the encoding blocks
+// xe ([column tile][k-block][lane], KBE k-blocks).  A group's A fragments are
+// one sequence of steps (tile by tile: the FP8 k-blocks of two 1 KB units
+// each, then the bf16 k-blocks of one unit) read from LDS DEPTH steps ahead of
+// their MFMAs into a ring of 2 DEPTH registers; scheduling barriers keep the
+// reads where they are issued (left alone, the compiler sinks each read next
+// to its use).
+template <class S, int NTL, int WAVES, int MPC, int MTO, int KBE, int EPI, bool FIRST, bool ENC, int DEPTH>
+__device__ __forceinline__ void dense_f8(const __amdgpu_buffer_rsrc_t wr, const float* bias_lds,
+                                         const float* head_lds, const int l, uint4* slot0, uint4* slot1,
                                          const i32x8 (&x)[NTL][S::K8], const uint4* xe, i32x8 (&y)[NTL][S::K8],
                                          float (&hp)[NTL][3], const int sw, const int sx, const int wv,
                                          const int lane) {
   static_assert(MTO % (2 * MPC) == 0, "layout");
+  constexpr int NS8 = FIRST ? 0 : S::K8;          // FP8 steps per tile
+  constexpr int NSE = (FIRST || ENC) ? KBE : 0;   // bf16 steps per tile
+  constexpr int KT = NS8 + NSE;                   // steps per tile
+  constexpr int UT = 2 * NS8 + NSE;               // 1 KB units per tile
+  constexpr int F = MPC * KT;                     // steps per group
+  constexpr int R = 2 * DEPTH;
   const int h = lane >> 5;
-  constexpr int U8 = FIRST ? 0 : 2 * S::K8;
-  const int u_tot = U8 + ((FIRST || use_enc) ? KBE : 0);
   const long base = S::unit_base(l);
   const float* bl = bias_lds + S::BS::bias_base(l) + h * 16;
-#pragma unroll
-  for (int mt = 0; mt < MTO; ++mt) {
-    uint4* grp = ((mt / MPC) & 1) ? slot1 : slot0;
-    if (mt % MPC == 0) {
-      uint4* nxt = ((mt / MPC) & 1) ? slot0 : slot1;
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      // buffer-path loads: with the global form in flight the compiler waits
-      // for all outstanding LDS reads at every use
-      const __amdgpu_buffer_rsrc_t wr = raw_rsrc(wb, (int)(S::UNITS * 1024));
-      if (mt + MPC < MTO)
-        issue_blocks_buf<WAVES>(wr, base + (long)(mt + MPC) * u_tot, MPC * u_tot, nxt, wv, lane);
-      else if (l + 1 < S::NL)
-        issue_blocks_buf<WAVES>(wr, S::unit_base(l + 1), MPC * S::layer_units(l + 1), nxt, wv, lane);
-    }
-    const uint4* cur = grp + (mt % MPC) * u_tot * 64;
+  auto bias_f8 = [&](f32x16 (&acc)[NTL], const int t) __attribute__((always_inline)) {
     f32x16 binit;
-    {
-      const float4* b4 = reinterpret_cast<const float4*>(bl + mt * 32);
+    const float4* b4 = reinterpret_cast<const float4*>(bl + t * 32);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float4 v = b4[i];
-        binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
-      }
+    for (int i = 0; i < 4; ++i) {
+      const float4 v = b4[i];
+      binit[4 * i] = v.x; binit[4 * i + 1] = v.y; binit[4 * i + 2] = v.z; binit[4 * i + 3] = v.w;
     }
-    f32x16 acc[NTL];
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt) acc[nt] = binit;
-    if constexpr (!FIRST) {
-#pragma unroll
-      for (int kb = 0; kb < S::K8; ++kb) {
-        const uint4 lo = cur[(2 * kb) * 64 + lane], hi = cur[(2 * kb + 1) * 64 + lane];
-        const i32x8 a = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-#pragma unroll
-        for (int nt = 0; nt < NTL; ++nt)
-          acc[nt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, x[nt][kb], acc[nt], 0, 0, 0, sw, 0, sx);
-      }
-    }
-    if (FIRST || use_enc) {
-#pragma unroll
-      for (int kb = 0; kb < KBE; ++kb) {
-        const bf16x8 a = __builtin_bit_cast(bf16x8, cur[(U8 + kb) * 64 + lane]);
-#pragma unroll
-        for (int nt = 0; nt < NTL; ++nt) {
-          const bf16x8 bx = __builtin_bit_cast(bf16x8, xe[(nt * KBE + kb) * 64 + lane]);
-          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
-        }
-      }
-    }
+  };
+  auto epilogue = [&](const f32x16 (&acc)[NTL], const int t) __attribute__((always_inline)) {
     if constexpr (EPI == kEpiRgb) {
       float p[NTL];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
 #pragma unroll
         for (int nt = 0; nt < NTL; ++nt) p[nt] = hp[nt][c];
-        head_partial<NTL>(acc, head_lds + c * S::DW, mt, h, p);
+        head_partial<NTL>(acc, head_lds + c * S::DW, t, h, p);
 #pragma unroll
         for (int nt = 0; nt < NTL; ++nt) hp[nt][c] = p[nt];
       }
@@ -151,13 +127,68 @@ __device__ __forceinline__ void dense_f8(const uint4* __restrict__ wb, const flo
         float p[NTL];
 #pragma unroll
         for (int nt = 0; nt < NTL; ++nt) p[nt] = hp[nt][0];
-        head_partial<NTL>(acc, head_lds, mt, h, p);
+        head_partial<NTL>(acc, head_lds, t, h, p);
 #pragma unroll
         for (int nt = 0; nt < NTL; ++nt) hp[nt][0] = p[nt];
       }
-      quantize_f8<NTL, S::K8, EPI != kEpiLinear>(acc, mt, y);
+      quantize_f8<NTL, S::K8, EPI != kEpiLinear>(acc, t, y);
     }
-  }
+  };
+  static_for<MTO / MPC>([&](auto gc) __attribute__((always_inline)) {
+    constexpr int g = decltype(gc)::value;
+    const uint4* cur = (g & 1) ? slot1 : slot0;
+    uint4* nxt = (g & 1) ? slot0 : slot1;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if constexpr ((g + 1) * MPC < MTO)
+      issue_blocks_buf<WAVES>(wr, base + (long)(g + 1) * MPC * UT, MPC * UT, nxt, wv, lane);
+    else if (l + 1 < S::NL)
+      issue_blocks_buf<WAVES>(wr, S::unit_base(l + 1), MPC * S::layer_units(l + 1), nxt, wv, lane);
+    uint4 rlo[R], rhi[R];
+    auto fetch = [&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (q < F) {
+        constexpr int mt = q / KT, s = q % KT;
+        if constexpr (s < NS8) {
+          rlo[q % R] = cur[(mt * UT + 2 * s) * 64 + lane];
+          rhi[q % R] = cur[(mt * UT + 2 * s + 1) * 64 + lane];
+        } else {
+          rlo[q % R] = cur[(mt * UT + NS8 + s) * 64 + lane];
+        }
+      }
+    };
+    static_for<DEPTH>(fetch);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16 acc[NTL];
+    static_for<F>([&](auto fc) __attribute__((always_inline)) {
+      constexpr int f = decltype(fc)::value;
+      constexpr int mt = f / KT, s = f % KT;
+      constexpr int t = g * MPC + mt;
+      if constexpr (s == 0) bias_f8(acc, t);
+      if constexpr (s < NS8) {
+        const uint4 lo = rlo[f % R], hi = rhi[f % R];
+        const i32x8 a = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt)
+          acc[nt] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, x[nt][s], acc[nt], 0, 0, 0, sw, 0, sx);
+      } else {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, rlo[f % R]);
+#pragma unroll
+        for (int nt = 0; nt < NTL; ++nt) {
+          const bf16x8 bx = __builtin_bit_cast(bf16x8, xe[(nt * KBE + s - NS8) * 64 + lane]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bx, acc[nt], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (f % DEPTH == 0)
+        static_for<DEPTH>([&](auto jc) __attribute__((always_inline)) {
+          fetch(std::integral_constant<int, f + DEPTH + decltype(jc)::value>{});
+        });
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (s == KT - 1) epilogue(acc, t);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  });
 }
 
 __device__ __forceinline__ float softplus_f(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
@@ -177,8 +208,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   __shared__ float4 s_heads[S::HEADS / 4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int h = lane >> 5;
-  const uint4* __restrict__ wb = reinterpret_cast<const uint4*>(a.wblocks);
-  issue_blocks_buf<WAVES>(raw_rsrc(wb, (int)(S::UNITS * 1024)), 0, MPC * S::layer_units(0), slot0, wv, lane);
+  const __amdgpu_buffer_rsrc_t wr = raw_rsrc(a.wblocks, (int)(S::UNITS * 1024));
+  issue_blocks_buf<WAVES>(wr, 0, MPC * S::layer_units(0), slot0, wv, lane);
   for (int i = threadIdx.x; i < S::BIASES / 4; i += THREADS) s_bias[i] = reinterpret_cast<const float4*>(a.bias)[i];
   for (int i = threadIdx.x; i < S::HEADS / 4; i += THREADS) s_heads[i] = reinterpret_cast<const float4*>(a.heads)[i];
 
@@ -195,31 +226,34 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
     for (int c = 0; c < 3; ++c) sp[nt][c] = rp[nt][c] = 0.0f;
+  constexpr int DP = kFp8Depth;
   // input layer: bf16 products with gamma(x)
-  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, true>(wb, bias, heads, 0, true, slot0, slot1, xb, s_gx[wv],
-                                                               xa, sp, 0, 0, wv, lane);
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, true, true, DP>(wr, bias, heads, 0, slot0, slot1, xb,
+                                                                         s_gx[wv], xa, sp, 0, 0, wv, lane);
 #pragma unroll 1
   for (int l = 1; l < S::D - 1; ++l) {
-    dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, false>(wb, bias, heads, l, l == S::SKIP, slot0, slot1, xa,
-                                                                  s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l], wv,
-                                                                  lane);
+    if (l == S::SKIP)
+      dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, false, true, DP>(
+          wr, bias, heads, l, slot0, slot1, xa, s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l], wv, lane);
+    else
+      dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiRelu, false, false, DP>(
+          wr, bias, heads, l, slot0, slot1, xa, s_gx[wv], xb, sp, a.f8_sw[l], a.f8_sx[l], wv, lane);
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
       for (int i = 0; i < S::K8; ++i) xa[nt][i] = xb[nt][i];
   }
   // last trunk layer: density head on its float32 outputs
-  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiReluSigma, false>(
-      wb, bias, heads + S::SIG_OFF, S::D - 1, S::D - 1 == S::SKIP, slot0, slot1, xa, s_gx[wv], xb, sp,
-      a.f8_sw[S::D - 1], a.f8_sx[S::D - 1], wv, lane);
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiReluSigma, false, S::D - 1 == S::SKIP, DP>(
+      wr, bias, heads + S::SIG_OFF, S::D - 1, slot0, slot1, xa, s_gx[wv], xb, sp, a.f8_sw[S::D - 1],
+      a.f8_sx[S::D - 1], wv, lane);
   // feature layer (no activation)
-  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiLinear, false>(wb, bias, heads, S::D, false, slot0, slot1, xb,
-                                                                  nullptr, xa, sp, a.f8_sw[S::D], a.f8_sx[S::D], wv,
-                                                                  lane);
+  dense_f8<S, NTL, WAVES, MPC, S::MT, S::KBX, kEpiLinear, false, false, DP>(
+      wr, bias, heads, S::D, slot0, slot1, xb, nullptr, xa, sp, a.f8_sw[S::D], a.f8_sx[S::D], wv, lane);
   // direction layer with gamma(d); colour head on its float32 outputs
-  dense_f8<S, NTL, WAVES, MPC, S::MTD, S::KBD, kEpiRgb, false>(wb, bias, heads + S::RGB_OFF, S::D + 1, true, slot0,
-                                                                slot1, xa, s_gd[wv], xb, rp, a.f8_sw[S::D + 1],
-                                                                a.f8_sx[S::D + 1], wv, lane);
+  dense_f8<S, NTL, WAVES, MPC, S::MTD, S::KBD, kEpiRgb, false, true, DP>(
+      wr, bias, heads + S::RGB_OFF, S::D + 1, slot0, slot1, xa, s_gd[wv], xb, rp, a.f8_sw[S::D + 1],
+      a.f8_sx[S::D + 1], wv, lane);
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt) {
     float zs = sp[nt][0];
