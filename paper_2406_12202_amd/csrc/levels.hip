@@ -444,8 +444,9 @@ __device__ __forceinline__ void level_weigh_and_draw(const LevelFinishArgs& a, d
       const double U = W[i];
       if (isfinite(U) && isfinite(L[i])) { cnt += 1.0; sum += U; }
     }
-    const double n_ok = block_sum(cnt, s_d);
-    const double mu = n_ok > 0.0 ? block_sum(sum, s_d) / n_ok : 0.0;
+    const double2 cs = block_sum2(cnt, sum, s_d);
+    const double n_ok = cs.x;
+    const double mu = n_ok > 0.0 ? cs.y / n_ok : 0.0;
     double ss = 0.0;
     for (int i = tid; i < a.N; i += kRedThreads) {
       const double U = W[i];
@@ -461,9 +462,9 @@ __device__ __forceinline__ void level_weigh_and_draw(const LevelFinishArgs& a, d
     __threadfence_block();
     __syncthreads();
   }
-  normalize_block(L, W, a.N, a.flags, s_d);
+  const double wmax = normalize_block(L, W, a.N, a.flags, s_d);
   if (a.est) pose_estimate_block(a.pose, W, a.N, a.est, a.flags, reinterpret_cast<double(*)[13]>(s_d));
-  resample_block(W, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u, s_prefix);
+  resample_block(W, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u, s_prefix, wmax);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishArgs a) {
@@ -471,8 +472,22 @@ __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishA
   __shared__ u64 s_u[kRedThreads / 64];
   __shared__ u64 s_prefix[kPrefixLds];
   __shared__ double s_l[kPrefixLds], s_w[kPrefixLds];
+  __shared__ double s_sink;
   const int tid = threadIdx.x;
   const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
+  // The gather at the end reads the poses (written by the kernel before the
+  // scores, mostly on other XCDs) and this thread's motion increment: both
+  // are read now, while the phases below run, so that the gather finds the
+  // poses in this XCD's L2 and the increment in registers.
+  {
+    double t = 0.0;
+    for (int i = tid; i < (a.N * 12 + 15) / 16; i += kRedThreads) t += a.pose[i * 16];   // one read per 128 B
+    if (t != t) s_sink = t;   // keeps the reads
+  }
+  const bool inc_r = a.predict_next && a.n_out <= kRedThreads;
+  double inc[12];
+  if (inc_r && tid < a.n_out)
+    for (int q = 0; q < 12; ++q) inc[q] = a.inc[(long)tid * 12 + q];
   // scores, mean F (in weight[]) come from k_level_scores; a set that fits is
   // read once into LDS, so the passes over it do not wait on memory
   if (a.N <= kPrefixLds) {
@@ -496,7 +511,7 @@ __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishA
     if (i < 0 || i >= a.N) {
       for (int q = 0; q < 12; ++q) out[q] = NAN;
     } else if (a.predict_next) {
-      apply_increment(a.pose + (long)i * 12, a.key->motion, a.inc + (long)k * 12, out);
+      apply_increment(a.pose + (long)i * 12, a.key->motion, inc_r ? inc : a.inc + (long)k * 12, out);
     } else {
       for (int q = 0; q < 12; ++q) out[q] = a.pose[(long)i * 12 + q];
     }
