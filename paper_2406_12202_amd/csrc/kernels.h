@@ -251,15 +251,24 @@ struct LevelFinishArgs {
   int n_out;
   double* next_pose;      // n_out x 12
   int predict_next;       // apply the next level's prediction to the drawn poses
-  double* inc;            // n_out x 12: the next level's motion increments (written by the scores kernel)
+  double* inc;            // n_out x 12: the next level's motion increments (written by the begin kernel)
   double* est;            // 12: pose read-out of this level's weighted set, or NULL
   int* flags;
 };
 
+// the motion increments of the levels after the first, drawn by the begin
+// kernel: level L's n[L] drawn particles get their increment for level L + 1
+// in inc[L] (n[L] x 12; n[L] = 0 where no level follows)
+constexpr int kMaxLevels = 8;
+struct LevelIncs {
+  double* inc[kMaxLevels];
+  int n[kMaxLevels];
+};
+
 hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* pose_in, double* pose_out, int N,
-                              hipStream_t st);
+                              const LevelIncs& incs, hipStream_t st);
 hipError_t set_level_begin_node(hipGraphExec_t ge, hipGraphNode_t node, LevelKey* key, const LevelKey& v,
-                                const double* pose_in, double* pose_out, int N);
+                                const double* pose_in, double* pose_out, int N, const LevelIncs& incs);
 // tile configuration (column tiles per wave, waves per workgroup), grid size
 hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int blocks, hipStream_t st);
 bool level_rays_config_ok(int ntl, int waves);

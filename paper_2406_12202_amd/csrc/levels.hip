@@ -25,38 +25,67 @@ namespace fl {
 using LS = SmallMapB;
 constexpr int kLevelSpr = 32;   // samples per ray on this path
 
-// the call's key written for the later kernels, and the first level's
-// prediction from the same values (passed by value)
-// one wave per workgroup: the float64 prediction is arithmetic-bound, so
-// small workgroups spread a few hundred particles over as many CUs
+// the call's key written for the later kernels, the first level's
+// prediction from the same values (passed by value), and in further
+// workgroups the motion increments of the later levels (they depend on the
+// drawn slot k, not on which particle is drawn, so the level kernels only
+// apply them); one wave per workgroup: the float64 arithmetic spreads over
+// as many CUs
 __global__ __launch_bounds__(64) void k_level_begin(LevelKey* key, const LevelKey v, const double* pose_in,
-                                                     double* pose_out, int N) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *key = v;
-  if (i >= N) return;
-  predict_pose(pose_in + (long)i * 12, pose_out + (long)i * 12, v.motion, v.sigma_t, v.sigma_r, v.seed, v.iter, i);
+                                                     double* pose_out, int N, const LevelIncs incs) {
+  const int nb0 = (N + 63) / 64;
+  int b = blockIdx.x;
+  if (b < nb0) {
+    const int i = b * 64 + threadIdx.x;
+    if (i == 0) *key = v;
+    if (i < N) predict_pose(pose_in + (long)i * 12, pose_out + (long)i * 12, v.motion, v.sigma_t, v.sigma_r, v.seed,
+                            v.iter, i);
+    return;
+  }
+  b -= nb0;
+  for (int L = 0; L < kMaxLevels; ++L) {
+    const int nb = (incs.n[L] + 63) / 64;
+    if (b < nb) {
+      const int k = b * 64 + threadIdx.x;
+      if (k < incs.n[L]) {
+        double E[12];
+        motion_increment(v.sigma_t, v.sigma_r, v.seed, v.iter + (uint64_t)L + 1, k, E);
+        for (int q = 0; q < 12; ++q) incs.inc[L][(long)k * 12 + q] = E[q];
+      }
+      return;
+    }
+    b -= nb;
+  }
+}
+
+static unsigned begin_blocks(const int N, const LevelIncs& incs) {
+  long nb = (N + 63) / 64;
+  for (int L = 0; L < kMaxLevels; ++L) nb += (incs.n[L] + 63) / 64;
+  return (unsigned)nb;
 }
 
 hipError_t launch_level_begin(LevelKey* key, const LevelKey& v, const double* pose_in, double* pose_out, int N,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_level_begin, dim3((N + 63) / 64), dim3(64), 0, st, key, v, pose_in, pose_out, N);
+                              const LevelIncs& incs, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_begin, dim3(begin_blocks(N, incs)), dim3(64), 0, st, key, v, pose_in, pose_out, N, incs);
   return hipGetLastError();
 }
 
 // the k_level_begin node of an instantiated graph given the next call's key
 // (the node keeps its launch shape; its arguments are copied when set)
 hipError_t set_level_begin_node(hipGraphExec_t ge, hipGraphNode_t node, LevelKey* key, const LevelKey& v,
-                                const double* pose_in, double* pose_out, int N) {
+                                const double* pose_in, double* pose_out, int N, const LevelIncs& incs) {
   hipKernelNodeParams p{};
   hipError_t e = hipGraphKernelNodeGetParams(node, &p);
   if (e != hipSuccess) return e;
   if (p.func != reinterpret_cast<void*>(&k_level_begin)) return hipErrorInvalidValue;
+  if (p.gridDim.x != begin_blocks(N, incs)) return hipErrorInvalidValue;
   LevelKey* k = key;
   LevelKey vv = v;
   const double* pi = pose_in;
   double* po = pose_out;
   int n = N;
-  void* args[] = {&k, &vv, &pi, &po, &n};
+  LevelIncs ic = incs;
+  void* args[] = {&k, &vv, &pi, &po, &n, &ic};
   p.kernelParams = args;
   p.extra = nullptr;
   return hipGraphExecKernelNodeSetParams(ge, node, &p);
@@ -384,21 +413,7 @@ hipError_t launch_level_rays(const LevelRayArgs& a, int ntl, int waves, int bloc
 // weight[] for the rejection statistics
 constexpr int kScoreThreads = 256;
 
-// Workgroups past the scores compute the next level's motion increments,
-// one per drawn particle k (they depend on k, not on which particle is
-// drawn), so the single-workgroup finish only applies them; one wave of each
-// such workgroup works (64 increments), which spreads the float64
-// arithmetic over more CUs.
-__global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a, const int score_blocks) {
-  if ((int)blockIdx.x >= score_blocks) {
-    const int k = ((int)blockIdx.x - score_blocks) * 64 + (int)threadIdx.x;
-    if (threadIdx.x < 64 && k < a.n_out) {
-      double E[12];
-      motion_increment(a.key->sigma_t, a.key->sigma_r, a.key->seed, a.key->iter + (uint64_t)a.level + 1, k, E);
-      for (int q = 0; q < 12; ++q) a.inc[(long)k * 12 + q] = E[q];
-    }
-    return;
-  }
+__global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinishArgs a) {
   const int G = particle_group(a.B);
   const int tid = blockIdx.x * kScoreThreads + threadIdx.x;
   const int g = threadIdx.x & (G - 1);
@@ -421,9 +436,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_level_scores(const LevelFinis
 hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
   const long threads = (long)a.N * particle_group(a.B);
   const int score_blocks = (int)((threads + kScoreThreads - 1) / kScoreThreads);
-  const int inc_blocks = a.predict_next ? (a.n_out + 63) / 64 : 0;
-  hipLaunchKernelGGL(k_level_scores, dim3((unsigned)(score_blocks + inc_blocks)), dim3(kScoreThreads), 0, st, a,
-                     score_blocks);
+  hipLaunchKernelGGL(k_level_scores, dim3((unsigned)score_blocks), dim3(kScoreThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -1420,6 +1420,16 @@ LevelRayArgs level_ray_args(const loc_ctx* c, const LevelCall& q, int L) {
 // first kernel writes the call's key kv (by value) for the later kernels and
 // predicts the first level from it; a captured graph gets each later call's
 // key on that node (set_level_begin_node)
+// where the begin kernel puts the later levels' motion increments
+LevelIncs level_incs(const loc_ctx* c, const LevelCall& q) {
+  LevelIncs incs{};
+  for (int L = 0; L + 1 < q.n_levels; ++L) {
+    incs.inc[L] = c->lv[L].inc.p;
+    incs.n[L] = c->lv[L].n_out;
+  }
+  return incs;
+}
+
 loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool prof, const LevelKey& kv) {
   auto run = [&](int kid, double flop, double bytes, auto fn) -> loc_status {
     if (prof) return timed(c, kid, flop, bytes, fn);
@@ -1427,8 +1437,9 @@ loc_status enqueue_levels(loc_ctx* c, const LevelCall& q, hipStream_t st, bool p
     return e == hipSuccess ? LOC_OK : fail(c, LOC_E_HIP, "launch of %s failed: %s", kKernelNames[kid], hipGetErrorString(e));
   };
   loc_status s;
+  const LevelIncs incs = level_incs(c, q);
   if ((s = run(K_LV_PREDICT, 0, 192.0 * q.N,
-               [&] { return launch_level_begin(c->key, kv, q.pose_in, c->lv[0].pose.p, q.N, st); })))
+               [&] { return launch_level_begin(c->key, kv, q.pose_in, c->lv[0].pose.p, q.N, incs, st); })))
     return s;
   for (int L = 0; L < q.n_levels; ++L) {
     auto& lv = c->lv[L];
@@ -1609,7 +1620,8 @@ loc_status loc_update_levels(loc_ctx* c, const float* image, const loc_camera* c
     if (e != hipSuccess) { drop_graph(c); return fail(c, LOC_E_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
     c->graph_sig = sig;
   } else {
-    hipError_t e = set_level_begin_node(c->gexec, c->begin_node, c->key, kv, q.pose_in, c->lv[0].pose.p, q.N);
+    hipError_t e = set_level_begin_node(c->gexec, c->begin_node, c->key, kv, q.pose_in, c->lv[0].pose.p, q.N,
+                                        level_incs(c, q));
     if (e != hipSuccess) return fail(c, LOC_E_HIP, "graph key update: %s", hipGetErrorString(e));
   }
   HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
