@@ -221,10 +221,11 @@ constexpr int kPrefixLds = 4096;
 
 // idx[k] = -1 for every k and flag 2 when all weights are zero.  s_max: one
 // double per wave; s_sum: one u64 per wave; s_prefix: kPrefixLds u64 (LDS).
-// wmax_in: the largest cleaned weight when the caller knows it, else < 0.
+// wmax_in: the largest cleaned weight when the caller knows it, else < 0;
+// idx_lds: an LDS copy of idx (n_out entries) when not null.
 __device__ inline void resample_block(const double* weight, int n_in, int n_out, uint64_t seed, uint64_t iter,
                                       u64* prefix, int32_t* idx, int* flags, double* s_max, u64* s_sum,
-                                      u64* s_prefix, const double wmax_in = -1.0) {
+                                      u64* s_prefix, const double wmax_in = -1.0, int32_t* idx_lds = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double wmax = wmax_in;
   if (wmax < 0.0) {
@@ -264,14 +265,19 @@ __device__ inline void resample_block(const double* weight, int n_in, int n_out,
   __threadfence_block();
   __syncthreads();
   if (Q == 0) {
-    for (int k = tid; k < n_out; k += kRedThreads) idx[k] = -1;
+    for (int k = tid; k < n_out; k += kRedThreads) {
+      idx[k] = -1;
+      if (idx_lds) idx_lds[k] = -1;
+    }
     if (tid == 0) atomicOr(flags, 2);
   } else {
     const u64 r0 = draw(seed, iter, kStreamResample, 0, 0, 0).x;
     const double inv_n = 1.0 / (double)n_out;
     for (int k = tid; k < n_out; k += kRedThreads) {
       const u64 th = resample_threshold(((u64)k << 32) + r0, Q, (u64)n_out, inv_n);
-      idx[k] = in_lds ? prefix_search(s_prefix, n_in, th) : prefix_search(prefix, n_in, th);
+      const int32_t v = in_lds ? prefix_search(s_prefix, n_in, th) : prefix_search(prefix, n_in, th);
+      idx[k] = v;
+      if (idx_lds) idx_lds[k] = v;
     }
   }
   __threadfence_block();

@@ -447,7 +447,7 @@ hipError_t launch_level_scores(const LevelFinishArgs& a, hipStream_t st) {
 // the weights on return).
 __device__ __forceinline__ void level_weigh_and_draw(const LevelFinishArgs& a, double* L, double* W, double* s_d,
                                                      u64* s_u, u64* s_prefix, const uint64_t seed,
-                                                     const uint64_t iter) {
+                                                     const uint64_t iter, int32_t* idx_lds) {
   const int tid = threadIdx.x;
   if (a.reject) {
     // mean and population standard deviation of the mean F over particles
@@ -477,58 +477,92 @@ __device__ __forceinline__ void level_weigh_and_draw(const LevelFinishArgs& a, d
   }
   const double wmax = normalize_block(L, W, a.N, a.flags, s_d);
   if (a.est) pose_estimate_block(a.pose, W, a.N, a.est, a.flags, reinterpret_cast<double(*)[13]>(s_d));
-  resample_block(W, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u, s_prefix, wmax);
+  resample_block(W, a.N, a.n_out, seed, iter, a.prefix, a.idx, a.flags, s_d, s_u, s_prefix, wmax, idx_lds);
 }
+
+// sets up to this size have their poses read into registers at the start
+// (two per thread) and staged in LDS for the gather once the draw is done
+constexpr int kPoseStage = 2 * kRedThreads;
 
 __global__ __launch_bounds__(kRedThreads) void k_level_finish(const LevelFinishArgs a) {
   __shared__ double s_d[kEstThreads * 13];   // reused by every phase
   __shared__ u64 s_u[kRedThreads / 64];
-  __shared__ u64 s_prefix[kPrefixLds];
-  __shared__ double s_l[kPrefixLds], s_w[kPrefixLds];
+  // l, w and the integer prefix of a set that fits; after the draw, the
+  // staged poses (12 doubles per particle)
+  __shared__ double s_lw[3 * kPrefixLds];
+  __shared__ int32_t s_idx[kPrefixLds];
   __shared__ double s_sink;
+  static_assert(12 * kPoseStage <= 3 * kPrefixLds, "staged poses fit");
+  double* s_l = s_lw;
+  double* s_w = s_lw + kPrefixLds;
+  u64* s_prefix = reinterpret_cast<u64*>(s_lw + 2 * kPrefixLds);
   const int tid = threadIdx.x;
   const uint64_t seed = a.key->seed, iter = a.key->iter + (uint64_t)a.level;
-  // The gather at the end reads the poses (written by the kernel before the
-  // scores, mostly on other XCDs) and this thread's motion increment: both
-  // are read now, while the phases below run, so that the gather finds the
-  // poses in this XCD's L2 and the increment in registers.
-  {
-    double t = 0.0;
-    for (int i = tid; i < (a.N * 12 + 15) / 16; i += kRedThreads) t += a.pose[i * 16];   // one read per 128 B
-    if (t != t) s_sink = t;   // keeps the reads
-  }
-  const bool inc_r = a.predict_next && a.n_out <= kRedThreads;
-  double inc[12];
-  if (inc_r && tid < a.n_out)
-    for (int q = 0; q < 12; ++q) inc[q] = a.inc[(long)tid * 12 + q];
   // scores, mean F (in weight[]) come from k_level_scores; a set that fits is
   // read once into LDS, so the passes over it do not wait on memory
-  if (a.N <= kPrefixLds) {
+  const bool small = a.N <= kPrefixLds;
+  if (small)
     for (int i = tid; i < a.N; i += kRedThreads) {
       s_l[i] = a.loglik[i];
       s_w[i] = a.weight[i];
     }
+  // The gather's inputs, read now so that their latency passes while the
+  // phases below run: the poses (written by the kernel before the scores,
+  // mostly on other XCDs), this thread's motion increment and O_t.
+  const bool stage = a.N <= kPoseStage;
+  double pr[2][12];
+  if (stage) {
+    for (int j = 0; j < 2; ++j) {
+      const int i = tid + j * kRedThreads;
+      if (i < a.N)
+        for (int q = 0; q < 12; ++q) pr[j][q] = a.pose[(long)i * 12 + q];
+    }
+  } else {
+    double t = 0.0;
+    for (int i = tid; i < (a.N * 12 + 15) / 16; i += kRedThreads) t += a.pose[i * 16];   // one read per 128 B
+    if (t != t) s_sink = t;   // keeps the reads: the gather then finds the poses in this XCD's L2
+  }
+  const bool inc_r = a.predict_next && a.n_out <= kRedThreads;
+  double inc[12], mo[12];
+  if (inc_r && tid < a.n_out)
+    for (int q = 0; q < 12; ++q) inc[q] = a.inc[(long)tid * 12 + q];
+  for (int q = 0; q < 12; ++q) mo[q] = a.key->motion[q];
+  int32_t* idx_lds = a.n_out <= kPrefixLds ? s_idx : nullptr;
+  if (small) {
     __syncthreads();
-    level_weigh_and_draw(a, s_l, s_w, s_d, s_u, s_prefix, seed, iter);
+    level_weigh_and_draw(a, s_l, s_w, s_d, s_u, s_prefix, seed, iter, idx_lds);
     for (int i = tid; i < a.N; i += kRedThreads) {
       a.loglik[i] = s_l[i];
       a.weight[i] = s_w[i];
     }
   } else {
-    level_weigh_and_draw(a, a.loglik, a.weight, s_d, s_u, s_prefix, seed, iter);
+    level_weigh_and_draw(a, a.loglik, a.weight, s_d, s_u, s_prefix, seed, iter, idx_lds);
+  }
+  if (stage) {
+    __syncthreads();   // l, w and the prefix are read for the last time
+    for (int j = 0; j < 2; ++j) {
+      const int i = tid + j * kRedThreads;
+      if (i < a.N)
+        for (int q = 0; q < 12; ++q) s_lw[i * 12 + q] = pr[j][q];
+    }
+    __syncthreads();
   }
   // gather the drawn poses; apply the next level's prediction to particle k
-  for (int k = tid; k < a.n_out; k += kRedThreads) {
-    const int i = a.idx[k];
-    double* out = a.next_pose + (long)k * 12;
-    if (i < 0 || i >= a.N) {
-      for (int q = 0; q < 12; ++q) out[q] = NAN;
-    } else if (a.predict_next) {
-      apply_increment(a.pose + (long)i * 12, a.key->motion, inc_r ? inc : a.inc + (long)k * 12, out);
-    } else {
-      for (int q = 0; q < 12; ++q) out[q] = a.pose[(long)i * 12 + q];
+  auto gather = [&](const double* P) __attribute__((always_inline)) {
+    for (int k = tid; k < a.n_out; k += kRedThreads) {
+      const int i = idx_lds ? idx_lds[k] : a.idx[k];
+      double* out = a.next_pose + (long)k * 12;
+      if (i < 0 || i >= a.N) {
+        for (int q = 0; q < 12; ++q) out[q] = NAN;
+      } else if (a.predict_next) {
+        apply_increment(P + (long)i * 12, mo, inc_r ? inc : a.inc + (long)k * 12, out);
+      } else {
+        for (int q = 0; q < 12; ++q) out[q] = P[(long)i * 12 + q];
+      }
     }
-  }
+  };
+  if (stage) gather(s_lw);
+  else gather(a.pose);
 }
 
 hipError_t launch_level_finish(const LevelFinishArgs& a, hipStream_t st) {
