@@ -94,6 +94,47 @@ def test_levels_equal_unfused_path_bitwise(torch_dev, empty_mode):
     assert _same(r["pose"], X)
 
 
+# Sets that take every branch of the level kernel: level 0 has more particles
+# than fit in LDS (4096) and draws more than fit there, level 1 more than fit
+# but draws into LDS, level 2 fits but is too large to stage its poses in
+# registers (1024) and draws more than one particle per thread (512), level 3
+# stages two poses per thread.
+LEVELS_BIG = [(8, 2, 4500), (4, 2, 1500), (2, 4, 700), (1, 4, 300)]
+
+
+@pytest.mark.parametrize("reject", [False, True])
+def test_levels_large_sets_equal_unfused_path_bitwise(torch_dev, reject):
+    torch = torch_dev
+    s, p, cam, poses, img = _setup(73, 5000)
+    c = ctx(s, p, "bf16")
+    img_d = _dev(img, torch)
+    kw = dict(motion=MOTION, sigma_t=0.02, sigma_r=0.01, seed=9, iter=5)
+    r = _run_levels(c, img_d, cam, LEVELS_BIG, _dev(poses, torch), torch, reject=reject, **kw)
+    assert r["flags"] == 0
+    u = ctx(s, p, "bf16")
+    X = poses
+    for L, (inv_R, B, n_out) in enumerate(LEVELS_BIG):
+        g = r["levels"][L]
+        po, ll, w, un = u.loc_update_particles(img_d, cam, inv_R, B, _dev(X, torch), MOTION, 0.02, 0.01, 9, 5 + L)
+        rgb, op, F, E = u.loc_ray_outputs()
+        assert _same(g["pose"], po.cpu().numpy()), L
+        for name, ref in (("C", rgb), ("A", op), ("F", F), ("E", E), ("uncert", un)):
+            assert _same(g[name], ref.cpu().numpy()), (L, name)
+        if not reject:
+            assert _same(g["loglik"], ll.cpu().numpy()), L
+            assert _same(g["weight"], w.cpu().numpy()), L
+        # the draw and the read-out from the level's own weights (after the
+        # rejection when it is on), through the per-step kernels
+        wl = _dev(g["weight"], torch)
+        idx = u.loc_resample(wl, n_out, 9, 5 + L)
+        assert _same(g["idx"], idx.cpu().numpy()), L
+        if L + 1 == len(LEVELS_BIG):
+            est = u.loc_pose_estimate(po, wl)
+            assert _same(r["est"], est.cpu().numpy())
+        X = po.cpu().numpy()[idx.cpu().numpy()]
+    assert _same(r["pose"], X)
+
+
 def test_levels_match_oracle_lockstep(torch_dev):
     torch = torch_dev
     s, p, cam, poses, img = _setup(72, 100)
