@@ -1,6 +1,9 @@
 // Coarse-to-fine update of the small map (4x64, bf16 MFMA, 32 stratified
-// samples per ray): per level one persistent fused ray kernel and one
-// single-workgroup level kernel.
+// samples per ray): a begin kernel, then per level one persistent fused ray
+// kernel, a scores kernel and one single-workgroup level kernel.
+//
+// k_level_begin writes the call's key, predicts the first level's particles
+// and draws the motion increments of the later levels.
 //
 // k_level_rays keeps the whole packed map (30 KB of bf16 chunks, biases,
 // heads) resident in LDS and walks the level's rays with a grid-stride loop
@@ -12,9 +15,11 @@
 // the same instruction sequence as the unfused kernels (raygen, k_mlp_bf16,
 // k_composite), so the results do not depend on the tile configuration.
 //
-// k_level_finish reduces each particle's rays in fixed order to S_i, l_i and
-// the mean uncertainty, applies the 1-sigma rejection, normalises, reads out
-// the pose, resamples to the next level's particle count, gathers the drawn
+// k_level_scores reduces each particle's rays in fixed order to S_i, l_i and
+// the mean uncertainty (Eq. 6).
+//
+// k_level_finish applies the 1-sigma rejection, normalises, reads out the
+// pose, resamples to the next level's particle count, gathers the drawn
 // poses and applies the next level's prediction.
 #include "filter_dev.h"
 #include "maplayout_bf16.h"
