@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize", "room", "grid"],
+    ap.add_argument("--mode", default="headline", choices=["headline", "single", "copy", "levels", "large", "localize", "room", "grid", "train"],
                     help="headline: FP32 plain vs BF16+proposal; single: one path (--workload/--precision); "
                          "copy: a plain 1 GiB device copy, the reference for HBM byte counters; "
                          "levels: the coarse-to-fine workload (eager and graph); large: the FP8 workload; "
@@ -655,6 +655,47 @@ def bench_room(args, torch):
     return 0
 
 
+def bench_train(args, torch):
+    """Map training (Eq. 2) on the room scene: time per Adam step of 2048 rays
+    x 32 samples with the gradient in float32 on the vector ALU and in
+    bfloat16 on the matrix cores (a bf16 context), after the warm-up steps, on
+    the same rays and initial map."""
+    from paper_2406_12202_amd import binding, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    spec = synth.spec("small", n_coarse=32)
+    O, D, C = synth.room_rays(args.seed, 512, 512)
+    rays = [torch.as_tensor(x, device=dev) for x in (O, D, C)]
+    batch = 2048
+    # FLOP per step: forward, input gradient and weight gradient of every
+    # product, 2 x 3 x (multiply-adds per sample) per sample
+    m = synth.SMALL_MAP
+    w = m["width"]
+    macs = w * (3 + 6 * m["L_xyz"]) + (m["n_layers"] - 1) * w * w + w + 3 * (w + 3 + 6 * m["L_dir"])
+    flop = 6.0 * macs * 32 * batch
+    res = {}
+    for prec in ("fp32", "bf16"):
+        c = binding.Context(spec, synth.room_map_init(args.seed), precision=prec, stream=stream)
+        c.loc_train_map(*rays, batch=batch, steps=max(1, args.warmup), lr=2e-3, seed=args.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = c.loc_train_map(*rays, batch=batch, steps=args.steps, lr=2e-3, seed=args.seed).cpu().numpy()
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / args.steps * 1e6
+        res[prec] = {"us_per_step": us, "TFLOPs": flop / (us * 1e-6) / 1e12, "loss_last": float(losses[-1])}
+        c.close()
+    out = {"metric": "map training step time (Eq. 2; 2048 rays x 32 samples, Adam)", "value": res["bf16"]["us_per_step"],
+           "unit": "us/step", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["bf16"]["us_per_step"] * 1e-3, "higher_is_better": False, "vs_baseline": None,
+           "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "train: 4x64 map on 262 k exact rays of the analytic room, batch 2048, 32 samples"},
+           "precisions": res, "speedup_bf16_over_fp32": res["fp32"]["us_per_step"] / res["bf16"]["us_per_step"],
+           "flop_per_step": flop}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_grid(args, torch):
     """The multi-resolution grid map (16 levels of 2^19 entries of two
     half-precision features, resolutions 16..2048 over [-4, 4]^3, 64-wide tiny
@@ -728,6 +769,8 @@ def main():
         return bench_room(args, torch)
     if args.mode == "grid":
         return bench_grid(args, torch)
+    if args.mode == "train":
+        return bench_train(args, torch)
     from paper_2406_12202_amd import binding, synth
 
     wl = args.workload if args.mode == "single" else "nerf"

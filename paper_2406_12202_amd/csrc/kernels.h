@@ -184,6 +184,7 @@ struct MapTrainArgs {
   int adam, step;
   float lr, beta1, beta2, eps;
   int S, jitter;           // coarse samples per ray (<= 64), stratified jitter
+  int bf16;                // 1: bfloat16 products on the matrix cores (S = 32), else float32
   uint64_t seed, iter;     // sample streams keyed (ray, 0) at counter iter
   float near_, far_, dt;
 };

@@ -9,6 +9,7 @@
 // ray at a time with hidden unit j on lane j; the vector a layer reads is
 // broadcast lane by lane with v_readlane, so no LDS traffic is needed for
 // activations.
+#include "bf16_tiles.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -63,9 +64,6 @@ __device__ __forceinline__ float softmax32(float z, int lane) {
 constexpr int kPropWaves = 4;
 constexpr int PK1 = PENC;   // 39 k-steps of layer 1
 constexpr int PW1 = 2 * PK1 * 64, PW2 = 2 * 32 * 64, PW3 = 32 * 64;
-typedef float pf32x16 __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ int prop_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
 __device__ __forceinline__ void prop_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -86,10 +84,10 @@ __global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const Proposa
       v = P[P_W1 + (mt * 32 + n) * PIN + (h ? PENC + kb : kb)];
     } else if (blk < 2 * PK1 + 64) {      // layer 2: block mt * 32 + s, s = 16 b + r
       const int q = blk - 2 * PK1, mt = q >> 5, st = q & 31;
-      v = P[P_W2 + (mt * 32 + n) * PH + 32 * (st >> 4) + prop_row(st & 15, h)];
+      v = P[P_W2 + (mt * 32 + n) * PH + 32 * (st >> 4) + tile_row(st & 15, h)];
     } else {                               // layer 3: block s
       const int st = blk - 2 * PK1 - 64;
-      v = P[P_W3 + n * PH + 32 * (st >> 4) + prop_row(st & 15, h)];
+      v = P[P_W3 + n * PH + 32 * (st >> 4) + tile_row(st & 15, h)];
     }
     s_w[e] = v;
   }
@@ -125,7 +123,7 @@ __global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const Proposa
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) h1[mt][r] = s_b[32 * mt + prop_row(r, h)];
+      for (int r = 0; r < 16; ++r) h1[mt][r] = s_b[32 * mt + tile_row(r, h)];
 #pragma unroll
     for (int kb = 0; kb < PK1; ++kb)
 #pragma unroll
@@ -140,7 +138,7 @@ __global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const Proposa
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) h2[mt][r] = s_b[PH + 32 * mt + prop_row(r, h)];
+      for (int r = 0; r < 16; ++r) h2[mt][r] = s_b[PH + 32 * mt + tile_row(r, h)];
 #pragma unroll
     for (int st = 0; st < 32; ++st)
 #pragma unroll
@@ -155,7 +153,7 @@ __global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const Proposa
     // once at the end) so that consecutive instructions are independent
     pf32x16 z0, z1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) { z0[r] = s_b[2 * PH + prop_row(r, h)]; z1[r] = 0.0f; }
+    for (int r = 0; r < 16; ++r) { z0[r] = s_b[2 * PH + tile_row(r, h)]; z1[r] = 0.0f; }
 #pragma unroll
     for (int st = 0; st < 32; st += 2) {
       z0 = __builtin_amdgcn_mfma_f32_32x32x2f32(w3[st * 64 + lane], h2[st >> 4][st & 15], z0, 0, 0, 0);
@@ -183,7 +181,7 @@ __global__ __launch_bounds__(64 * kPropWaves) void k_proposal_fine(const Proposa
     // pdf 0.99 p + 0.01 / 32 on 32 equal bins: masses to LDS, then the
     // inclusive prefix of each ray's bins in bin order (lane half 0)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) c_ray[n][prop_row(r, h)] = 0.99f * z0[r] + 0.01f / PB;
+    for (int r = 0; r < 16; ++r) c_ray[n][tile_row(r, h)] = 0.99f * z0[r] + 0.01f / PB;
     prop_wave_sync();
     if (h == 0) {
       float c = 0.0f;
@@ -385,47 +383,13 @@ constexpr int kTrainBWaves = 4;
 constexpr int kTrainBTiles = 2;
 constexpr int PX = 80;                              // padded encoding
 constexpr int PKX = PX / 16;                        // 5 k-blocks of layer 1
-constexpr int TROW = 40;                            // LDS table row stride (bf16)
+constexpr int TROW = kTabRow;                       // LDS table row stride (bf16)
 // weight fragments (1 KB blocks) in LDS
 constexpr int FB_W1 = 0, FB_W2 = FB_W1 + 2 * PKX, FB_W3 = FB_W2 + 2 * 4, FB_W3T = FB_W3 + 4, FB_W2T = FB_W3T + 2 * 2,
               FB_N = FB_W2T + 2 * 4;
 // per-wave tables (bf16 rows of TROW): gz 32, h2 64, ga2 64, h1 64, ga1 64, x 96
 constexpr int TB_GZ = 0, TB_H2 = TB_GZ + 32, TB_GA2 = TB_H2 + 64, TB_H1 = TB_GA2 + 64, TB_GA1 = TB_H1 + 64,
               TB_X = TB_GA1 + 64, TB_ROWS = TB_X + 96;
-
-typedef __bf16 pbf16x8 __attribute__((ext_vector_type(8)));
-typedef float pf32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 pbf16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ int chain_row(int kb, int h, int q) { return 16 * kb + 8 * (q >> 2) + 4 * h + (q & 3); }
-
-__device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
-  const pf32x2 f = {a, b};
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, pbf16x2));
-}
-
-// rounded bf16 operands of k-blocks 2 mt and 2 mt + 1 from an output tile
-__device__ __forceinline__ void tile_operands_bf16(const pf32x16& t, pbf16x8& k0, pbf16x8& k1) {
-  uint4 u0, u1;
-  u0.x = pack2_bf16(t[0], t[1]); u0.y = pack2_bf16(t[2], t[3]);
-  u0.z = pack2_bf16(t[4], t[5]); u0.w = pack2_bf16(t[6], t[7]);
-  u1.x = pack2_bf16(t[8], t[9]); u1.y = pack2_bf16(t[10], t[11]);
-  u1.z = pack2_bf16(t[12], t[13]); u1.w = pack2_bf16(t[14], t[15]);
-  k0 = __builtin_bit_cast(pbf16x8, u0);
-  k1 = __builtin_bit_cast(pbf16x8, u1);
-}
-
-// a 32-row output tile (rows row0 + 8 (v / 4) + 4 h + v % 4 of column n) into
-// the [row][ray] table as bf16, the same rounding as tile_operands_bf16
-__device__ __forceinline__ void tile_to_table(const pf32x16& t, __bf16* tab, const int row0, const int n,
-                                              const int h) {
-#pragma unroll
-  for (int v = 0; v < 16; ++v) tab[(row0 + 8 * (v >> 2) + 4 * h + (v & 3)) * TROW + n] = (__bf16)t[v];
-}
-
-__device__ __forceinline__ pbf16x8 table_operand(const __bf16* tab, const int row, const int kb, const int h) {
-  return __builtin_bit_cast(pbf16x8, *reinterpret_cast<const uint4*>(tab + row * TROW + 16 * kb + 8 * h));
-}
 
 __device__ __forceinline__ float warp_f32(float v, int k) { return __shfl_xor(v, k, 64); }
 
@@ -544,7 +508,7 @@ __global__ __launch_bounds__(64 * kTrainBWaves) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s1[mt][r] = s_b[32 * mt + prop_row(r, h)];
+      for (int r = 0; r < 16; ++r) s1[mt][r] = s_b[32 * mt + tile_row(r, h)];
 #pragma unroll
       for (int kb = 0; kb < PKX; ++kb)
         s1[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W1 + mt * PKX + kb) * 64 + lane]),
@@ -561,7 +525,7 @@ __global__ __launch_bounds__(64 * kTrainBWaves) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s2v[mt][r] = s_b[PH + 32 * mt + prop_row(r, h)];
+      for (int r = 0; r < 16; ++r) s2v[mt][r] = s_b[PH + 32 * mt + tile_row(r, h)];
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
         s2v[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W2 + mt * 4 + kb) * 64 + lane]),
@@ -576,7 +540,7 @@ __global__ __launch_bounds__(64 * kTrainBWaves) __attribute__((amdgpu_waves_per_
       tile_operands_bf16(h2[mt], h2b[2 * mt], h2b[2 * mt + 1]);
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) z[r] = s_b[2 * PH + prop_row(r, h)];
+    for (int r = 0; r < 16; ++r) z[r] = s_b[2 * PH + tile_row(r, h)];
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
       z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, s_w[(FB_W3 + kb) * 64 + lane]), h2b[kb], z,
@@ -703,7 +667,7 @@ __global__ __launch_bounds__(64 * kTrainBWaves) __attribute__((amdgpu_waves_per_
   float* out = a.partial + (long)wave * P_N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int row = prop_row(r, h);
+    const int row = tile_row(r, h);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
       const int u = 32 * mt + row;

@@ -16,6 +16,7 @@
 // hidden weight matrix; two passes, see k_map_grad).  Canonical parameter order as the map description:
 // W0 (64 x 39), b0, W1, b1, W2, b2, W3, b3 (64 x 64 each), w_s (1 x 64), b_s,
 // W_c (3 x 79), b_c.
+#include "bf16_tiles.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -292,22 +293,491 @@ __global__ __launch_bounds__(64 * kTmWaves) void k_map_grad(const MapTrainArgs a
   }
 }
 
-// sum of the per-wave partials in wave order; then the gradient, or one Adam
-// step (t = step, counted from 1)
-__global__ __launch_bounds__(256) void k_map_reduce(const MapTrainArgs a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e == 0 && a.loss_out) {
-    float l = 0.0f;
-    for (int v = 0; v < a.n_waves; ++v) l += a.loss_partial[v];
-    a.loss_out[a.loss_index] = l / (float)a.batch;
+// ---------------------------------------------------------------------------
+// The same gradient in bfloat16 on the matrix cores (v_mfma_f32_32x32x16_bf16,
+// float32 accumulation) for 32 samples per ray: a wave takes one ray at a
+// time as a tile of 32 sample columns (lane (n, h) holds sample n; layouts
+// of bf16_tiles.h).  Forward and the backward pass through the layers run
+// transposed, out^T = W in^T: the encoding gamma(x) enters in natural order
+// (k-row 16 kb + 8 h + q, padded to 48 with x_39 = 1, the bias column of
+// dW0), the hidden activations chained, the head tile's rows are sigma, r,
+// g, b (then zeros) over [h3, gamma(d)] with gamma(d) padded to 16 by a 1
+// whose weight is zero (and whose column of dW_head is the head biases'
+// gradient).  The compositing gradient is the float32 kernel's, on the lanes
+// of half 0.  The weight gradients contract over the samples: activations,
+// output gradients and the encodings go through per-wave LDS tables
+// [row][sample], and dW = G H^T accumulates in registers over the wave's
+// rays; db1..db3 come from the same tables against a column of ones, into
+// LDS.  Each wave writes its partial gradient in parameter order.
+namespace tmb {
+constexpr int WAVES = 3;
+constexpr int XK = 3;                                    // k-blocks of gamma(x) (48 rows)
+// weight fragments (1 KB blocks) in LDS
+constexpr int F_W0 = 0, F_W1 = F_W0 + 2 * XK, F_W2 = F_W1 + 8, F_W3 = F_W2 + 8, F_WH = F_W3 + 8,
+              F_W1T = F_WH + 5, F_W2T = F_W1T + 8, F_W3T = F_W2T + 8, F_WHT = F_W3T + 8, F_N = F_WHT + 2;
+// per-wave tables (rows of kTabRow bf16): gamma(x) 48 + a zero row, h0..h3,
+// the current layer's output gradient, the head gradient (4 rows + a zero
+// row), gamma(d) (15 rows, a row of ones, a zero row)
+constexpr int T_X = 0, T_H0 = T_X + 49, T_H1 = T_H0 + 64, T_H2 = T_H1 + 64, T_H3 = T_H2 + 64, T_DZ = T_H3 + 64,
+              T_G = T_DZ + 64, T_D = T_G + 5, T_ROWS = T_D + 17;
+}  // namespace tmb
+
+__device__ __forceinline__ pf32x16 tmb_zero() {
+  pf32x16 z;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) z[r] = 0.0f;
+  return z;
+}
+
+__device__ __forceinline__ pf32x16 tmb_mfma(const uint4& a, const pbf16x8& b, const pf32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, a), b, c, 0, 0, 0);
+}
+
+// ReLU'd output gradient of tile mt: da where the activation (its table
+// rows, [unit][sample]) is positive
+__device__ __forceinline__ pf32x16 tmb_mask(const pf32x16& da, const __bf16* hrows, const int mt, const int n,
+                                            const int h) {
+  pf32x16 dz;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) dz[v] = (float)hrows[(32 * mt + tile_row(v, h)) * kTabRow + n] > 0.0f ? da[v] : 0.0f;
+  return dz;
+}
+
+template <int PASS>
+__global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_map_grad_bf16(
+    const MapTrainArgs a) {
+  using namespace tmb;
+  __shared__ uint4 s_w[F_N * 64];
+  __shared__ __align__(16) __bf16 s_t[WAVES][T_ROWS * kTabRow];
+  __shared__ float s_b[4 * tm::H + 4];
+  __shared__ float s_db[WAVES][3 * tm::H];
+  const float* __restrict__ P = a.params;
+  // weight fragments in the operand order of each product: lane (m, h) of
+  // block holds A[m][k] for its eight k of k-block kb
+  for (int e = threadIdx.x; e < F_N * 64; e += blockDim.x) {
+    const int blk = e >> 6, ln = e & 63, m = ln & 31, h = ln >> 5;
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float x = 0.0f;
+      if (blk < F_W1) {                          // W0: block mt * 3 + kb, natural k
+        const int mt = blk / XK, kb = blk - mt * XK, k = 16 * kb + 8 * h + q;
+        x = k < tm::IX ? P[tm::W0 + (32 * mt + m) * tm::IX + k] : 0.0f;
+      } else if (blk < F_WH) {                   // W1..W3: block mt * 4 + kb, chained k
+        const int b = blk - F_W1, l = b >> 3, mt = (b >> 2) & 1, kb = b & 3;
+        x = P[tm::W1 + l * (tm::H * tm::H + tm::H) + (32 * mt + m) * tm::H + chain_row(kb, h, q)];
+      } else if (blk < F_W1T) {                  // head: kb 0..3 chained h3, kb 4 gamma(d) natural
+        const int kb = blk - F_WH;
+        if (m < 4) {
+          if (kb < 4) {
+            const int u = chain_row(kb, h, q);
+            x = m == 0 ? P[tm::WS + u] : P[tm::WC + (m - 1) * tm::IC + u];
+          } else {
+            const int k = 8 * h + q;
+            x = (m > 0 && k < tm::ID) ? P[tm::WC + (m - 1) * tm::IC + tm::H + k] : 0.0f;
+          }
+        }
+      } else if (blk < F_WHT) {                  // W1^T..W3^T: rows = input units, chained k = output units
+        const int b = blk - F_W1T, l = b >> 3, mt = (b >> 2) & 1, kb = b & 3;
+        x = P[tm::W1 + l * (tm::H * tm::H + tm::H) + chain_row(kb, h, q) * tm::H + 32 * mt + m];
+      } else {                                   // head^T: rows = h3 units, natural k = head rows
+        const int mt = blk - F_WHT, k = 8 * h + q, u = 32 * mt + m;
+        if (k == 0) x = P[tm::WS + u];
+        else if (k < 4) x = P[tm::WC + (k - 1) * tm::IC + u];
+      }
+      v[q] = x;
+    }
+    uint4 u;
+    u.x = pack2_bf16(v[0], v[1]); u.y = pack2_bf16(v[2], v[3]);
+    u.z = pack2_bf16(v[4], v[5]); u.w = pack2_bf16(v[6], v[7]);
+    s_w[e] = u;
   }
-  if (e >= tm::N) return;
-  float g = 0.0f;
-  for (int v = 0; v < a.n_waves; ++v) g += a.partial[(long)v * tm::N + e];
-  if (a.grad_out) a.grad_out[e] = g;
+  for (int e = threadIdx.x; e < 4 * tm::H + 4; e += blockDim.x) {
+    float x;
+    if (e < 4 * tm::H) {
+      const int l = e / tm::H, j = e - l * tm::H;
+      x = P[(l == 0 ? tm::B0 : tm::B1 + (l - 1) * (tm::H * tm::H + tm::H)) + j];
+    } else {
+      const int r = e - 4 * tm::H;
+      x = r == 0 ? P[tm::BS] : P[tm::BC + r - 1];
+    }
+    s_b[e] = x;
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 31, h = lane >> 5;
+  __bf16* tab = s_t[wv];
+  for (int e = lane; e < 3 * tm::H; e += 64) s_db[wv][e] = 0.0f;
+  // constant rows: the zero rows and gamma(d)'s row of ones
+  if (h == 0) {
+    tab[(T_X + 48) * kTabRow + n] = (__bf16)0.0f;
+    tab[(T_G + 4) * kTabRow + n] = (__bf16)0.0f;
+    tab[(T_D + 15) * kTabRow + n] = (__bf16)1.0f;
+    tab[(T_D + 16) * kTabRow + n] = (__bf16)0.0f;
+  }
+  __syncthreads();
+  const int wave = blockIdx.x * WAVES + wv;
+  if (wave >= a.n_waves) return;   // no barrier follows
+  const float scale = 2.0f / (float)a.batch;
+
+  pf32x16 dw0[2][2], dw[3][2][2], dwh[3];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      dw0[mt][nt] = tmb_zero();
+#pragma unroll
+      for (int l = 0; l < 3; ++l) dw[l][mt][nt] = tmb_zero();
+    }
+#pragma unroll
+  for (int nt = 0; nt < 3; ++nt) dwh[nt] = tmb_zero();
+  float lsum = 0.0f;
+  pbf16x8 ones;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ones[q] = (__bf16)1.0f;
+
+  for (int q0 = 0; q0 < a.rays_per_wave; ++q0) {
+    const int rb = wave * a.rays_per_wave + q0;   // position in the batch
+    if (rb >= a.batch) break;
+    const long ray = ((long)a.first + rb) % a.n_rays;
+    const float4 o = a.ray_o[ray], d = a.ray_d[ray];
+    // sample n of the ray (streams keyed (ray, 0), as the float32 kernel)
+    float xi = 0.0f;
+    if (a.jitter) xi = unit24(pick(draw(a.seed, a.iter, kStreamJitCoarse, (uint32_t)ray, 0, n >> 2), n & 3));
+    const float t = a.near_ + ((float)n + xi) * a.dt;
+    // gamma(x) operands (k-row 16 kb + 8 h + q) and their table rows
+    pbf16x8 xb[XK];
+    {
+      const float pc[3] = {fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z)};
+      float sn[3][6], cs[3][6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int l = 0; l < 6; ++l) sincospif(ldexpf(pc[c], l), &sn[c][l], &cs[c][l]);
+#pragma unroll
+      for (int kb = 0; kb < XK; ++kb) {
+        float xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float x0 = 0.0f, x1 = 0.0f;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int k = 16 * kb + 8 * hh + q;
+            float x = 0.0f;
+            if (k < 3) x = pc[k];
+            else if (k < tm::IX) {
+              const int qq = k - 3, l = qq / 6, rr = qq % 6, c = rr % 3;
+              x = rr < 3 ? sn[c][l] : cs[c][l];
+            } else if (k == tm::IX) {
+              x = 1.0f;
+            }
+            if (hh == 0) x0 = x; else x1 = x;
+          }
+          xv[q] = h ? x1 : x0;
+        }
+        uint4 u;
+        u.x = pack2_bf16(xv[0], xv[1]); u.y = pack2_bf16(xv[2], xv[3]);
+        u.z = pack2_bf16(xv[4], xv[5]); u.w = pack2_bf16(xv[6], xv[7]);
+        xb[kb] = __builtin_bit_cast(pbf16x8, u);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tab[(T_X + 16 * kb + 8 * h + q) * kTabRow + n] = xb[kb][q];
+      }
+    }
+    // gamma(d) operand (natural k-row 8 h + q; k = 15 holds 1) and table
+    pbf16x8 gdb;
+    {
+      float sd[3][2], cd[3][2];
+      const float dc[3] = {d.x, d.y, d.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) sincospif(ldexpf(dc[c], l), &sd[c][l], &cd[c][l]);
+      float gv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float x0 = 0.0f, x1 = 0.0f;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int k = 8 * hh + q;
+          float x;
+          if (k < 3) x = dc[k];
+          else if (k < tm::ID) {
+            const int qq = k - 3, l = qq / 6, rr = qq % 6, c = rr % 3;
+            x = rr < 3 ? sd[c][l] : cd[c][l];
+          } else {
+            x = 1.0f;
+          }
+          if (hh == 0) x0 = x; else x1 = x;
+        }
+        gv[q] = h ? x1 : x0;
+      }
+      uint4 u;
+      u.x = pack2_bf16(gv[0], gv[1]); u.y = pack2_bf16(gv[2], gv[3]);
+      u.z = pack2_bf16(gv[4], gv[5]); u.w = pack2_bf16(gv[6], gv[7]);
+      gdb = __builtin_bit_cast(pbf16x8, u);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (8 * h + q < tm::ID) tab[(T_D + 8 * h + q) * kTabRow + n] = gdb[q];
+    }
+    // forward (each layer's activations also into its table)
+    pbf16x8 hb[4];   // chained operands of the last layer computed
+    {
+      pf32x16 s0[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s0[mt][r] = s_b[32 * mt + tile_row(r, h)];
+#pragma unroll
+        for (int kb = 0; kb < XK; ++kb) s0[mt] = tmb_mfma(s_w[(F_W0 + mt * XK + kb) * 64 + lane], xb[kb], s0[mt]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s0[mt][r] = fmaxf(s0[mt][r], 0.0f);
+        tile_operands_bf16(s0[mt], hb[2 * mt], hb[2 * mt + 1]);
+        tile_to_table(s0[mt], tab + T_H0 * kTabRow, 32 * mt, n, h);
+      }
+    }
+#pragma unroll
+    for (int l = 1; l < 4; ++l) {
+      pf32x16 sl[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sl[mt][r] = s_b[l * tm::H + 32 * mt + tile_row(r, h)];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+          sl[mt] = tmb_mfma(s_w[(F_W1 + (l - 1) * 8 + mt * 4 + kb) * 64 + lane], hb[kb], sl[mt]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sl[mt][r] = fmaxf(sl[mt][r], 0.0f);
+        tile_to_table(sl[mt], tab + (T_H0 + 64 * l) * kTabRow, 32 * mt, n, h);
+      }
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) tile_operands_bf16(sl[mt], hb[2 * mt], hb[2 * mt + 1]);
+    }
+    pf32x16 z;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = tile_row(r, h);
+      z[r] = row < 4 ? s_b[4 * tm::H + row] : 0.0f;
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) z = tmb_mfma(s_w[(F_WH + kb) * 64 + lane], hb[kb], z);
+    z = tmb_mfma(s_w[(F_WH + 4) * 64 + lane], gdb, z);
+    // compositing (Eq. 1) and its gradient on the lanes of half 0: sample n
+    const bool on = h == 0;
+    const float zs = z[0], zc[3] = {z[1], z[2], z[3]};
+    const float sig = on ? tm_softplus(zs) : 0.0f;
+    float cl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cl[c] = tm_sigmoid(zc[c]);
+    const float t_next = __shfl_down(t, 1, 32);
+    const float delta = n + 1 < 32 ? t_next - t : a.far_ - t;
+    const float tau = sig * delta;
+    float incl = tau;
+#pragma unroll
+    for (int o2 = 1; o2 < 32; o2 <<= 1) {
+      const float u = __shfl_up(incl, o2, 32);
+      if (n >= o2) incl += u;
+    }
+    const float T_k = expf(-(incl - tau)), T_k1 = expf(-incl);
+    const float wk = on ? T_k * (-expm1f(-tau)) : 0.0f;
+    float gC[3], sfx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float wc = wk * cl[c];
+      float sc = wc, tot = wc;
+#pragma unroll
+      for (int o2 = 1; o2 < 32; o2 <<= 1) {
+        const float u = __shfl_up(sc, o2, 32);
+        if (n >= o2) sc += u;
+        tot += __shfl_xor(tot, o2, 32);
+      }
+      sfx[c] = tot - sc;
+      const float err = tot - a.target[ray * 3 + c];
+      lsum += err * err;
+      gC[c] = scale * err;
+    }
+    float dsig = 0.0f, dzc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dsig = fmaf(gC[c], T_k1 * cl[c] - sfx[c], dsig);
+      dzc[c] = on ? wk * gC[c] * cl[c] * (1.0f - cl[c]) : 0.0f;
+    }
+    const float dzs = on ? dsig * delta * tm_sigmoid(zs) : 0.0f;
+    // head gradient: operand (natural k-rows 0..3 in half 0) and table rows
+    pbf16x8 gb;
+    {
+      uint4 u;
+      u.x = pack2_bf16(dzs, dzc[0]);
+      u.y = pack2_bf16(dzc[1], dzc[2]);
+      u.z = 0u;
+      u.w = 0u;
+      gb = __builtin_bit_cast(pbf16x8, u);
+      if (on)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tab[(T_G + r) * kTabRow + n] = gb[r];
+    }
+    // backward through the layers: da3 = W_head^T g, then dz_l and dW_l
+    pf32x16 dz[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+      dz[mt] = tmb_mask(tmb_mfma(s_w[(F_WHT + mt) * 64 + lane], gb, tmb_zero()), tab + T_H3 * kTabRow, mt, n, h);
+#pragma unroll
+    for (int l = 3; l >= 0; --l) {
+      // pass 0 accumulates W3, W2 (and the heads), pass 1 W1, W0
+      const bool mine = PASS == 0 ? l >= 2 : l <= 1;
+      if (mine) {
+      // dz_l into the table (after the last layer's reads of it)
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) tile_to_table(dz[mt], tab + T_DZ * kTabRow, 32 * mt, n, h);
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("" ::: "memory");
+      // dW_l += dz_l h_{l-1}^T over the 32 samples; db_l against ones
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        pbf16x8 ga[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T_DZ * kTabRow, 32 * mt + n, kb, h);
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb) {
+            if (l == 0) {
+              const int row = 32 * nt + n < 48 ? 32 * nt + n : 48;
+              dw0[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  ga[kb], table_operand(tab + T_X * kTabRow, row, kb, h), dw0[mt][nt], 0, 0, 0);
+            } else {
+              dw[l - 1][mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  ga[kb], table_operand(tab + (T_H0 + 64 * (l - 1)) * kTabRow, 32 * nt + n, kb, h),
+                  dw[l - 1][mt][nt], 0, 0, 0);
+            }
+          }
+        if (l > 0) {
+          pf32x16 db = tmb_zero();
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb) db = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[kb], ones, db, 0, 0, 0);
+          if (n == 0)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) s_db[wv][(l - 1) * tm::H + 32 * mt + tile_row(v, h)] += db[v];
+        }
+      }
+      }
+      if (l == 0 || (PASS == 0 && l == 2)) break;
+      // da_{l-1} = W_l^T dz_l, masked by h_{l-1} > 0
+      pbf16x8 dzb[4];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) tile_operands_bf16(dz[mt], dzb[2 * mt], dzb[2 * mt + 1]);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        pf32x16 da = tmb_zero();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) da = tmb_mfma(s_w[(F_W1T + (l - 1) * 8 + mt * 4 + kb) * 64 + lane], dzb[kb], da);
+        dz[mt] = tmb_mask(da, tab + (T_H0 + 64 * (l - 1)) * kTabRow, mt, n, h);
+      }
+    }
+    // head weights: dW_head += g [h3, gamma(d)]^T (row m of g: min(m, 4), a zero row)
+    if (PASS == 0) {
+      pbf16x8 ga[2];
+      const int grow = n < 4 ? n : 4;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T_G * kTabRow, grow, kb, h);
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+          dwh[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ga[kb], table_operand(tab + T_H3 * kTabRow, 32 * nt + n, kb, h), dwh[nt], 0, 0, 0);
+        dwh[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            ga[kb], table_operand(tab + T_D * kTabRow, n < 16 ? n : 16, kb, h), dwh[2], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+  }
+  // per-wave partials in parameter order (each pass its own entries)
+  float* out = a.partial + (long)wave * tm::N;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int j = 32 * mt + tile_row(v, h);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const int k = 32 * nt + n;
+        if (PASS == 1) {
+          if (k < tm::IX) out[tm::W0 + j * tm::IX + k] = dw0[mt][nt][v];
+          else if (k == tm::IX) out[tm::B0 + j] = dw0[mt][nt][v];
+          out[tm::W1 + j * tm::H + k] = dw[0][mt][nt][v];
+        } else {
+#pragma unroll
+          for (int l = 1; l < 3; ++l) out[tm::W1 + l * (tm::H * tm::H + tm::H) + j * tm::H + k] = dw[l][mt][nt][v];
+        }
+      }
+    }
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+  for (int e = lane; e < 3 * tm::H; e += 64) {
+    const int l = e / tm::H, j = e - l * tm::H;
+    if (PASS == 0 ? l >= 1 : l == 0) out[tm::B1 + l * (tm::H * tm::H + tm::H) + j] = s_db[wv][e];
+  }
+  if (PASS == 1) return;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = tile_row(v, h);
+    if (r >= 4) continue;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int u = 32 * nt + n;
+      if (r == 0) out[tm::WS + u] = dwh[nt][v];
+      else out[tm::WC + (r - 1) * tm::IC + u] = dwh[nt][v];
+    }
+    if (n < tm::ID) {
+      if (r > 0) out[tm::WC + (r - 1) * tm::IC + tm::H + n] = dwh[2][v];
+    } else if (n == tm::ID) {
+      if (r == 0) out[tm::BS] = dwh[2][v];
+      else out[tm::BC + r - 1] = dwh[2][v];
+    }
+  }
+  if (lane == 0) a.loss_partial[wave] = lsum;
+}
+
+// sum of the per-wave partials; then the gradient, or one Adam step (t =
+// step, counted from 1).  A workgroup takes kRedP parameters; its kRedG
+// thread groups sum waves g, g + kRedG, ... and the groups' sums are added
+// in group order (a fixed order: the result does not depend on the launch).
+// The last workgroup sums the loss the same way.
+constexpr int kRedP = 32, kRedG = 8;
+
+__global__ __launch_bounds__(kRedP * kRedG) void k_map_reduce(const MapTrainArgs a) {
+  __shared__ float s_part[kRedG * kRedP];
+  const int p = threadIdx.x & (kRedP - 1), g = threadIdx.x / kRedP;
+  if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    if (!a.loss_out) return;   // whole workgroup, before any barrier
+    float l = 0.0f;
+    for (int v = threadIdx.x; v < a.n_waves; v += kRedP * kRedG) l += a.loss_partial[v];
+    s_part[threadIdx.x] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int k = 0; k < kRedP * kRedG; ++k) t += s_part[k];
+      a.loss_out[a.loss_index] = t / (float)a.batch;
+    }
+    return;
+  }
+  const int e = blockIdx.x * kRedP + p;
+  float acc = 0.0f;
+  if (e < tm::N) {
+#pragma unroll 4
+    for (int v = g; v < a.n_waves; v += kRedG) acc += a.partial[(long)v * tm::N + e];
+  }
+  s_part[g * kRedP + p] = acc;
+  __syncthreads();
+  if (g != 0 || e >= tm::N) return;
+  float gsum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kRedG; ++k) gsum += s_part[k * kRedP + p];
+  if (a.grad_out) a.grad_out[e] = gsum;
   if (a.adam) {
-    const float m = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
-    const float v = a.beta2 * a.v[e] + (1.0f - a.beta2) * g * g;
+    const float m = a.beta1 * a.m[e] + (1.0f - a.beta1) * gsum;
+    const float v = a.beta2 * a.v[e] + (1.0f - a.beta2) * gsum * gsum;
     a.m[e] = m;
     a.v[e] = v;
     const float mhat = m / (1.0f - powf(a.beta1, (float)a.step));
@@ -318,14 +788,26 @@ __global__ __launch_bounds__(256) void k_map_reduce(const MapTrainArgs a) {
 
 hipError_t launch_map_grad(const MapTrainArgs& a, hipStream_t st) {
   if (a.S < 1 || a.S > 64 || a.n_waves < 1) return hipErrorInvalidValue;
-  const dim3 grid((a.n_waves + kTmWaves - 1) / kTmWaves);
-  hipLaunchKernelGGL(k_map_grad<0>, grid, dim3(64 * kTmWaves), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_map_grad<1>, grid, dim3(64 * kTmWaves), 0, st, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_map_reduce, dim3((tm::N + 255) / 256), dim3(256), 0, st, a);
+  hipError_t e;
+  if (a.bf16) {
+    if (a.S != 32) return hipErrorInvalidValue;
+    const dim3 grid((a.n_waves + tmb::WAVES - 1) / tmb::WAVES);
+    hipLaunchKernelGGL(k_map_grad_bf16<0>, grid, dim3(64 * tmb::WAVES), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_map_grad_bf16<1>, grid, dim3(64 * tmb::WAVES), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    const dim3 grid((a.n_waves + kTmWaves - 1) / kTmWaves);
+    hipLaunchKernelGGL(k_map_grad<0>, grid, dim3(64 * kTmWaves), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_map_grad<1>, grid, dim3(64 * kTmWaves), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_map_reduce, dim3((tm::N + kRedP - 1) / kRedP + 1), dim3(kRedP * kRedG), 0, st, a);
   return hipGetLastError();
 }
 
