@@ -70,7 +70,8 @@ _H, _IX, _IC = 64, 39, 79
 _OFF = np.cumsum([0, _H * _IX, _H, _H * _H, _H, _H * _H, _H, _H * _H, _H, _H, 1, 3 * _IC, 3])
 
 
-@pytest.mark.parametrize("n,jitter", [(48, 1), (130, 0)])
+# 1001 rays: two rays per wave, the last wave with one
+@pytest.mark.parametrize("n,jitter", [(48, 1), (130, 0), (1001, 1)])
 def test_map_gradient_bf16_matches_oracle(torch_dev, n, jitter):
     torch = torch_dev
     spec = synth.spec("small", n_coarse=32, jitter=jitter)
