@@ -449,9 +449,18 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       const float pc[3] = {fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z)};
       float sn[3][6], cs[3][6];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c) {
+        // band 0 by sincospif, band l + 1 from band l by the double-angle
+        // identities (each doubling at most doubles the absolute error:
+        // within 2^5 float32 roundings at band 5, far inside bf16 rounding)
+        sincospif(pc[c], &sn[c][0], &cs[c][0]);
 #pragma unroll
-        for (int l = 0; l < 6; ++l) sincospif(ldexpf(pc[c], l), &sn[c][l], &cs[c][l]);
+        for (int l = 1; l < 6; ++l) {
+          const float sa = sn[c][l - 1], ca = cs[c][l - 1];
+          sn[c][l] = 2.0f * sa * ca;
+          cs[c][l] = (ca - sa) * (ca + sa);
+        }
+      }
 #pragma unroll
       for (int kb = 0; kb < XK; ++kb) {
         float xv[8];
@@ -487,9 +496,11 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       float sd[3][2], cd[3][2];
       const float dc[3] = {d.x, d.y, d.z};
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int l = 0; l < 2; ++l) sincospif(ldexpf(dc[c], l), &sd[c][l], &cd[c][l]);
+      for (int c = 0; c < 3; ++c) {
+        sincospif(dc[c], &sd[c][0], &cd[c][0]);
+        sd[c][1] = 2.0f * sd[c][0] * cd[c][0];
+        cd[c][1] = (cd[c][0] - sd[c][0]) * (cd[c][0] + sd[c][0]);
+      }
       float gv[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
