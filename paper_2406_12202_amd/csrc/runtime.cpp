@@ -1995,14 +1995,14 @@ loc_status loc_localize(loc_ctx* c, const float* image, const loc_camera* cam, i
 namespace {
 
 constexpr int kMapWavesMax = 1024;   // partial-gradient rows per call, at most
-constexpr int kMapWavesBf16 = 768;   // the same for the bf16 kernel
+constexpr int kMapWavesBf16 = 1024;  // the same for the bf16 kernel (four waves per CU)
 
 loc_status tm_prepare(loc_ctx* c, const float* ray_o, const float* ray_d, int n, int batch, MapTrainArgs& ta) {
   const loc_map_desc& d = c->desc;
   if (c->kind != kMapSmall || d.n_fine != 0 || d.n_coarse > 64 || c->desc.precision == LOC_FP8_E4M3)
     return fail(c, LOC_E_UNSUPPORTED, "map training covers the 4x64 map with at most 64 coarse and no fine samples");
   // bf16 contexts with 32 samples per ray take the matrix-core kernel: one
-  // ray at a time per wave, sized to fill 768 waves (three per CU) once
+  // ray at a time per wave, sized to fill 1024 waves (four per CU) once
   const bool bf16 = d.precision == LOC_BF16 && d.n_coarse == 32;
   const int rpw = bf16 ? (batch + kMapWavesBf16 - 1) / kMapWavesBf16 : (batch + kMapWavesMax - 1) / kMapWavesMax;
   const int n_waves = (batch + rpw - 1) / rpw;

@@ -310,16 +310,33 @@ __global__ __launch_bounds__(64 * kTmWaves) void k_map_grad(const MapTrainArgs a
 // rays; db1..db3 come from the same tables against a column of ones, into
 // LDS.  Each wave writes its partial gradient in parameter order.
 namespace tmb {
-constexpr int WAVES = 3;
+constexpr int WAVES = 4;
 constexpr int XK = 3;                                    // k-blocks of gamma(x) (48 rows)
-// weight fragments (1 KB blocks) in LDS
+// weight fragments (1 KB blocks) in LDS; pass 0 stages the blocks before
+// F_W2T, pass 1 all
 constexpr int F_W0 = 0, F_W1 = F_W0 + 2 * XK, F_W2 = F_W1 + 8, F_W3 = F_W2 + 8, F_WH = F_W3 + 8,
-              F_W1T = F_WH + 5, F_W2T = F_W1T + 8, F_W3T = F_W2T + 8, F_WHT = F_W3T + 8, F_N = F_WHT + 2;
-// per-wave tables (rows of kTabRow bf16): gamma(x) 48 + a zero row, h0..h3,
-// the current layer's output gradient, the head gradient (4 rows + a zero
-// row), gamma(d) (15 rows, a row of ones, a zero row)
-constexpr int T_X = 0, T_H0 = T_X + 49, T_H1 = T_H0 + 64, T_H2 = T_H1 + 64, T_H3 = T_H2 + 64, T_DZ = T_H3 + 64,
-              T_G = T_DZ + 64, T_D = T_G + 5, T_ROWS = T_D + 17;
+              F_W3T = F_WH + 5, F_WHT = F_W3T + 8, F_W2T = F_WHT + 2, F_W1T = F_W2T + 8, F_N = F_W1T + 8;
+__host__ __device__ constexpr int f_wt(int l) { return l == 3 ? F_W3T : (l == 2 ? F_W2T : F_W1T); }
+template <int PASS>
+constexpr int frag_blocks() { return PASS == 0 ? F_W2T : F_N; }
+// per-wave tables (rows of kTabRow bf16) of a pass; -1: not kept.  Pass 0:
+// h1, h2, h3, the output gradient of the current layer, the head gradient
+// (4 rows and a zero row), gamma(d) (15 rows, a row of ones, a zero row).
+// Pass 1: gamma(x) (48 rows and a zero row), h0, the output gradient.
+template <int PASS>
+struct Tab;
+template <>
+struct Tab<0> {
+  static constexpr int X = -1, H0 = -1, H1 = 0, H2 = 64, H3 = 128, DZ = 192, G = 256, D = 261, ROWS = 278;
+};
+template <>
+struct Tab<1> {
+  static constexpr int X = 0, H0 = 49, H1 = -1, H2 = -1, H3 = -1, DZ = 113, G = -1, D = -1, ROWS = 177;
+};
+template <int PASS>
+__host__ __device__ constexpr int tab_h(int l) {
+  return l == 0 ? Tab<PASS>::H0 : (l == 1 ? Tab<PASS>::H1 : (l == 2 ? Tab<PASS>::H2 : Tab<PASS>::H3));
+}
 }  // namespace tmb
 
 __device__ __forceinline__ pf32x16 tmb_zero() {
@@ -333,13 +350,12 @@ __device__ __forceinline__ pf32x16 tmb_mfma(const uint4& a, const pbf16x8& b, co
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(pbf16x8, a), b, c, 0, 0, 0);
 }
 
-// ReLU'd output gradient of tile mt: da where the activation (its table
-// rows, [unit][sample]) is positive
-__device__ __forceinline__ pf32x16 tmb_mask(const pf32x16& da, const __bf16* hrows, const int mt, const int n,
-                                            const int h) {
+// ReLU'd output gradient of tile mt: da where the layer's activation was
+// positive (bit 16 mt + v of the layer's mask)
+__device__ __forceinline__ pf32x16 tmb_mask(const pf32x16& da, const uint32_t mask, const int mt) {
   pf32x16 dz;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) dz[v] = (float)hrows[(32 * mt + tile_row(v, h)) * kTabRow + n] > 0.0f ? da[v] : 0.0f;
+  for (int v = 0; v < 16; ++v) dz[v] = (mask >> (16 * mt + v)) & 1u ? da[v] : 0.0f;
   return dz;
 }
 
@@ -347,14 +363,16 @@ template <int PASS>
 __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_map_grad_bf16(
     const MapTrainArgs a) {
   using namespace tmb;
-  __shared__ uint4 s_w[F_N * 64];
-  __shared__ __align__(16) __bf16 s_t[WAVES][T_ROWS * kTabRow];
+  using T = Tab<PASS>;
+  constexpr int FN = frag_blocks<PASS>();
+  __shared__ uint4 s_w[FN * 64];
+  __shared__ __align__(16) __bf16 s_t[WAVES][T::ROWS * kTabRow];
   __shared__ float s_b[4 * tm::H + 4];
   __shared__ float s_db[WAVES][3 * tm::H];
   const float* __restrict__ P = a.params;
   // weight fragments in the operand order of each product: lane (m, h) of
   // block holds A[m][k] for its eight k of k-block kb
-  for (int e = threadIdx.x; e < F_N * 64; e += blockDim.x) {
+  for (int e = threadIdx.x; e < FN * 64; e += blockDim.x) {
     const int blk = e >> 6, ln = e & 63, m = ln & 31, h = ln >> 5;
     float v[8];
 #pragma unroll
@@ -366,7 +384,7 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       } else if (blk < F_WH) {                   // W1..W3: block mt * 4 + kb, chained k
         const int b = blk - F_W1, l = b >> 3, mt = (b >> 2) & 1, kb = b & 3;
         x = P[tm::W1 + l * (tm::H * tm::H + tm::H) + (32 * mt + m) * tm::H + chain_row(kb, h, q)];
-      } else if (blk < F_W1T) {                  // head: kb 0..3 chained h3, kb 4 gamma(d) natural
+      } else if (blk < F_W3T) {                  // head: kb 0..3 chained h3, kb 4 gamma(d) natural
         const int kb = blk - F_WH;
         if (m < 4) {
           if (kb < 4) {
@@ -377,13 +395,14 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
             x = (m > 0 && k < tm::ID) ? P[tm::WC + (m - 1) * tm::IC + tm::H + k] : 0.0f;
           }
         }
-      } else if (blk < F_WHT) {                  // W1^T..W3^T: rows = input units, chained k = output units
-        const int b = blk - F_W1T, l = b >> 3, mt = (b >> 2) & 1, kb = b & 3;
-        x = P[tm::W1 + l * (tm::H * tm::H + tm::H) + chain_row(kb, h, q) * tm::H + 32 * mt + m];
-      } else {                                   // head^T: rows = h3 units, natural k = head rows
+      } else if (blk >= F_WHT && blk < F_W2T) {  // head^T: rows = h3 units, natural k = head rows
         const int mt = blk - F_WHT, k = 8 * h + q, u = 32 * mt + m;
         if (k == 0) x = P[tm::WS + u];
         else if (k < 4) x = P[tm::WC + (k - 1) * tm::IC + u];
+      } else {                                   // W3^T, W2^T, W1^T: rows = input units, chained k = output units
+        const int l = blk < F_WHT ? 3 : (blk < F_W1T ? 2 : 1);
+        const int b = blk - f_wt(l), mt = b >> 2, kb = b & 3;
+        x = P[tm::W1 + (l - 1) * (tm::H * tm::H + tm::H) + chain_row(kb, h, q) * tm::H + 32 * mt + m];
       }
       v[q] = x;
     }
@@ -408,10 +427,13 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
   for (int e = lane; e < 3 * tm::H; e += 64) s_db[wv][e] = 0.0f;
   // constant rows: the zero rows and gamma(d)'s row of ones
   if (h == 0) {
-    tab[(T_X + 48) * kTabRow + n] = (__bf16)0.0f;
-    tab[(T_G + 4) * kTabRow + n] = (__bf16)0.0f;
-    tab[(T_D + 15) * kTabRow + n] = (__bf16)1.0f;
-    tab[(T_D + 16) * kTabRow + n] = (__bf16)0.0f;
+    if constexpr (PASS == 1) {
+      tab[(T::X + 48) * kTabRow + n] = (__bf16)0.0f;
+    } else {
+      tab[(T::G + 4) * kTabRow + n] = (__bf16)0.0f;
+      tab[(T::D + 15) * kTabRow + n] = (__bf16)1.0f;
+      tab[(T::D + 16) * kTabRow + n] = (__bf16)0.0f;
+    }
   }
   __syncthreads();
   const int wave = blockIdx.x * WAVES + wv;
@@ -486,8 +508,9 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
         u.x = pack2_bf16(xv[0], xv[1]); u.y = pack2_bf16(xv[2], xv[3]);
         u.z = pack2_bf16(xv[4], xv[5]); u.w = pack2_bf16(xv[6], xv[7]);
         xb[kb] = __builtin_bit_cast(pbf16x8, u);
+        if constexpr (PASS == 1)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) tab[(T_X + 16 * kb + 8 * h + q) * kTabRow + n] = xb[kb][q];
+          for (int q = 0; q < 8; ++q) tab[(T::X + 16 * kb + 8 * h + q) * kTabRow + n] = xb[kb][q];
       }
     }
     // gamma(d) operand (natural k-row 8 h + q; k = 15 holds 1) and table
@@ -526,10 +549,11 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       gdb = __builtin_bit_cast(pbf16x8, u);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (8 * h + q < tm::ID) tab[(T_D + 8 * h + q) * kTabRow + n] = gdb[q];
+        if (PASS == 0 && 8 * h + q < tm::ID) tab[(T::D + 8 * h + q) * kTabRow + n] = gdb[q];
     }
     // forward (each layer's activations also into its table)
     pbf16x8 hb[4];   // chained operands of the last layer computed
+    uint32_t mk[4];  // ReLU masks of h0..h3: bit 16 mt + v
     {
       pf32x16 s0[2];
 #pragma unroll
@@ -541,8 +565,13 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int r = 0; r < 16; ++r) s0[mt][r] = fmaxf(s0[mt][r], 0.0f);
         tile_operands_bf16(s0[mt], hb[2 * mt], hb[2 * mt + 1]);
-        tile_to_table(s0[mt], tab + T_H0 * kTabRow, 32 * mt, n, h);
+        if constexpr (T::H0 >= 0) tile_to_table(s0[mt], tab + T::H0 * kTabRow, 32 * mt, n, h);
       }
+      mk[0] = 0u;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mk[0] |= (s0[mt][r] > 0.0f ? 1u : 0u) << (16 * mt + r);
     }
 #pragma unroll
     for (int l = 1; l < 4; ++l) {
@@ -556,8 +585,13 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
           sl[mt] = tmb_mfma(s_w[(F_W1 + (l - 1) * 8 + mt * 4 + kb) * 64 + lane], hb[kb], sl[mt]);
 #pragma unroll
         for (int r = 0; r < 16; ++r) sl[mt][r] = fmaxf(sl[mt][r], 0.0f);
-        tile_to_table(sl[mt], tab + (T_H0 + 64 * l) * kTabRow, 32 * mt, n, h);
+        if (tab_h<PASS>(l) >= 0) tile_to_table(sl[mt], tab + tab_h<PASS>(l) * kTabRow, 32 * mt, n, h);
       }
+      mk[l] = 0u;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mk[l] |= (sl[mt][r] > 0.0f ? 1u : 0u) << (16 * mt + r);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) tile_operands_bf16(sl[mt], hb[2 * mt], hb[2 * mt + 1]);
     }
@@ -620,15 +654,15 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       u.z = 0u;
       u.w = 0u;
       gb = __builtin_bit_cast(pbf16x8, u);
-      if (on)
+      if (PASS == 0 && on)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) tab[(T_G + r) * kTabRow + n] = gb[r];
+        for (int r = 0; r < 4; ++r) tab[(T::G + r) * kTabRow + n] = gb[r];
     }
     // backward through the layers: da3 = W_head^T g, then dz_l and dW_l
     pf32x16 dz[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
-      dz[mt] = tmb_mask(tmb_mfma(s_w[(F_WHT + mt) * 64 + lane], gb, tmb_zero()), tab + T_H3 * kTabRow, mt, n, h);
+      dz[mt] = tmb_mask(tmb_mfma(s_w[(F_WHT + mt) * 64 + lane], gb, tmb_zero()), mk[3], mt);
 #pragma unroll
     for (int l = 3; l >= 0; --l) {
       // pass 0 accumulates W3, W2 (and the heads), pass 1 W1, W0
@@ -638,7 +672,7 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       __builtin_amdgcn_wave_barrier();
       asm volatile("" ::: "memory");
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) tile_to_table(dz[mt], tab + T_DZ * kTabRow, 32 * mt, n, h);
+      for (int mt = 0; mt < 2; ++mt) tile_to_table(dz[mt], tab + T::DZ * kTabRow, 32 * mt, n, h);
       __builtin_amdgcn_wave_barrier();
       asm volatile("" ::: "memory");
       // dW_l += dz_l h_{l-1}^T over the 32 samples; db_l against ones
@@ -646,7 +680,7 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       for (int mt = 0; mt < 2; ++mt) {
         pbf16x8 ga[2];
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T_DZ * kTabRow, 32 * mt + n, kb, h);
+        for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T::DZ * kTabRow, 32 * mt + n, kb, h);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
@@ -654,10 +688,10 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
             if (l == 0) {
               const int row = 32 * nt + n < 48 ? 32 * nt + n : 48;
               dw0[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ga[kb], table_operand(tab + T_X * kTabRow, row, kb, h), dw0[mt][nt], 0, 0, 0);
+                  ga[kb], table_operand(tab + T::X * kTabRow, row, kb, h), dw0[mt][nt], 0, 0, 0);
             } else {
               dw[l - 1][mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  ga[kb], table_operand(tab + (T_H0 + 64 * (l - 1)) * kTabRow, 32 * nt + n, kb, h),
+                  ga[kb], table_operand(tab + tab_h<PASS>(l - 1) * kTabRow, 32 * nt + n, kb, h),
                   dw[l - 1][mt][nt], 0, 0, 0);
             }
           }
@@ -680,8 +714,8 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       for (int mt = 0; mt < 2; ++mt) {
         pf32x16 da = tmb_zero();
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) da = tmb_mfma(s_w[(F_W1T + (l - 1) * 8 + mt * 4 + kb) * 64 + lane], dzb[kb], da);
-        dz[mt] = tmb_mask(da, tab + (T_H0 + 64 * (l - 1)) * kTabRow, mt, n, h);
+        for (int kb = 0; kb < 4; ++kb) da = tmb_mfma(s_w[(f_wt(l) + mt * 4 + kb) * 64 + lane], dzb[kb], da);
+        dz[mt] = tmb_mask(da, mk[l - 1], mt);
       }
     }
     // head weights: dW_head += g [h3, gamma(d)]^T (row m of g: min(m, 4), a zero row)
@@ -689,15 +723,15 @@ __global__ __launch_bounds__(64 * tmb::WAVES) __attribute__((amdgpu_waves_per_eu
       pbf16x8 ga[2];
       const int grow = n < 4 ? n : 4;
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T_G * kTabRow, grow, kb, h);
+      for (int kb = 0; kb < 2; ++kb) ga[kb] = table_operand(tab + T::G * kTabRow, grow, kb, h);
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
           dwh[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ga[kb], table_operand(tab + T_H3 * kTabRow, 32 * nt + n, kb, h), dwh[nt], 0, 0, 0);
+              ga[kb], table_operand(tab + T::H3 * kTabRow, 32 * nt + n, kb, h), dwh[nt], 0, 0, 0);
         dwh[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            ga[kb], table_operand(tab + T_D * kTabRow, n < 16 ? n : 16, kb, h), dwh[2], 0, 0, 0);
+            ga[kb], table_operand(tab + T::D * kTabRow, n < 16 ? n : 16, kb, h), dwh[2], 0, 0, 0);
       }
     }
     __builtin_amdgcn_wave_barrier();
