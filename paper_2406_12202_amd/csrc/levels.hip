@@ -221,19 +221,26 @@ __device__ __forceinline__ void head_tile_r(const uint4* w, const float* bl, con
   }
 }
 
-// operands of column tile nt for lane (n, h) from the lane that computed
-// sample n of ray nt (lane n + 32 nt): its own half-h operand when nt == h,
-// else the partner lane's (lane xor 32), which sends its half-(1 - h) operand
-__device__ __forceinline__ void tile_operands(const bf16x8& mine, const bf16x8& other_half, const int h,
-                                              bf16x8& t0, bf16x8& t1) {
-  uint4 u = __builtin_bit_cast(uint4, other_half);
-  u.x = (uint32_t)__shfl_xor((int)u.x, 32, 64);
-  u.y = (uint32_t)__shfl_xor((int)u.y, 32, 64);
-  u.z = (uint32_t)__shfl_xor((int)u.z, 32, 64);
-  u.w = (uint32_t)__shfl_xor((int)u.w, 32, 64);
-  const bf16x8 recv = __builtin_bit_cast(bf16x8, u);
-  t0 = h == 0 ? mine : recv;
-  t1 = h == 1 ? mine : recv;
+// Column-tile operands from a lane's two k-halves.  On entry lane (n, h)
+// holds k-half 0 of sample n of ray h in t0 and k-half 1 in t1; on return t0
+// is column tile 0's operand (lane (n, h): k-half h of ray 0's sample n) and
+// t1 column tile 1's.  v_permlane32_swap exchanges the upper 32 lanes of its
+// first operand with the lower 32 lanes of its second, which is exactly the
+// move of ray 0's k-half 1 up and ray 1's k-half 0 down.
+__device__ __forceinline__ uint32_t swap_lo(uint32_t& a, const uint32_t b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = r[0];
+  return r[1];
+}
+
+__device__ __forceinline__ void tile_pair(bf16x8& t0, bf16x8& t1) {
+  uint4 u = __builtin_bit_cast(uint4, t0), v = __builtin_bit_cast(uint4, t1);
+  v.x = swap_lo(u.x, v.x);
+  v.y = swap_lo(u.y, v.y);
+  v.z = swap_lo(u.z, v.z);
+  v.w = swap_lo(u.w, v.w);
+  t0 = __builtin_bit_cast(bf16x8, u);
+  t1 = __builtin_bit_cast(bf16x8, v);
 }
 
 // Rays go through the wave in pairs: lane (n, h) = lane n + 32 h owns sample
@@ -282,6 +289,11 @@ k_level_rays(const LevelRayArgs a) {
     // holding the draw of ray q's samples 4 g .. 4 g + 3
     bf16x8 gdr[2][LS::KBD];
     posenc_both<LS::LD, LS::KBD>(rs.d[0], rs.d[1], rs.d[2], gdr);
+    // k-half h of it in lane (n, h): column tile nt of pair q0 reads it from
+    // lane q0 + nt + 32 h, which holds ray q0 + nt
+    uint4 gdh[LS::KBD];
+#pragma unroll
+    for (int kb = 0; kb < LS::KBD; ++kb) gdh[kb] = __builtin_bit_cast(uint4, h ? gdr[1][kb] : gdr[0][kb]);
     u32x4 jd = {0u, 0u, 0u, 0u};
     if (a.jitter) {
       static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
@@ -305,26 +317,21 @@ k_level_rays(const LevelRayArgs a) {
       }
       const float tk = a.near_ + ((float)k + xi) * a.dt;
       bf16x8 x0[NTL][LS::KBX], gdt[NTL][LS::KBD];
-      {
-        bf16x8 gx[2][LS::KBX], gd[2][LS::KBD];
-        posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), gx);
+      posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), x0);
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+      for (int kb = 0; kb < LS::KBX; ++kb) tile_pair(x0[0][kb], x0[1][kb]);
 #pragma unroll
-          for (int kb = 0; kb < LS::KBD; ++kb) {
-            uint4 u = __builtin_bit_cast(uint4, gdr[hh][kb]);
-            u.x = (uint32_t)__shfl((int)u.x, q, 64);
-            u.y = (uint32_t)__shfl((int)u.y, q, 64);
-            u.z = (uint32_t)__shfl((int)u.z, q, 64);
-            u.w = (uint32_t)__shfl((int)u.w, q, 64);
-            gd[hh][kb] = __builtin_bit_cast(bf16x8, u);
-          }
+      for (int nt = 0; nt < NTL; ++nt) {
+        const int src = q0 + nt + 32 * h;
 #pragma unroll
-        for (int kb = 0; kb < LS::KBX; ++kb)
-          tile_operands(h ? gx[1][kb] : gx[0][kb], h ? gx[0][kb] : gx[1][kb], h, x0[0][kb], x0[1][kb]);
-#pragma unroll
-        for (int kb = 0; kb < LS::KBD; ++kb)
-          tile_operands(h ? gd[1][kb] : gd[0][kb], h ? gd[0][kb] : gd[1][kb], h, gdt[0][kb], gdt[1][kb]);
+        for (int kb = 0; kb < LS::KBD; ++kb) {
+          uint4 u;
+          u.x = (uint32_t)__shfl((int)gdh[kb].x, src, 64);
+          u.y = (uint32_t)__shfl((int)gdh[kb].y, src, 64);
+          u.z = (uint32_t)__shfl((int)gdh[kb].z, src, 64);
+          u.w = (uint32_t)__shfl((int)gdh[kb].w, src, 64);
+          gdt[nt][kb] = __builtin_bit_cast(bf16x8, u);
+        }
       }
       // the map on both column tiles (layer order and arithmetic of k_mlp_bf16)
       bf16x8 xa[NTL][LS::KBH], xb[NTL][LS::KBH];
@@ -348,8 +355,9 @@ k_level_rays(const LevelRayArgs a) {
       float hv[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float t1 = __shfl(hacc[1][v] + hacc[1][v + 4], n, 64);
-        hv[v] = h ? t1 : hacc[0][v] + hacc[0][v + 4];
+        uint32_t r0 = __float_as_uint(hacc[0][v] + hacc[0][v + 4]);
+        swap_lo(r0, __float_as_uint(hacc[1][v] + hacc[1][v + 4]));
+        hv[v] = __uint_as_float(r0);
       }
       // everything below reads only lanes of the same half before the
       // shuffles of the next pair
