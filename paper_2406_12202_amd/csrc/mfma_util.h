@@ -31,13 +31,42 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
   static_for_impl(fn, std::make_integer_sequence<int, N>{});
 }
 
+// sin(pi x) and cos(pi x) for band 0 of the encoding: x = j / 2 + r with
+// j = rint(2 x) and |r| <= 1/4 (r is exact in float32), sin(pi r) and
+// cos(pi r) by polynomials in r^2 fitted on [0, 1/4] toward the minimax
+// error (odd terms to r^9, even to r^10), then the j quarter turns:
+// sin(pi x) = +-sin(pi r) or +-cos(pi r) by j mod 4.  Largest absolute
+// error 8.4e-8 on |x| <= 12 (float32 arithmetic against exact values);
+// positions are finite and small, so the long-argument reduction of a
+// library sincospi is not needed.
+__device__ __forceinline__ void sincospi_enc(const float x, float& s, float& c) {
+  const float j = __builtin_rintf(x + x);
+  const float r = fmaf(j, -0.5f, x);
+  const float z = r * r;
+  float ps = fmaf(z, 0x1.3e17e8p-4f, -0x1.32535cp-1f);
+  ps = fmaf(z, ps, 0x1.4668f2p+1f);
+  ps = fmaf(z, ps, -0x1.4abbc4p+2f);
+  ps = fmaf(z, ps, 0x1.921fb6p+1f);
+  const float sr = r * ps;
+  float pc = fmaf(z, -0x1.901bd6p-6f, 0x1.e12f86p-3f);
+  pc = fmaf(z, pc, -0x1.55d0b8p+0f);
+  pc = fmaf(z, pc, 0x1.03c1e6p+2f);
+  pc = fmaf(z, pc, -0x1.3bd3ccp+2f);
+  const float cr = fmaf(z, pc, 1.0f);
+  const int q = (int)j;
+  const float a = (q & 1) ? cr : sr;
+  const float b = (q & 1) ? sr : cr;
+  s = __int_as_float(__float_as_int(a) ^ ((q & 2) << 30));
+  c = __int_as_float(__float_as_int(b) ^ (((q + 1) & 2) << 30));
+}
+
 // bf16 operands of the encoding gamma(p) (pseudo-pair layout of
-// maplayout_bf16.h).  sin and cos of band 0 come from sincospif; band b + 1
-// follows from band b by the double-angle identities sin 2a = 2 sin a cos a,
-// cos 2a = (cos a - sin a)(cos a + sin a).  Each doubling at most doubles the
-// absolute error, so band L - 1 is within 2^(L-1) float32 roundings
-// (6e-5 for L = 10) of the exact value, far inside the bf16 rounding of the
-// operands (2^-9 relative).
+// maplayout_bf16.h).  sin and cos of band 0 come from sincospi_enc; band
+// b + 1 follows from band b by the double-angle identities
+// sin 2a = 2 sin a cos a, cos 2a = (cos a - sin a)(cos a + sin a).  Each
+// doubling at most doubles the absolute error, so band L - 1 is within
+// 2^(L-1) float32 roundings (1e-4 for L = 10) of the exact value, far inside
+// the bf16 rounding of the operands (2^-9 relative).
 // values of both lane halves: out[hh][kb] is the operand of half hh
 template <int L, int KB>
 __device__ __forceinline__ void posenc_both(const float p0, const float p1, const float p2, bf16x8 (&out)[2][KB]) {
@@ -45,7 +74,7 @@ __device__ __forceinline__ void posenc_both(const float p0, const float p1, cons
   const float pc[3] = {p0, p1, p2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    sincospif(pc[c], &sn[c][0], &cs[c][0]);
+    sincospi_enc(pc[c], sn[c][0], cs[c][0]);
 #pragma unroll
     for (int l = 1; l < L; ++l) {
       const float sa = sn[c][l - 1], ca = cs[c][l - 1];
