@@ -190,7 +190,7 @@ __device__ __forceinline__ int half_min_int(int v, int h) {
 template <int WAVES>
 struct LevelCfg {
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4;
+  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + WAVES * 1024;
 };
 
 // the head tile with the direction operands in registers (head_tile's
@@ -219,6 +219,15 @@ __device__ __forceinline__ void head_tile_r(const uint4* w, const float* bl, con
 #pragma unroll
     for (int nt = 0; nt < NTL; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, gd[nt][kb], acc[nt], 0, 0, 0);
   }
+}
+
+// orders one wave's LDS writes before its later reads of other lanes' words
+// (a wave's LDS operations complete in issue order; this keeps the compiler
+// from moving them across)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Column-tile operands from a lane's two k-halves.  On entry lane (n, h)
@@ -257,6 +266,7 @@ k_level_rays(const LevelRayArgs a) {
   constexpr int NTL = 2;
   __shared__ uint4 s_w[LS::BLOCKS * 64];
   __shared__ float4 s_bias[LS::BIASES / 4];
+  __shared__ uint32_t s_jit[WAVES][4 * 64];   // per wave: the batch's jitter draws, [lane][word]
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 31, h = lane >> 5;
   {
@@ -286,7 +296,8 @@ k_level_rays(const LevelRayArgs a) {
     }
     // once per batch: the direction encoding of lane q's ray (lanes q mod
     // kRayBatch hold it), and the jitter draws of all its rays, lane 8 q + g
-    // holding the draw of ray q's samples 4 g .. 4 g + 3
+    // drawing ray q's samples 4 g .. 4 g + 3 (word 32 q + k of the wave's LDS
+    // row is then sample k of ray q)
     bf16x8 gdr[2][LS::KBD];
     posenc_both<LS::LD, LS::KBD>(rs.d[0], rs.d[1], rs.d[2], gdr);
     // k-half h of it in lane (n, h): column tile nt of pair q0 reads it from
@@ -294,11 +305,16 @@ k_level_rays(const LevelRayArgs a) {
     uint4 gdh[LS::KBD];
 #pragma unroll
     for (int kb = 0; kb < LS::KBD; ++kb) gdh[kb] = __builtin_bit_cast(uint4, h ? gdr[1][kb] : gdr[0][kb]);
-    u32x4 jd = {0u, 0u, 0u, 0u};
     if (a.jitter) {
       static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
       const int qd = lane >> 3;
-      jd = draw(seed, iter, kStreamJitCoarse, __shfl(rs.i, qd, 64), __shfl(rs.j, qd, 64), lane & 7);
+      const u32x4 jd = draw(seed, iter, kStreamJitCoarse, __shfl(rs.i, qd, 64), __shfl(rs.j, qd, 64), lane & 7);
+      wave_lds_sync();   // the previous batch's reads are done
+      s_jit[wv][4 * lane] = jd.x;
+      s_jit[wv][4 * lane + 1] = jd.y;
+      s_jit[wv][4 * lane + 2] = jd.z;
+      s_jit[wv][4 * lane + 3] = jd.w;
+      wave_lds_sync();
     }
     for (int q0 = 0; q0 < kRayBatch; q0 += 2) {
       // this lane's ray (q0 + h) and sample n
@@ -309,12 +325,7 @@ k_level_rays(const LevelRayArgs a) {
       const float ob0 = __shfl(rs.obs[0], q, 64), ob1 = __shfl(rs.obs[1], q, 64), ob2 = __shfl(rs.obs[2], q, 64);
       const int k = n;
       float xi = 0.0f;
-      if (a.jitter) {
-        const int src = 8 * q + (k >> 2);
-        const u32x4 dq = {(uint32_t)__shfl((int)jd.x, src, 64), (uint32_t)__shfl((int)jd.y, src, 64),
-                          (uint32_t)__shfl((int)jd.z, src, 64), (uint32_t)__shfl((int)jd.w, src, 64)};
-        xi = unit24(pick(dq, k & 3));
-      }
+      if (a.jitter) xi = unit24(s_jit[wv][32 * q0 + lane]);   // sample k of ray q
       const float tk = a.near_ + ((float)k + xi) * a.dt;
       bf16x8 x0[NTL][LS::KBX], gdt[NTL][LS::KBD];
       posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), x0);
