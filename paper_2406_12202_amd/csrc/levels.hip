@@ -190,7 +190,7 @@ __device__ __forceinline__ int half_min_int(int v, int h) {
 template <int WAVES>
 struct LevelCfg {
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + WAVES * 1024;
+  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + WAVES * (1024 + kRayBatch * 48);
 };
 
 // the head tile with the direction operands in registers (head_tile's
@@ -267,6 +267,7 @@ k_level_rays(const LevelRayArgs a) {
   __shared__ uint4 s_w[LS::BLOCKS * 64];
   __shared__ float4 s_bias[LS::BIASES / 4];
   __shared__ uint32_t s_jit[WAVES][4 * 64];   // per wave: the batch's jitter draws, [lane][word]
+  __shared__ float4 s_ray[WAVES][kRayBatch][3];   // per wave: the batch's rays, {o, obs0}, {d, obs1}, {obs2}
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 31, h = lane >> 5;
   {
@@ -305,24 +306,31 @@ k_level_rays(const LevelRayArgs a) {
     uint4 gdh[LS::KBD];
 #pragma unroll
     for (int kb = 0; kb < LS::KBD; ++kb) gdh[kb] = __builtin_bit_cast(uint4, h ? gdr[1][kb] : gdr[0][kb]);
+    static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
+    u32x4 jd = {0u, 0u, 0u, 0u};
     if (a.jitter) {
-      static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
       const int qd = lane >> 3;
-      const u32x4 jd = draw(seed, iter, kStreamJitCoarse, __shfl(rs.i, qd, 64), __shfl(rs.j, qd, 64), lane & 7);
-      wave_lds_sync();   // the previous batch's reads are done
+      jd = draw(seed, iter, kStreamJitCoarse, __shfl(rs.i, qd, 64), __shfl(rs.j, qd, 64), lane & 7);
+    }
+    wave_lds_sync();   // the previous batch's reads are done
+    if (lane < kRayBatch) {
+      s_ray[wv][lane][0] = make_float4(rs.o[0], rs.o[1], rs.o[2], rs.obs[0]);
+      s_ray[wv][lane][1] = make_float4(rs.d[0], rs.d[1], rs.d[2], rs.obs[1]);
+      s_ray[wv][lane][2] = make_float4(rs.obs[2], 0.0f, 0.0f, 0.0f);
+    }
+    if (a.jitter) {
       s_jit[wv][4 * lane] = jd.x;
       s_jit[wv][4 * lane + 1] = jd.y;
       s_jit[wv][4 * lane + 2] = jd.z;
       s_jit[wv][4 * lane + 3] = jd.w;
-      wave_lds_sync();
     }
+    wave_lds_sync();
     for (int q0 = 0; q0 < kRayBatch; q0 += 2) {
       // this lane's ray (q0 + h) and sample n
       const int q = q0 + h;
       const long ray = bt * kRayBatch + q;
-      const float4 o = make_float4(__shfl(rs.o[0], q, 64), __shfl(rs.o[1], q, 64), __shfl(rs.o[2], q, 64), 0.0f);
-      const float4 d = make_float4(__shfl(rs.d[0], q, 64), __shfl(rs.d[1], q, 64), __shfl(rs.d[2], q, 64), 0.0f);
-      const float ob0 = __shfl(rs.obs[0], q, 64), ob1 = __shfl(rs.obs[1], q, 64), ob2 = __shfl(rs.obs[2], q, 64);
+      const float4 o = s_ray[wv][q][0], d = s_ray[wv][q][1];
+      const float ob0 = o.w, ob1 = d.w, ob2 = s_ray[wv][q][2].x;
       const int k = n;
       float xi = 0.0f;
       if (a.jitter) xi = unit24(s_jit[wv][32 * q0 + lane]);   // sample k of ray q
