@@ -190,7 +190,7 @@ __device__ __forceinline__ int half_min_int(int v, int h) {
 template <int WAVES>
 struct LevelCfg {
   static constexpr int THREADS = 64 * WAVES;
-  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + WAVES * (1024 + kRayBatch * 48);
+  static constexpr long LDS = LS::BLOCKS * 1024 + LS::BIASES * 4 + WAVES * (1024 + kRayBatch * (48 + 32 * LS::KBD));
 };
 
 // the head tile with the direction operands in registers (head_tile's
@@ -268,6 +268,7 @@ k_level_rays(const LevelRayArgs a) {
   __shared__ float4 s_bias[LS::BIASES / 4];
   __shared__ uint32_t s_jit[WAVES][4 * 64];   // per wave: the batch's jitter draws, [lane][word]
   __shared__ float4 s_ray[WAVES][kRayBatch][3];   // per wave: the batch's rays, {o, obs0}, {d, obs1}, {obs2}
+  __shared__ uint4 s_gdir[WAVES][kRayBatch][2 * LS::KBD];   // per wave: their direction operands [ray][half][k-block]
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 31, h = lane >> 5;
   {
@@ -295,17 +296,13 @@ k_level_rays(const LevelRayArgs a) {
         default: ray_setup<8>(a, seed, iter, r, rs); break;
       }
     }
-    // once per batch: the direction encoding of lane q's ray (lanes q mod
-    // kRayBatch hold it), and the jitter draws of all its rays, lane 8 q + g
-    // drawing ray q's samples 4 g .. 4 g + 3 (word 32 q + k of the wave's LDS
-    // row is then sample k of ray q)
+    // once per batch, into the wave's LDS rows: lane q's ray (origin,
+    // direction, observation) and the bf16 operands of its direction
+    // encoding for q < kRayBatch, and the jitter draws of all its rays, lane
+    // 8 q + g drawing ray q's samples 4 g .. 4 g + 3 (word 32 q + k of the
+    // jitter row is then sample k of ray q)
     bf16x8 gdr[2][LS::KBD];
     posenc_both<LS::LD, LS::KBD>(rs.d[0], rs.d[1], rs.d[2], gdr);
-    // k-half h of it in lane (n, h): column tile nt of pair q0 reads it from
-    // lane q0 + nt + 32 h, which holds ray q0 + nt
-    uint4 gdh[LS::KBD];
-#pragma unroll
-    for (int kb = 0; kb < LS::KBD; ++kb) gdh[kb] = __builtin_bit_cast(uint4, h ? gdr[1][kb] : gdr[0][kb]);
     static_assert(kRayBatch * kLevelSpr / 4 == 64, "one draw per lane covers a batch");
     u32x4 jd = {0u, 0u, 0u, 0u};
     if (a.jitter) {
@@ -317,6 +314,10 @@ k_level_rays(const LevelRayArgs a) {
       s_ray[wv][lane][0] = make_float4(rs.o[0], rs.o[1], rs.o[2], rs.obs[0]);
       s_ray[wv][lane][1] = make_float4(rs.d[0], rs.d[1], rs.d[2], rs.obs[1]);
       s_ray[wv][lane][2] = make_float4(rs.obs[2], 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int kb = 0; kb < LS::KBD; ++kb) s_gdir[wv][lane][hh * LS::KBD + kb] = __builtin_bit_cast(uint4, gdr[hh][kb]);
     }
     if (a.jitter) {
       s_jit[wv][4 * lane] = jd.x;
@@ -339,19 +340,12 @@ k_level_rays(const LevelRayArgs a) {
       posenc_both<LS::LX, LS::KBX>(fmaf(tk, d.x, o.x), fmaf(tk, d.y, o.y), fmaf(tk, d.z, o.z), x0);
 #pragma unroll
       for (int kb = 0; kb < LS::KBX; ++kb) tile_pair(x0[0][kb], x0[1][kb]);
+      // column tile nt: k-half h of ray q0 + nt's direction operands
 #pragma unroll
-      for (int nt = 0; nt < NTL; ++nt) {
-        const int src = q0 + nt + 32 * h;
+      for (int nt = 0; nt < NTL; ++nt)
 #pragma unroll
-        for (int kb = 0; kb < LS::KBD; ++kb) {
-          uint4 u;
-          u.x = (uint32_t)__shfl((int)gdh[kb].x, src, 64);
-          u.y = (uint32_t)__shfl((int)gdh[kb].y, src, 64);
-          u.z = (uint32_t)__shfl((int)gdh[kb].z, src, 64);
-          u.w = (uint32_t)__shfl((int)gdh[kb].w, src, 64);
-          gdt[nt][kb] = __builtin_bit_cast(bf16x8, u);
-        }
-      }
+        for (int kb = 0; kb < LS::KBD; ++kb)
+          gdt[nt][kb] = __builtin_bit_cast(bf16x8, s_gdir[wv][q0 + nt][h * LS::KBD + kb]);
       // the map on both column tiles (layer order and arithmetic of k_mlp_bf16)
       bf16x8 xa[NTL][LS::KBH], xb[NTL][LS::KBH];
       dense_res<NTL, LS::MT, LS::KBX, LS::KBX, false, LS::KBH>(s_w + LS::block_base(0) * 64,
