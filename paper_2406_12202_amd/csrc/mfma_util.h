@@ -233,8 +233,28 @@ __device__ __forceinline__ float dot_b(const float* __restrict__ w, const bf16x8
   return s;
 }
 
-__device__ __forceinline__ float softplus_b(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float sigmoid_b(float z) { return 1.0f / (1.0f + expf(-z)); }
+// Density and colour nonlinearities of the bf16 heads, on the hardware
+// base-2 exponential and reciprocal (each within a few float32 ulps; the
+// heads' inputs are sums of bf16 products, rounded to 2^-9 relative).
+// softplus(z) = max(z, 0) + log1p(u), u = e^-|z| in (0, 1], with
+// log1p(u) = 2 atanh(s), s = u / (2 + u) <= 1/3, summed as the odd series
+// 2 s (1 + s^2/3 + ... + s^12/13) (next term below 2e-8 of the sum).
+__device__ __forceinline__ float exp_b(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+__device__ __forceinline__ float softplus_b(float z) {
+  const float u = exp_b(-fabsf(z));
+  const float s = u * __builtin_amdgcn_rcpf(2.0f + u);
+  const float s2 = s * s;
+  float p = fmaf(s2, 1.0f / 13.0f, 1.0f / 11.0f);
+  p = fmaf(s2, p, 1.0f / 9.0f);
+  p = fmaf(s2, p, 1.0f / 7.0f);
+  p = fmaf(s2, p, 1.0f / 5.0f);
+  p = fmaf(s2, p, 1.0f / 3.0f);
+  p = fmaf(s2, p, 1.0f);
+  return fmaxf(z, 0.0f) + 2.0f * s * p;
+}
+
+__device__ __forceinline__ float sigmoid_b(float z) { return __builtin_amdgcn_rcpf(1.0f + exp_b(-z)); }
 
 // both heads of a map without direction layer as one MFMA tile: acc rows 0
 // (density) and 1..3 (colour) in lanes of half 0, from the head chunk w
