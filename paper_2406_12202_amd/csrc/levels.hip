@@ -22,6 +22,7 @@
 // pose, resamples to the next level's particle count, gathers the drawn
 // poses and applies the next level's prediction.
 #include "filter_dev.h"
+#include "compositing.h"
 #include "maplayout_bf16.h"
 #include "mfma_util.h"
 
@@ -387,7 +388,7 @@ k_level_rays(const LevelRayArgs a) {
       float cr = 0.0f, cg = 0.0f, cb = 0.0f, accw = 0.0f;
       int ktr = 1 << 30, kop = 1 << 30;
       const float tau = sg * (tn - tk);
-      const float w = expf(run) * -expm1f(-tau);
+      const float w = transmittance(run) * opacity(tau);
       const float lt = run;
       cr = fmaf(w, cr0, cr); cg = fmaf(w, cg0, cg); cb = fmaf(w, cb0, cb);
       accw += w;
@@ -402,8 +403,8 @@ k_level_rays(const LevelRayArgs a) {
         const float t_tr = __shfl(tk, ktr, 32), l_tr = __shfl(lt, ktr, 32), s_tr = __shfl(sg, ktr, 32);
         const int ko = kop < kLevelSpr ? kop : 0;
         const float t_op = __shfl(tk, ko, 32), l_op = __shfl(lt, ko, 32), s_op = __shfl(sg, ko, 32);
-        const float zt = t_tr + (l_tr - a.log_trans) / s_tr;
-        const float zo = (kop < kLevelSpr) ? t_op + (l_op - a.log_opq) / s_op : a.far_;
+        const float zt = crossing_depth(t_tr, l_tr, a.log_trans, s_tr);
+        const float zo = (kop < kLevelSpr) ? crossing_depth(t_op, l_op, a.log_opq, s_op) : a.far_;
         F = fmaxf(zo - zt, a.tau);
       }
       const float er = ob0 - cr, eg = ob1 - cg, eb = ob2 - cb;

@@ -1,6 +1,7 @@
 // Ray generation, hierarchical fine-sample placement and the per-ray
 // compositing scan with the uncertainty F and the per-particle score.
 #include "common.h"
+#include "compositing.h"
 #include "kernels.h"
 
 namespace fl {
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(64 * kCompWaves) void k_composite(const CompositeAr
     if (k < S) {
       const float tn = (k + 1 < S) ? s_tm[k + 1] : a.far_;
       const float tau = s_sg[k] * (tn - s_tm[k]);
-      const float w = expf(run) * -expm1f(-tau);
+      const float w = transmittance(run) * opacity(tau);
       s_lt[k] = run;
       const float4 c = s_rgb[k];
       cr = fmaf(w, c.x, cr); cg = fmaf(w, c.y, cg); cb = fmaf(w, c.z, cb);
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(64 * kCompWaves) void k_composite(const CompositeAr
   if (lane == 0) {
     float F = a.empty_F;
     if (ktr < S) {
-      const float zt = s_tm[ktr] + (s_lt[ktr] - a.log_trans) / s_sg[ktr];
-      const float zo = (kop < S) ? s_tm[kop] + (s_lt[kop] - a.log_opq) / s_sg[kop] : a.far_;
+      const float zt = crossing_depth(s_tm[ktr], s_lt[ktr], a.log_trans, s_sg[ktr]);
+      const float zo = (kop < S) ? crossing_depth(s_tm[kop], s_lt[kop], a.log_opq, s_sg[kop]) : a.far_;
       F = fmaxf(zo - zt, a.tau);
     }
     float E = 0.0f;
