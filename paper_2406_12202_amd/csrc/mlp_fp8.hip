@@ -191,8 +191,6 @@ __device__ __forceinline__ void dense_f8(const __amdgpu_buffer_rsrc_t wr, const 
   });
 }
 
-__device__ __forceinline__ float softplus_f(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float sigmoid_f(float z) { return 1.0f / (1.0f + expf(-z)); }
 
 template <class S, int NTL, int WAVES, int MPC>
 __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
@@ -254,17 +252,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_mlp_fp8(const MlpArgs a) {
   dense_f8<S, NTL, WAVES, MPC, S::MTD, S::KBD, kEpiRgb, false, true, DP>(
       wr, bias, heads + S::RGB_OFF, S::D + 1, slot0, slot1, xa, s_gd[wv], xb, rp, a.f8_sw[S::D + 1],
       a.f8_sx[S::D + 1], wv, lane);
+  // the heads' nonlinearities on the hardware exp2 and reciprocal (a few float32
+  // ulps, far below the E4M3 roundings of the activations)
 #pragma unroll
   for (int nt = 0; nt < NTL; ++nt) {
     float zs = sp[nt][0];
     zs += __shfl_xor(zs, 32, 64);
-    const float sigma = softplus_f(zs + heads[S::SIG_OFF + S::W]);
+    const float sigma = softplus_b(zs + heads[S::SIG_OFF + S::W]);
     float rgb[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float z = rp[nt][c];
       z += __shfl_xor(z, 32, 64);
-      rgb[c] = sigmoid_f(z + heads[S::RGB_OFF + 3 * S::DW + c]);
+      rgb[c] = sigmoid_b(z + heads[S::RGB_OFF + 3 * S::DW + c]);
     }
     if (valid[nt] && h == 0) (seg2[nt] ? a.out2 : a.out)[sidx[nt]] = make_float4(sigma, rgb[0], rgb[1], rgb[2]);
   }
