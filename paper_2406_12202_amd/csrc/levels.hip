@@ -6,7 +6,7 @@
 // and draws the motion increments of the later levels.
 //
 // k_level_rays keeps the whole packed map (30 KB of bf16 chunks, biases,
-// heads) resident in LDS and walks the level's rays with a grid-stride loop
+// heads) resident in LDS, beside 1.6 KB of staging rows per wave, and walks the level's rays with a grid-stride loop
 // over waves: for each ray (one 32-sample column tile) it generates the pixel
 // ray of the particle's predicted pose, the box-averaged observation, the
 // stratified samples and their encodings, evaluates the map, composites along
@@ -257,9 +257,11 @@ __device__ __forceinline__ void tile_pair(bf16x8& t0, bf16x8& t1) {
 // n of ray h of the pair for everything outside the MFMAs (jitter, depth,
 // encoding, head nonlinearities, compositing), so no lane repeats another's
 // work; a lane computes both k-halves of its sample's encoding operands and
-// exchanges one half with lane xor 32 to hold the MFMA operands of both
-// column tiles, the map runs on the two tiles, and the head rows of tile 1
-// are moved from half 0 to half 1 by one shuffle per row.
+// exchanges one half with lane xor 32 (v_permlane32_swap) to hold the MFMA
+// operands of both column tiles, the map runs on the two tiles, and the head
+// rows of tile 1 move from half 0 to half 1 by the same swap.  A batch's ray
+// data (origin, direction, observation, direction-encoding operands, jitter
+// draws) is staged once in the wave's LDS rows and read back per pair.
 template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(FL_LEVEL_WAVES_PER_EU))) void
 k_level_rays(const LevelRayArgs a) {
