@@ -6,8 +6,9 @@
 // and draws the motion increments of the later levels.
 //
 // k_level_rays keeps the whole packed map (30 KB of bf16 chunks, biases,
-// heads) resident in LDS, beside 1.6 KB of staging rows per wave, and walks the level's rays with a grid-stride loop
-// over waves: for each ray (one 32-sample column tile) it generates the pixel
+// heads) resident in LDS, beside 1.6 KB of staging rows per wave, and
+// walks the level's rays with a grid-stride loop over waves: for each ray
+// (one 32-sample column tile) it generates the pixel
 // ray of the particle's predicted pose, the box-averaged observation, the
 // stratified samples and their encodings, evaluates the map, composites along
 // the ray with a wave scan of log transmittance, finds Eq. 5's depths, and
